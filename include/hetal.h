@@ -1,0 +1,231 @@
+/*
+ * hetal.h -- C ABI of the MI355X (gfx950) library for encrypted matrix
+ * products over RNS-CKKS ciphertexts: the DiagABT and DiagATB algorithms of
+ * "HETAL: Efficient Privacy-preserving Transfer Learning with Homomorphic
+ * Encryption" (ICML 2023), Sec. 4.2 and App. B (Alg. 1-4), and the CKKS
+ * operations they are built from (Sec. 2.2).
+ *
+ * Conventions
+ *  - Every call returns an int status: HETAL_OK (0) or a negative HETAL_E_*
+ *    code; hetal_last_error() gives the message of the calling thread's last
+ *    failure.  On failure no output is valid.
+ *  - Ciphertexts and plaintexts live in device memory that the CALLER owns
+ *    (for instance a torch tensor); the structs below carry the pointer, its
+ *    capacity in 64-bit words, the level and the FP64 scale.  The library
+ *    never frees caller memory.  Outputs must have room for the result
+ *    (capacity checked; E_INVALID_ARG otherwise) and get level and scale
+ *    written.  An output may alias an input.
+ *  - Device layout: a polynomial at level l is uint64 [l+1][N], limb-major,
+ *    row i holding the residues modulo q_i in [0, q_i), in the NTT domain in
+ *    the library's internal (bit-reversed) evaluation order.  A ciphertext is
+ *    uint64 [2][l+1][N].  hetal_ct_to_coeff gives the canonical coefficient
+ *    form, the only form meant for comparison with other implementations.
+ *  - Host arrays are plain C arrays, row-major, as described per call.
+ *  - All device work is queued on the context's HIP stream (set at creation
+ *    or by hetal_ctx_set_stream).  Calls that return host data synchronise
+ *    that stream first.  A context is not thread-safe.
+ *  - Randomness is an input: the secret key's coefficients, every key
+ *    switching key's uniform mask and error, and every encryption's mask and
+ *    error are supplied by the caller, so results are deterministic.
+ */
+#ifndef HETAL_H
+#define HETAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HETAL_OK = 0,
+  HETAL_E_INVALID_ARG = -1, /* null pointer, bad size, capacity too small */
+  HETAL_E_SHAPE = -2,       /* matrix shape / tiling precondition violated */
+  HETAL_E_LEVEL = -3,       /* not enough levels left (depth exhausted) */
+  HETAL_E_NO_KEY = -4,      /* a needed relinearisation or Galois key is missing */
+  HETAL_E_SCALE = -5,       /* operands with incompatible scales */
+  HETAL_E_OOM = -6,         /* device allocation failed */
+  HETAL_E_DEVICE = -7,      /* HIP runtime error */
+  HETAL_E_PARAMS = -8,      /* unsupported parameter set */
+  HETAL_E_OVERFLOW = -9     /* an encoded coefficient does not fit in 62 bits */
+};
+
+typedef struct hetal_ctx hetal_ctx;
+typedef struct hetal_sk hetal_sk;
+typedef struct hetal_keys hetal_keys;
+
+/* Parameter set.  N = 2^log_n (12 <= log_n <= 16); q_0 is the largest prime
+ * below 2^q0_bits, q_1..q_{num_q-1} the largest primes below 2^q_bits in
+ * descending order, and the num_p special primes p_0.. the largest primes
+ * below q_0; all are 1 mod 2N (q0_bits, q_bits <= 50).  dnum digits of
+ * alpha = ceil(num_q / dnum) consecutive primes are used for hybrid key
+ * switching.  Limits: num_q + num_p <= 32, alpha <= 8, num_p <= 8. */
+typedef struct {
+  int log_n;
+  int num_q;
+  int num_p;
+  int dnum;
+  int q0_bits;
+  int q_bits;
+} hetal_params;
+
+typedef struct {
+  uint64_t* data;  /* device, [2][level+1][N] */
+  size_t capacity; /* 64-bit words available at data */
+  int level;
+  double scale;
+} hetal_ct;
+
+typedef struct {
+  uint64_t* data;  /* device, [level+1][N] */
+  size_t capacity;
+  int level;
+  double scale;
+} hetal_pt;
+
+/* An encrypted block matrix (App. B.1): the matrix is zero padded to
+ * multiples of s0 x s1 (s0 * s1 = N/2) and cut into n_rb x n_cb blocks, block
+ * (i, j) written row-major into the slots of ciphertext i * n_cb + j.
+ * data: device, [n_rb * n_cb][2][level+1][N]. */
+typedef struct {
+  uint64_t* data;
+  size_t capacity;
+  int n_rb;
+  int n_cb;
+  int s0;
+  int s1;
+  int level;
+  double scale;
+} hetal_mat;
+
+const char* hetal_last_error(void);
+
+/* Context: parameters, precomputed tables (roots of unity, basis-conversion
+ * constants, double-double FFT roots) and a device memory pool for
+ * temporaries.  `stream` is a hipStream_t (NULL = default stream).
+ * E_PARAMS if the parameter set is outside the limits above. */
+int hetal_ctx_create(const hetal_params* params, void* stream, hetal_ctx** out);
+void hetal_ctx_destroy(hetal_ctx* ctx);
+int hetal_ctx_set_stream(hetal_ctx* ctx, void* stream);
+/* n: ring degree; slots: N/2; max_level: num_q - 1; num_primes: num_q + num_p. */
+int hetal_ctx_info(const hetal_ctx* ctx, int* n, int* slots, int* max_level, int* num_primes);
+/* Writes q_0..q_{num_q-1}, p_0..p_{num_p-1} to out (host, num_q + num_p words). */
+int hetal_ctx_primes(const hetal_ctx* ctx, uint64_t* out);
+int hetal_synchronize(hetal_ctx* ctx);
+/* Galois elements: left rotation by r slots is X -> X^(5^r mod 2N) (r < 0:
+ * right rotation); conjugation is X -> X^(2N-1) (Sec. 2.2: Lrot, conj). */
+uint64_t hetal_galois_rot(const hetal_ctx* ctx, int r);
+uint64_t hetal_galois_conj(const hetal_ctx* ctx);
+
+/* Secret key from its N signed coefficients (host int64, each in {-1,0,1}).
+ * The key is stored on the device in NTT form over every prime. */
+int hetal_sk_create(hetal_ctx* ctx, const int64_t* s_coeffs, hetal_sk** out);
+void hetal_sk_destroy(hetal_sk* sk);
+
+/* Evaluation keys (public operation keys, Sec. 3.1), held in library-owned
+ * device memory: 2 * dnum * (num_q + num_p) * N words per key.
+ * Key for s' (s^2 for relinearisation, tau_g(s) for Galois element g):
+ *   ksk_j = (-a_j s + e_j + g_j s', a_j), j < dnum, over all primes, where
+ *   g_j = P mod q_i for q_i in digit j and 0 otherwise (0 modulo each p_k).
+ * a: host uint64 [dnum][num_q + num_p][N], uniform modulo each prime,
+ *    coefficient form; e: host int64 [dnum][N], small signed errors. */
+int hetal_keys_create(hetal_ctx* ctx, hetal_keys** out);
+void hetal_keys_destroy(hetal_keys* keys);
+int hetal_keys_gen_relin(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, const uint64_t* a, const int64_t* e);
+int hetal_keys_gen_galois(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, uint64_t galois, const uint64_t* a,
+                          const int64_t* e);
+
+/* Encoding (Sec. 2.2, CKKS): slot k of the message is the value of the
+ * plaintext polynomial at zeta^(5^k), zeta = exp(i pi / N).  The
+ * coefficients round(scale * sigma^-1(z)) are computed in double-double
+ * arithmetic and rounded half to even, values within 2^-24 of a half-integer
+ * counting as halves.  re, im: host double [N/2] (im may be NULL).
+ * E_OVERFLOW if a coefficient reaches 2^62.  out->capacity >= (level+1)*N. */
+int hetal_encode(hetal_ctx* ctx, const double* re, const double* im, int level, double scale, hetal_pt* out);
+/* Slots of a plaintext (centred CRT of its first two limbs, divided by its
+ * scale).  re, im: host double [N/2] (im may be NULL).  Synchronises. */
+int hetal_decode(hetal_ctx* ctx, const hetal_pt* pt, double* re, double* im);
+
+/* Secret-key encryption (c0, c1) = (-a s + m + e, a) at the plaintext's
+ * level.  a: host uint64 [level+1][N] uniform modulo q_i, coefficient form;
+ * e: host int64 [N]. */
+int hetal_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, const uint64_t* a, const int64_t* e,
+                  hetal_ct* out);
+/* m = c0 + c1 s. */
+int hetal_decrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, hetal_pt* out);
+
+/* Homomorphic operations (Sec. 2.2).  Operands of add/sub/hmult must share
+ * level (E_LEVEL) and scale up to a relative 1e-9 (E_SCALE). */
+int hetal_add(hetal_ctx* ctx, const hetal_ct* a, const hetal_ct* b, hetal_ct* out);
+int hetal_sub(hetal_ctx* ctx, const hetal_ct* a, const hetal_ct* b, hetal_ct* out);
+/* Multiplication by i in every slot (by X^(N/2)): exact, no level used. */
+int hetal_mul_i(hetal_ctx* ctx, const hetal_ct* a, hetal_ct* out);
+/* CMult: (c0 m, c1 m); the scale multiplies.  pt->level must equal ct->level. */
+int hetal_cmult(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, hetal_ct* out);
+/* Mult: tensor product, then relinearisation of the s^2 term (no rescale). */
+int hetal_hmult(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* a, const hetal_ct* b, hetal_ct* out);
+/* Lrot(ct, r): slot j receives slot j + r (r < 0 rotates right).  Hybrid key
+ * switching: ModUp of c1 per digit, the automorphism applied to the extended
+ * digits, inner product with the key, ModDown with a centred basis
+ * conversion; plus tau_g(c0).  E_NO_KEY without the Galois key. */
+int hetal_hrot(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, int r, hetal_ct* out);
+/* Slot-wise complex conjugation (Galois element 2N-1). */
+int hetal_conj(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, hetal_ct* out);
+/* Rescale: c_i <- (c_i - [c_l]_centred) q_l^-1 mod q_i, level - 1, scale / q_l.
+ * E_LEVEL at level 0. */
+int hetal_rescale(hetal_ctx* ctx, const hetal_ct* ct, hetal_ct* out);
+/* Drop the limbs above `level`; the scale is unchanged. */
+int hetal_mod_drop(hetal_ctx* ctx, const hetal_ct* ct, int level, hetal_ct* out);
+
+/* Canonical coefficient form (host uint64 [2][level+1][N] resp. [level+1][N]);
+ * synchronises.  from_coeff is the inverse. */
+int hetal_ct_to_coeff(hetal_ctx* ctx, const hetal_ct* ct, uint64_t* host);
+int hetal_pt_to_coeff(hetal_ctx* ctx, const hetal_pt* pt, uint64_t* host);
+int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double scale, hetal_ct* out);
+
+/* Block-encode and encrypt a host matrix (double, row-major rows x cols).
+ * tiling: 0 none; 1 vertical (the c x cols matrix repeated s0 / c times
+ * down, the B-bar of Alg. 1); 2 horizontal (the rows x c matrix repeated
+ * s1 / c times across, the A-underbar of Alg. 4).  The caller sets
+ * out->s0 (s1 = N/2 / s0), out->level and out->scale; the library sets n_rb,
+ * n_cb.  a: host uint64 [n_rb*n_cb][level+1][N]; e: host int64 [n_rb*n_cb][N].
+ * E_SHAPE if c does not divide the tiled dimension. */
+int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int c,
+                      const uint64_t* a, const int64_t* e, hetal_mat* out);
+/* Decrypt and decode every block: host double [n_rb*s0][n_cb*s1] (real
+ * parts; padding included).  Synchronises. */
+int hetal_mat_decrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_mat* m, double* host);
+
+/* DiagABT (Alg. 1, Prop. 1): <t A Bbar^T> from <A> (n_rb x n_cb blocks) and
+ * <Bbar> (1 x n_cb blocks, B tiled vertically).  c: rows of B padded to a
+ * power of two, 1 < c <= s0, c | s1.  out: n_rb x 1 blocks at level
+ * min(level A, level Bbar) - 3; block i slot (r, j) holds
+ * t (A B^T)[i s0 + r][j mod c].  Needs the relinearisation key, the
+ * conjugation key and Galois keys for the steps hetal_required_rot_steps
+ * lists.  CS uses 2 log s1 rotations and one CMult, RS log s0 rotations. */
+int hetal_enc_matmul_abt(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* a, const hetal_mat* bbar, int c,
+                         double t, hetal_mat* out);
+/* DiagATB (Alg. 4, Prop. 2): <t Abar^T B> from <Abar> (n_rb x 1 blocks, A
+ * tiled horizontally) and <B> (n_rb x n_cb blocks).  out: 1 x n_cb blocks;
+ * block j slot (r, col) holds t (A^T B)[r mod c][j s1 + col].  When
+ * level(Abar) < level(B) the PRotUp branch runs (output level
+ * min(lA - 1, lB - 1) - 2), else the RotLeft branch (min(lA - 2, lB) - 2). */
+int hetal_enc_matmul_atb(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* abar, const hetal_mat* b, int c,
+                         double t, hetal_mat* out);
+/* Rotation steps (signed, left positive) the algorithms need, for key
+ * generation: op 0 = DiagABT, 1 = DiagATB (RotLeft branch), 2 = DiagATB
+ * (PRotUp branch).  *n: in, capacity of out; out, count written. */
+int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int c, int s0, int32_t* out, int* n);
+
+/* Operation counters since the last reset: [0] rotations, [1] conjugations,
+ * [2] Mult, [3] CMult, [4] rescales, [5] key switches, [6] NTT limb
+ * transforms, [7] kernel launches. */
+int hetal_counters_get(const hetal_ctx* ctx, int64_t* out8);
+int hetal_counters_reset(hetal_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HETAL_H */

@@ -1,0 +1,640 @@
+// extern "C" entry points: argument validation, error translation, and the
+// host <-> device transfers of the client-side calls.
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hetal.h"
+#include "matrix.hpp"
+
+using namespace hetal;
+
+struct hetal_ctx {
+  Context c;
+  MaskCache masks;
+};
+
+struct hetal_sk {
+  hetal_ctx* ctx;
+  SecretKeyDev key;
+};
+
+struct hetal_keys {
+  hetal_ctx* ctx;
+  KeySet set;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return HETAL_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return HETAL_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HETAL_E_DEVICE;
+  }
+}
+
+void need(bool ok, int code, const char* msg) {
+  if (!ok) fail(code, msg);
+}
+
+void check_ct(const Context& c, const hetal_ct* ct, const char* what) {
+  need(ct && ct->data, HETAL_E_INVALID_ARG, what);
+  need(ct->level >= 0 && ct->level < c.num_q, HETAL_E_LEVEL, "ciphertext level out of range");
+  need(ct->capacity >= c.ct_words(ct->level), HETAL_E_INVALID_ARG, "ciphertext capacity smaller than its level needs");
+}
+
+void check_out(const Context& c, const hetal_ct* out, int level) {
+  need(out && out->data, HETAL_E_INVALID_ARG, "output ciphertext");
+  need(out->capacity >= c.ct_words(level), HETAL_E_INVALID_ARG, "output capacity too small for the result");
+}
+
+void check_pt(const Context& c, const hetal_pt* pt) {
+  need(pt && pt->data, HETAL_E_INVALID_ARG, "plaintext");
+  need(pt->level >= 0 && pt->level < c.num_q, HETAL_E_LEVEL, "plaintext level out of range");
+  need(pt->capacity >= c.poly_words(pt->level), HETAL_E_INVALID_ARG, "plaintext capacity too small");
+}
+
+CtView view_of(const hetal_ct* ct) { return CtView{ct->data, ct->level, ct->scale}; }
+
+// Host -> device upload into a pool buffer.  The stream is drained first, so a
+// pool buffer that queued kernels still read is never overwritten by a copy
+// from pageable memory, whatever ordering the runtime gives such copies.
+Tmp upload_words(Context& c, const void* host, size_t bytes) {
+  Tmp t(c.pool, (bytes + 7) / 8);
+  HCHECK(hipStreamSynchronize(c.stream));
+  HCHECK(hipMemcpyAsync(t.p, host, bytes, hipMemcpyHostToDevice, c.stream));
+  return t;
+}
+
+// NTT form of caller-supplied coefficient-form randomness a ([count][l][N]) and e ([count][N]).
+void load_randomness(Context& c, const uint64_t* a_host, const int64_t* e_host, int level, int count, Tmp& a, Tmp& e) {
+  const size_t poly = c.poly_words(level);
+  HCHECK(hipStreamSynchronize(c.stream));
+  HCHECK(hipMemcpyAsync(a.p, a_host, (size_t)count * poly * 8, hipMemcpyHostToDevice, c.stream));
+  RowsRef rows = c.rows(ROWS_CT, level);
+  RowsRef first{rows.d, level + 1};
+  ntt_forward(c, a, poly, count, first);
+  Tmp ecoef = upload_words(c, e_host, (size_t)count * c.n * 8);
+  k_reduce_signed(c, reinterpret_cast<const i64*>(ecoef.p), e, first, count, c.n, poly);
+  ntt_forward(c, e, poly, count, first);
+  HCHECK(hipStreamSynchronize(c.stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hetal_last_error(void) { return g_last_error.c_str(); }
+
+int hetal_ctx_create(const hetal_params* params, void* stream, hetal_ctx** out) {
+  return guarded([&] {
+    need(params && out, HETAL_E_INVALID_ARG, "null argument");
+    hetal_ctx* h = new hetal_ctx();
+    try {
+      context_init(h->c, *params, (hipStream_t)stream);
+    } catch (...) {
+      context_free(h->c);
+      delete h;
+      throw;
+    }
+    h->masks.c = &h->c;
+    *out = h;
+  });
+}
+
+void hetal_ctx_destroy(hetal_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->c.stream);
+  for (auto& kv : ctx->masks.pts) ctx->c.pool.put(kv.second);
+  ctx->masks.pts.clear();
+  context_free(ctx->c);
+  delete ctx;
+}
+
+int hetal_ctx_set_stream(hetal_ctx* ctx, void* stream) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    HCHECK(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.stream = (hipStream_t)stream;
+  });
+}
+
+int hetal_ctx_info(const hetal_ctx* ctx, int* n, int* slots, int* max_level, int* num_primes) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    if (n) *n = ctx->c.n;
+    if (slots) *slots = ctx->c.slots;
+    if (max_level) *max_level = ctx->c.num_q - 1;
+    if (num_primes) *num_primes = ctx->c.nprimes;
+  });
+}
+
+int hetal_ctx_primes(const hetal_ctx* ctx, uint64_t* out) {
+  return guarded([&] {
+    need(ctx && out, HETAL_E_INVALID_ARG, "null argument");
+    std::memcpy(out, ctx->c.primes.data(), ctx->c.primes.size() * 8);
+  });
+}
+
+int hetal_synchronize(hetal_ctx* ctx) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    HCHECK(hipStreamSynchronize(ctx->c.stream));
+  });
+}
+
+uint64_t hetal_galois_rot(const hetal_ctx* ctx, int r) { return ctx ? galois_rot(ctx->c, r) : 0; }
+uint64_t hetal_galois_conj(const hetal_ctx* ctx) { return ctx ? galois_conj(ctx->c) : 0; }
+
+int hetal_sk_create(hetal_ctx* ctx, const int64_t* s_coeffs, hetal_sk** out) {
+  return guarded([&] {
+    need(ctx && s_coeffs && out, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    for (int k = 0; k < c.n; ++k) need(s_coeffs[k] >= -1 && s_coeffs[k] <= 1, HETAL_E_INVALID_ARG, "secret must be ternary");
+    u64* s = nullptr;
+    if (hipMalloc(&s, (size_t)c.nprimes * c.n * 8) != hipSuccess) fail(HETAL_E_OOM, "secret key allocation");
+    Tmp coef = upload_words(c, s_coeffs, (size_t)c.n * 8);
+    RowsRef all = c.rows(ROWS_ALL, 0);
+    k_reduce_signed(c, reinterpret_cast<const i64*>(coef.p), s, all, 1, 0, 0);
+    ntt_forward(c, s, 0, 1, all);
+    HCHECK(hipStreamSynchronize(c.stream));
+    hetal_sk* h = new hetal_sk{ctx, SecretKeyDev{s}};
+    *out = h;
+  });
+}
+
+void hetal_sk_destroy(hetal_sk* sk) {
+  if (!sk) return;
+  (void)hipStreamSynchronize(sk->ctx->c.stream);
+  (void)hipFree(sk->key.s);
+  delete sk;
+}
+
+int hetal_keys_create(hetal_ctx* ctx, hetal_keys** out) {
+  return guarded([&] {
+    need(ctx && out, HETAL_E_INVALID_ARG, "null argument");
+    *out = new hetal_keys{ctx, KeySet{}};
+  });
+}
+
+void hetal_keys_destroy(hetal_keys* keys) {
+  if (!keys) return;
+  (void)hipStreamSynchronize(keys->ctx->c.stream);
+  if (keys->set.relin) (void)hipFree(keys->set.relin);
+  for (auto& kv : keys->set.galois) (void)hipFree(kv.second);
+  delete keys;
+}
+
+static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint64_t* a_host, const int64_t* e_host) {
+  const size_t rows_words = (size_t)c.nprimes * c.n;
+  Tmp a(c.pool, (size_t)c.dnum * rows_words);
+  Tmp e(c.pool, (size_t)c.dnum * rows_words);
+  HCHECK(hipStreamSynchronize(c.stream));
+  HCHECK(hipMemcpyAsync(a.p, a_host, (size_t)c.dnum * rows_words * 8, hipMemcpyHostToDevice, c.stream));
+  RowsRef all = c.rows(ROWS_ALL, 0);
+  ntt_forward(c, a, rows_words, c.dnum, all);
+  Tmp ecoef = upload_words(c, e_host, (size_t)c.dnum * c.n * 8);
+  k_reduce_signed(c, reinterpret_cast<const i64*>(ecoef.p), e, all, c.dnum, c.n, rows_words);
+  ntt_forward(c, e, rows_words, c.dnum, all);
+  u64* key = nullptr;
+  if (hipMalloc(&key, c.key_words() * 8) != hipSuccess) fail(HETAL_E_OOM, "key allocation");
+  k_keygen(c, a, e, s, sp, key);
+  HCHECK(hipStreamSynchronize(c.stream));
+  return key;
+}
+
+int hetal_keys_gen_relin(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, const uint64_t* a, const int64_t* e) {
+  return guarded([&] {
+    need(ctx && keys && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    Tmp s2(c.pool, (size_t)c.nprimes * c.n);
+    k_mul_rows(c, sk->key.s, sk->key.s, s2, c.nprimes, c.nprimes, c.nprimes);
+    u64* key = make_switch_key(c, sk->key.s, s2, a, e);
+    if (keys->set.relin) (void)hipFree(keys->set.relin);
+    keys->set.relin = key;
+  });
+}
+
+int hetal_keys_gen_galois(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, uint64_t galois, const uint64_t* a,
+                          const int64_t* e) {
+  return guarded([&] {
+    need(ctx && keys && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    need(galois % 2 == 1 && galois < 2ull * c.n, HETAL_E_INVALID_ARG, "Galois element must be odd and below 2N");
+    Tmp sg(c.pool, (size_t)c.nprimes * c.n);
+    k_galois(c, sk->key.s, sg, c.nprimes, c.nprimes, (u32)galois);
+    u64* key = make_switch_key(c, sk->key.s, sg, a, e);
+    auto it = keys->set.galois.find((u32)galois);
+    if (it != keys->set.galois.end()) (void)hipFree(it->second);
+    keys->set.galois[(u32)galois] = key;
+  });
+}
+
+int hetal_encode(hetal_ctx* ctx, const double* re, const double* im, int level, double scale, hetal_pt* out) {
+  return guarded([&] {
+    need(ctx && re && out && out->data, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    need(level >= 0 && level < c.num_q, HETAL_E_LEVEL, "level out of range");
+    need(out->capacity >= c.poly_words(level), HETAL_E_INVALID_ARG, "plaintext capacity too small");
+    need(scale > 0, HETAL_E_SCALE, "scale must be positive");
+    Tmp dre = upload_words(c, re, (size_t)c.slots * 8);
+    Tmp dim(c.pool, c.slots);
+    HCHECK(hipStreamSynchronize(c.stream));
+    if (im) HCHECK(hipMemcpyAsync(dim.p, im, (size_t)c.slots * 8, hipMemcpyHostToDevice, c.stream));
+    encode_slots(c, reinterpret_cast<double*>(dre.p), im ? reinterpret_cast<double*>(dim.p) : nullptr, 1, 0, level,
+                 scale, out->data, 0);
+    out->level = level;
+    out->scale = scale;
+  });
+}
+
+int hetal_decode(hetal_ctx* ctx, const hetal_pt* pt, double* re, double* im) {
+  return guarded([&] {
+    need(ctx && re, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_pt(c, pt);
+    const size_t poly = c.poly_words(pt->level);
+    Tmp coef(c.pool, poly);
+    HCHECK(hipMemcpyAsync(coef.p, pt->data, poly * 8, hipMemcpyDeviceToDevice, c.stream));
+    RowsRef rows = c.rows(ROWS_CT, pt->level);
+    ntt_inverse(c, coef, 0, 1, RowsRef{rows.d, pt->level + 1});
+    Tmp out(c.pool, (size_t)c.slots * 2);
+    double* dre = reinterpret_cast<double*>(out.p);
+    k_decode(c, coef, pt->level, pt->scale, dre, dre + c.slots);
+    HCHECK(hipMemcpyAsync(re, dre, (size_t)c.slots * 8, hipMemcpyDeviceToHost, c.stream));
+    if (im) HCHECK(hipMemcpyAsync(im, dre + c.slots, (size_t)c.slots * 8, hipMemcpyDeviceToHost, c.stream));
+    HCHECK(hipStreamSynchronize(c.stream));
+  });
+}
+
+int hetal_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, const uint64_t* a, const int64_t* e,
+                  hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_pt(c, pt);
+    check_out(c, out, pt->level);
+    const size_t poly = c.poly_words(pt->level);
+    Tmp an(c.pool, poly), en(c.pool, poly);
+    load_randomness(c, a, e, pt->level, 1, an, en);
+    k_encrypt(c, an, en, pt->data, sk->key.s, out->data, pt->level);
+    out->level = pt->level;
+    out->scale = pt->scale;
+  });
+}
+
+int hetal_decrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, hetal_pt* out) {
+  return guarded([&] {
+    need(ctx && sk && out && out->data, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_ct(c, ct, "ciphertext");
+    need(out->capacity >= c.poly_words(ct->level), HETAL_E_INVALID_ARG, "plaintext capacity too small");
+    k_decrypt(c, ct->data, sk->key.s, out->data, ct->level);
+    out->level = ct->level;
+    out->scale = ct->scale;
+  });
+}
+
+int hetal_add(hetal_ctx* ctx, const hetal_ct* a, const hetal_ct* b, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, a, "a");
+    check_ct(ctx->c, b, "b");
+    check_out(ctx->c, out, a->level);
+    double s;
+    op_add(ctx->c, view_of(a), view_of(b), out->data, &s, false);
+    out->level = a->level;
+    out->scale = s;
+  });
+}
+
+int hetal_sub(hetal_ctx* ctx, const hetal_ct* a, const hetal_ct* b, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, a, "a");
+    check_ct(ctx->c, b, "b");
+    check_out(ctx->c, out, a->level);
+    double s;
+    op_add(ctx->c, view_of(a), view_of(b), out->data, &s, true);
+    out->level = a->level;
+    out->scale = s;
+  });
+}
+
+int hetal_mul_i(hetal_ctx* ctx, const hetal_ct* a, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, a, "a");
+    check_out(ctx->c, out, a->level);
+    op_mul_i(ctx->c, view_of(a), out->data);
+    out->level = a->level;
+    out->scale = a->scale;
+  });
+}
+
+int hetal_cmult(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, ct, "ciphertext");
+    check_pt(ctx->c, pt);
+    need(pt->level == ct->level, HETAL_E_LEVEL, "plaintext and ciphertext levels differ");
+    check_out(ctx->c, out, ct->level);
+    need(out->data != pt->data, HETAL_E_INVALID_ARG, "output must not alias the plaintext");
+    op_cmult(ctx->c, view_of(ct), pt->data, out->data);
+    out->level = ct->level;
+    out->scale = ct->scale * pt->scale;
+  });
+}
+
+int hetal_hmult(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* a, const hetal_ct* b, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && keys, HETAL_E_INVALID_ARG, "null argument");
+    check_ct(ctx->c, a, "a");
+    check_ct(ctx->c, b, "b");
+    check_out(ctx->c, out, a->level);
+    const double s = a->scale * b->scale;
+    op_hmult(ctx->c, keys->set, view_of(a), view_of(b), out->data);
+    out->level = a->level;
+    out->scale = s;
+  });
+}
+
+int hetal_hrot(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, int r, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && keys, HETAL_E_INVALID_ARG, "null argument");
+    check_ct(ctx->c, ct, "ciphertext");
+    check_out(ctx->c, out, ct->level);
+    const double s = ct->scale;
+    const int lv = ct->level;
+    op_galois(ctx->c, keys->set, view_of(ct), galois_rot(ctx->c, r), out->data);
+    ctx->c.counters[0] += 1;
+    out->level = lv;
+    out->scale = s;
+  });
+}
+
+int hetal_conj(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && keys, HETAL_E_INVALID_ARG, "null argument");
+    check_ct(ctx->c, ct, "ciphertext");
+    check_out(ctx->c, out, ct->level);
+    const double s = ct->scale;
+    const int lv = ct->level;
+    op_galois(ctx->c, keys->set, view_of(ct), galois_conj(ctx->c), out->data);
+    ctx->c.counters[1] += 1;
+    out->level = lv;
+    out->scale = s;
+  });
+}
+
+int hetal_rescale(hetal_ctx* ctx, const hetal_ct* ct, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, ct, "ciphertext");
+    need(ct->level >= 1, HETAL_E_LEVEL, "no level left to rescale");
+    check_out(ctx->c, out, ct->level - 1);
+    const int lv = ct->level;
+    const double s = ct->scale / (double)ctx->c.primes[lv];
+    op_rescale(ctx->c, view_of(ct), out->data);
+    out->level = lv - 1;
+    out->scale = s;
+  });
+}
+
+int hetal_mod_drop(hetal_ctx* ctx, const hetal_ct* ct, int level, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, ct, "ciphertext");
+    need(level >= 0 && level <= ct->level, HETAL_E_LEVEL, "target level out of range");
+    check_out(ctx->c, out, level);
+    const double s = ct->scale;
+    op_mod_drop(ctx->c, view_of(ct), level, out->data);
+    out->level = level;
+    out->scale = s;
+  });
+}
+
+int hetal_ct_to_coeff(hetal_ctx* ctx, const hetal_ct* ct, uint64_t* host) {
+  return guarded([&] {
+    need(ctx && host, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_ct(c, ct, "ciphertext");
+    const size_t words = c.ct_words(ct->level);
+    Tmp t(c.pool, words);
+    HCHECK(hipMemcpyAsync(t.p, ct->data, words * 8, hipMemcpyDeviceToDevice, c.stream));
+    ntt_inverse(c, t, 0, 1, c.rows(ROWS_CT, ct->level));
+    HCHECK(hipMemcpyAsync(host, t.p, words * 8, hipMemcpyDeviceToHost, c.stream));
+    HCHECK(hipStreamSynchronize(c.stream));
+  });
+}
+
+int hetal_pt_to_coeff(hetal_ctx* ctx, const hetal_pt* pt, uint64_t* host) {
+  return guarded([&] {
+    need(ctx && host, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_pt(c, pt);
+    const size_t words = c.poly_words(pt->level);
+    Tmp t(c.pool, words);
+    HCHECK(hipMemcpyAsync(t.p, pt->data, words * 8, hipMemcpyDeviceToDevice, c.stream));
+    RowsRef rows = c.rows(ROWS_CT, pt->level);
+    ntt_inverse(c, t, 0, 1, RowsRef{rows.d, pt->level + 1});
+    HCHECK(hipMemcpyAsync(host, t.p, words * 8, hipMemcpyDeviceToHost, c.stream));
+    HCHECK(hipStreamSynchronize(c.stream));
+  });
+}
+
+int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double scale, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && host, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    need(level >= 0 && level < c.num_q, HETAL_E_LEVEL, "level out of range");
+    check_out(c, out, level);
+    const size_t words = c.ct_words(level);
+    HCHECK(hipStreamSynchronize(c.stream));
+    for (int p = 0; p < 2; ++p)
+      for (int i = 0; i <= level; ++i)
+        for (int k = 0; k < c.n; ++k)
+          need(host[((size_t)p * (level + 1) + i) * c.n + k] < c.primes[i], HETAL_E_INVALID_ARG, "residue not reduced");
+    HCHECK(hipMemcpyAsync(out->data, host, words * 8, hipMemcpyHostToDevice, c.stream));
+    ntt_forward(c, out->data, 0, 1, c.rows(ROWS_CT, level));
+    HCHECK(hipStreamSynchronize(c.stream));
+    out->level = level;
+    out->scale = scale;
+  });
+}
+
+int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int cc,
+                      const uint64_t* a, const int64_t* e, hetal_mat* out) {
+  return guarded([&] {
+    need(ctx && sk && host && a && e && out && out->data, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    need(rows > 0 && cols > 0, HETAL_E_SHAPE, "empty matrix");
+    need(out->s0 > 0 && c.slots % out->s0 == 0, HETAL_E_SHAPE, "s0 must divide N/2");
+    const int s0 = out->s0, s1 = c.slots / s0;
+    need(out->level >= 0 && out->level < c.num_q, HETAL_E_LEVEL, "level out of range");
+    need(out->scale > 0, HETAL_E_SCALE, "scale must be positive");
+    int n_rb, n_cb;
+    if (tiling == 0) {
+      n_rb = (rows + s0 - 1) / s0;
+      n_cb = (cols + s1 - 1) / s1;
+    } else if (tiling == 1) {
+      need(cc >= rows && cc > 0 && s0 % cc == 0, HETAL_E_SHAPE, "vertical tiling needs rows <= c and c | s0");
+      n_rb = 1;
+      n_cb = (cols + s1 - 1) / s1;
+    } else if (tiling == 2) {
+      need(cc >= cols && cc > 0 && s1 % cc == 0, HETAL_E_SHAPE, "horizontal tiling needs cols <= c and c | s1");
+      n_rb = (rows + s0 - 1) / s0;
+      n_cb = 1;
+    } else {
+      fail(HETAL_E_INVALID_ARG, "tiling must be 0, 1 or 2");
+    }
+    const int nb = n_rb * n_cb;
+    const int lv = out->level;
+    need(out->capacity >= (size_t)nb * c.ct_words(lv), HETAL_E_INVALID_ARG, "matrix capacity too small");
+    Tmp dmat = upload_words(c, host, (size_t)rows * cols * 8);
+    Tmp slots(c.pool, (size_t)nb * c.slots);
+    k_block_layout(c, reinterpret_cast<const double*>(dmat.p), rows, cols, tiling, cc, s0, s1, n_rb, n_cb,
+                   reinterpret_cast<double*>(slots.p));
+    const size_t poly = c.poly_words(lv);
+    Tmp pts(c.pool, (size_t)nb * poly);
+    encode_slots(c, reinterpret_cast<const double*>(slots.p), nullptr, nb, c.slots, lv, out->scale, pts, poly);
+    Tmp an(c.pool, (size_t)nb * poly), en(c.pool, (size_t)nb * poly);
+    load_randomness(c, a, e, lv, nb, an, en);
+    for (int b = 0; b < nb; ++b)
+      k_encrypt(c, an.p + b * poly, en.p + b * poly, pts.p + b * poly, sk->key.s, out->data + b * c.ct_words(lv), lv);
+    out->n_rb = n_rb;
+    out->n_cb = n_cb;
+    out->s1 = s1;
+    HCHECK(hipStreamSynchronize(c.stream));
+  });
+}
+
+int hetal_mat_decrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_mat* m, double* host) {
+  return guarded([&] {
+    need(ctx && sk && m && m->data && host, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    need(m->s0 > 0 && (long)m->s0 * m->s1 == c.slots, HETAL_E_SHAPE, "bad block shape");
+    const int nb = m->n_rb * m->n_cb, lv = m->level;
+    need(m->capacity >= (size_t)nb * c.ct_words(lv), HETAL_E_INVALID_ARG, "matrix capacity too small");
+    const size_t poly = c.poly_words(lv);
+    Tmp pt(c.pool, poly);
+    Tmp sl(c.pool, c.slots);
+    std::vector<double> slots(c.slots);
+    const long width = (long)m->n_cb * m->s1;
+    RowsRef rows = c.rows(ROWS_CT, lv);
+    for (int b = 0; b < nb; ++b) {
+      k_decrypt(c, m->data + b * c.ct_words(lv), sk->key.s, pt, lv);
+      ntt_inverse(c, pt, 0, 1, RowsRef{rows.d, lv + 1});
+      k_decode(c, pt, lv, m->scale, reinterpret_cast<double*>(sl.p), nullptr);
+      HCHECK(hipMemcpyAsync(slots.data(), sl.p, (size_t)c.slots * 8, hipMemcpyDeviceToHost, c.stream));
+      HCHECK(hipStreamSynchronize(c.stream));
+      const int bi = b / m->n_cb, bj = b % m->n_cb;
+      for (int r = 0; r < m->s0; ++r)
+        std::memcpy(host + ((long)bi * m->s0 + r) * width + (long)bj * m->s1, slots.data() + (long)r * m->s1,
+                    (size_t)m->s1 * 8);
+    }
+  });
+}
+
+static std::vector<CtView> block_views(const Context& c, const hetal_mat* m) {
+  std::vector<CtView> v;
+  for (int b = 0; b < m->n_rb * m->n_cb; ++b) v.push_back(CtView{m->data + b * c.ct_words(m->level), m->level, m->scale});
+  return v;
+}
+
+static void check_mat(const Context& c, const hetal_mat* m, const char* what) {
+  need(m && m->data, HETAL_E_INVALID_ARG, what);
+  need(m->n_rb > 0 && m->n_cb > 0, HETAL_E_SHAPE, "empty block grid");
+  need(m->s0 > 0 && (long)m->s0 * m->s1 == c.slots, HETAL_E_SHAPE, "s0 * s1 must equal N/2");
+  need(m->level >= 0 && m->level < c.num_q, HETAL_E_LEVEL, "matrix level out of range");
+  need(m->capacity >= (size_t)m->n_rb * m->n_cb * c.ct_words(m->level), HETAL_E_INVALID_ARG, "matrix capacity too small");
+}
+
+static void store_blocks(Context& c, std::vector<Cipher>& res, hetal_mat* out, int n_rb, int n_cb, int s0, int s1) {
+  const int lv = res[0].level;
+  need(out && out->data, HETAL_E_INVALID_ARG, "output matrix");
+  need(out->capacity >= res.size() * c.ct_words(lv), HETAL_E_INVALID_ARG, "output capacity too small");
+  for (size_t b = 0; b < res.size(); ++b)
+    HCHECK(hipMemcpyAsync(out->data + b * c.ct_words(lv), res[b].d, c.ct_words(lv) * 8, hipMemcpyDeviceToDevice,
+                          c.stream));
+  out->n_rb = n_rb;
+  out->n_cb = n_cb;
+  out->s0 = s0;
+  out->s1 = s1;
+  out->level = lv;
+  out->scale = res[0].scale;
+}
+
+int hetal_enc_matmul_abt(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* a, const hetal_mat* bbar, int cc,
+                         double t, hetal_mat* out) {
+  return guarded([&] {
+    need(ctx && keys, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_mat(c, a, "A");
+    check_mat(c, bbar, "Bbar");
+    need(a->s0 == bbar->s0, HETAL_E_SHAPE, "A and Bbar block shapes differ");
+    need(bbar->n_rb == 1 && bbar->n_cb == a->n_cb, HETAL_E_SHAPE, "Bbar must be one block row matching A's columns");
+    std::vector<CtView> av = block_views(c, a), bv = block_views(c, bbar);
+    std::vector<std::vector<CtView>> A(a->n_rb);
+    for (int i = 0; i < a->n_rb; ++i) A[i].assign(av.begin() + i * a->n_cb, av.begin() + (i + 1) * a->n_cb);
+    std::vector<Cipher> res = diag_abt(c, keys->set, ctx->masks, A, bv, cc, a->s0, a->s1, t);
+    store_blocks(c, res, out, a->n_rb, 1, a->s0, a->s1);
+  });
+}
+
+int hetal_enc_matmul_atb(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* abar, const hetal_mat* b, int cc,
+                         double t, hetal_mat* out) {
+  return guarded([&] {
+    need(ctx && keys, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_mat(c, abar, "Abar");
+    check_mat(c, b, "B");
+    need(abar->s0 == b->s0, HETAL_E_SHAPE, "Abar and B block shapes differ");
+    need(abar->n_cb == 1 && abar->n_rb == b->n_rb, HETAL_E_SHAPE, "Abar must be one block column matching B's rows");
+    std::vector<CtView> av = block_views(c, abar), bv = block_views(c, b);
+    std::vector<std::vector<CtView>> B(b->n_rb);
+    for (int i = 0; i < b->n_rb; ++i) B[i].assign(bv.begin() + i * b->n_cb, bv.begin() + (i + 1) * b->n_cb);
+    std::vector<Cipher> res = diag_atb(c, keys->set, ctx->masks, av, B, cc, b->s0, b->s1, t);
+    store_blocks(c, res, out, 1, b->n_cb, b->s0, b->s1);
+  });
+}
+
+int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int cc, int s0, int32_t* out, int* n) {
+  return guarded([&] {
+    need(ctx && n, HETAL_E_INVALID_ARG, "null argument");
+    need(s0 > 0 && ctx->c.slots % s0 == 0, HETAL_E_SHAPE, "s0 must divide N/2");
+    std::vector<int> steps = required_rot_steps(ctx->c, op, cc, s0);
+    need(out == nullptr || *n >= (int)steps.size(), HETAL_E_INVALID_ARG, "output array too small");
+    if (out)
+      for (size_t i = 0; i < steps.size(); ++i) out[i] = steps[i];
+    *n = (int)steps.size();
+  });
+}
+
+int hetal_counters_get(const hetal_ctx* ctx, int64_t* out8) {
+  return guarded([&] {
+    need(ctx && out8, HETAL_E_INVALID_ARG, "null argument");
+    std::memcpy(out8, ctx->c.counters, sizeof(ctx->c.counters));
+  });
+}
+
+int hetal_counters_reset(hetal_ctx* ctx) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    std::memset(ctx->c.counters, 0, sizeof(ctx->c.counters));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+// Internal declarations of the HETAL gfx950 library: the context with its
+// precomputed tables, the device memory pool, and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "hetal.h"
+#include "modarith.hpp"
+
+namespace hetal {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+#define HCHECK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) ::hetal::fail(HETAL_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int MAX_PRIMES = 32;
+constexpr int MAX_ALPHA = 8;
+constexpr int MAX_K = 8;
+constexpr int MAX_BATCH = 16;
+
+// Fast basis conversion constants of one digit at one level (ModUp).
+struct ModUpTab {
+  int nsrc;
+  int first;                      // index of the digit's first prime (digit = [first, first + nsrc))
+  u64 dinv[MAX_ALPHA];            // (D / d_i)^-1 mod d_i
+  u64 dinv_sh[MAX_ALPHA];         // its Shoup companion
+  u64 dhat[MAX_ALPHA][MAX_PRIMES];  // (D / d_i) mod t, t = global prime index
+};
+
+// Centred conversion from the special primes to q_i, and P^-1 mod q_i (ModDown).
+struct ModDownTab {
+  int k;
+  int pad;
+  u64 pkinv[MAX_K];               // (P / p_k)^-1 mod p_k
+  u64 pkinv_sh[MAX_K];
+  u64 phat[MAX_K][MAX_PRIMES];    // (P / p_k) mod q_i
+  u64 pinv[MAX_PRIMES];           // P^-1 mod q_i
+  u64 pinv_sh[MAX_PRIMES];
+};
+
+// q_l^-1 mod q_i (i < l) for the rescale at level l.
+struct RescaleTab {
+  u64 inv[MAX_PRIMES];
+  u64 inv_sh[MAX_PRIMES];
+};
+
+// Per prime: N^-1, and psi^-brev(1) N^-1 (the last inverse butterfly with N^-1 merged);
+// i_q = psi^(N/2), a square root of -1 (multiplication by X^(N/2) in the NTT domain).
+struct PrimeConsts {
+  u64 ninv, ninv_sh;
+  u64 w1ninv, w1ninv_sh;
+  u64 iq, iq_sh;
+  u64 pmod;      // P mod q (0 for special primes)
+  u64 pmod_sh;
+};
+
+// Size-bucketed cache of device allocations; all work is ordered on one stream,
+// so a buffer returned to the pool may be handed out again immediately.
+class Pool {
+ public:
+  u64* get(size_t words);
+  void put(u64* p);
+  void release_all();
+  ~Pool();
+  size_t bytes_held() const { return held_; }
+
+ private:
+  std::multimap<size_t, u64*> free_;
+  std::map<u64*, size_t> size_of_;
+  size_t held_ = 0;
+};
+
+// RAII lease of a pool buffer.
+struct Tmp {
+  Pool* pool;
+  u64* p;
+  Tmp(Pool& pl, size_t words) : pool(&pl), p(pl.get(words)) {}
+  ~Tmp() {
+    if (p) pool->put(p);
+  }
+  Tmp(Tmp&& o) noexcept : pool(o.pool), p(o.p) { o.p = nullptr; }
+  Tmp(const Tmp&) = delete;
+  Tmp& operator=(const Tmp&) = delete;
+  operator u64*() const { return p; }
+};
+
+enum RowTable { ROWS_CT = 0, ROWS_MODUP, ROWS_SPECIAL, ROWS_TOP, ROWS_ALL, ROWS_ALL2, ROWS_EXT, NUM_ROW_TABLES };
+
+struct RowsRef {
+  const int2* d;
+  int count;
+};
+
+struct Context {
+  int log_n = 0, n = 0, slots = 0;
+  int num_q = 0, num_p = 0, dnum = 0, alpha = 0, nprimes = 0;
+  std::vector<u64> primes;  // q_0..q_{num_q-1}, p_0..p_{num_p-1}
+  hipStream_t stream = nullptr;
+
+  ModInfo* d_mod = nullptr;          // [nprimes]
+  ulonglong2* d_tw_fwd = nullptr;    // [nprimes][N]: (psi^brev(x), Shoup)
+  ulonglong2* d_tw_inv = nullptr;    // [nprimes][N]: (psi^-brev(x), Shoup)
+  PrimeConsts* d_pc = nullptr;       // [nprimes]
+  ModUpTab* d_modup = nullptr;       // [num_q levels][dnum]
+  ModDownTab* d_moddown = nullptr;   // one table (rows q_0..q_{num_q-1})
+  RescaleTab* d_rescale = nullptr;   // [num_q]
+  double* d_roots = nullptr;         // [2N][4]: exp(2 pi i j / 2N) in double-double (re hi, re lo, im hi, im lo)
+  u32* d_pow5 = nullptr;             // [N/2]: 5^k mod 2N
+  int2* d_rows = nullptr;            // all row tables, packed
+  std::vector<int> row_off[NUM_ROW_TABLES], row_cnt[NUM_ROW_TABLES];
+
+  std::vector<ModUpTab> h_modup;
+  ModDownTab h_moddown;
+  std::vector<PrimeConsts> h_pc;
+
+  Pool pool;
+  int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  RowsRef rows(RowTable t, int level) const {
+    return RowsRef{d_rows + row_off[t][level], row_cnt[t][level]};
+  }
+  int beta(int level) const { return (level + 1 + alpha - 1) / alpha; }
+  int ext_prime(int level, int r) const { return r <= level ? r : num_q + (r - level - 1); }
+  size_t poly_words(int level) const { return (size_t)(level + 1) * n; }
+  size_t ct_words(int level) const { return 2 * poly_words(level); }
+  size_t key_words() const { return (size_t)dnum * 2 * nprimes * n; }
+  void count_launch(int k = 1) { counters[7] += k; }
+};
+
+void context_init(Context& c, const hetal_params& p, hipStream_t stream);
+void context_free(Context& c);
+
+// ---------------------------------------------------------------- kernels
+// NTT over `rows` (row index inside a batch item, prime index) of `batch`
+// items spaced batch_stride words apart.  Input and output reduced to [0, q).
+void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows);
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows);
+
+struct KsItem {
+  const u64* key;  // [dnum][2][nprimes][N]
+  u32 g;           // Galois element (1: none)
+};
+
+// Hybrid key switching of `count` polynomials at `level` (NTT form, [l][N] each,
+// in_stride apart; in_stride = 0 with hoisted: one input shared by all items).
+// out_i = (add0_i gathered by g_i (if add0) + ModDown(sum_j tau_g(ModUp_j(d)) * b_j),
+//          add1_i (if add1) + ModDown(sum_j tau_g(ModUp_j(d)) * a_j)).
+struct KsJob {
+  int level = 0;
+  int count = 0;
+  const u64* in = nullptr;
+  size_t in_stride = 0;
+  KsItem item[MAX_BATCH];
+  u64* out = nullptr;
+  size_t out_stride = 0;
+  const u64* add0 = nullptr;
+  size_t add0_stride = 0;
+  bool add0_galois = false;
+  const u64* add1 = nullptr;
+  size_t add1_stride = 0;
+};
+void key_switch(Context& c, const KsJob& job);
+
+// Elementwise kernels on [rows][N] arrays whose row i is modulo prime (i mod period).
+void k_add(Context& c, const u64* a, const u64* b, u64* out, int rows, int period);
+void k_sub(Context& c, const u64* a, const u64* b, u64* out, int rows, int period);
+void k_mul_rows(Context& c, const u64* a, const u64* b, u64* out, int rows, int period, int b_period);
+void k_mul_i(Context& c, const u64* a, u64* out, int rows, int period);
+void k_galois(Context& c, const u64* a, u64* out, int rows, int period, u32 g);
+void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int level);
+void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride);
+void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
+                     size_t out_stride);
+void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level);
+void k_decrypt(Context& c, const u64* ct, const u64* s, u64* m, int level);
+void k_keygen(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* s, const u64* sp, u64* key);
+
+// Encoding (double-double) and decoding.
+void k_encode(Context& c, const double* d_re, const double* d_im, int count, size_t slot_stride, int level,
+              double scale, u64* out, size_t out_stride, int* d_status);
+void k_decode(Context& c, const u64* m_coeff, int level, double scale, double* d_re, double* d_im);
+void k_block_layout(Context& c, const double* d_mat, int rows, int cols, int tiling, int c_rep, int s0, int s1,
+                    int n_rb, int n_cb, double* d_slots);
+
+}  // namespace hetal

@@ -1,0 +1,84 @@
+// Exact 64-bit modular arithmetic for gfx950 (device side).
+//
+// All moduli are primes below 2^50.  Residues stored in memory are always
+// reduced to [0, q).  Two multiplication forms are used:
+//   * Shoup multiplication by a constant w (with w' = floor(w 2^64 / q)):
+//     for any a < 2^64, a*w - floor(a*w'/2^64)*q lies in [0, 2q);
+//   * Barrett reduction of a 128-bit value x < 2^(b+64), b = bitlen(q) - 1,
+//     with mu = floor(2^(b+64) / q): the estimate floor((x >> b) * mu / 2^64)
+//     is at most 2 below floor(x / q), so two conditional subtractions finish.
+// Integer multiplies (v_mul_lo_u32, v_mul_hi_u32, v_mad_u64_u32) issue at
+// full rate on gfx950, so these are VALU sequences of ~20 instructions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+struct ModInfo {
+  u64 q;
+  u64 mu;       // floor(2^(b+64) / q)
+  u64 one_sh;   // floor(2^64 / q): Shoup companion of 1, for lazy final reductions
+  int b;        // bitlen(q) - 1
+  int pad;
+};
+
+struct U128 {
+  u64 lo, hi;
+};
+
+__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) { return __umul64hi(a, b); }
+
+__device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
+  U128 r;
+  r.lo = a * b;
+  r.hi = __umul64hi(a, b);
+  return r;
+}
+
+__device__ __forceinline__ void acc_wide(U128& acc, U128 x) {
+  u64 lo = acc.lo + x.lo;
+  acc.hi += x.hi + (lo < x.lo ? 1ull : 0ull);
+  acc.lo = lo;
+}
+
+// a*w mod q lazily: result in [0, 2q) for any a < 2^64.
+__device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 wp, u64 q) {
+  u64 h = __umul64hi(a, wp);
+  return a * w - h * q;
+}
+
+__device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
+
+__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 wp, u64 q) { return csub(mul_shoup_lazy(a, w, wp, q), q); }
+
+// x mod q for x < 2^64, through Shoup multiplication by 1.
+__device__ __forceinline__ u64 reduce64(u64 x, const ModInfo& m) { return csub(x - __umul64hi(x, m.one_sh) * m.q, m.q); }
+
+// x mod q for x < 2^(b+64).
+__device__ __forceinline__ u64 reduce128(U128 x, const ModInfo& m) {
+  u64 t = (x.hi << (64 - m.b)) | (x.lo >> m.b);
+  u64 qh = __umul64hi(t, m.mu);
+  u64 r = x.lo - qh * m.q;
+  r = csub(r, m.q);
+  return csub(r, m.q);
+}
+
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const ModInfo& m) { return reduce128(mul_wide(a, b), m); }
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+__device__ __forceinline__ u64 neg_mod(u64 a, u64 q) { return a ? q - a : 0; }
+
+// 16-bit bit reversal helper for NTT-domain index maps.
+__device__ __forceinline__ u32 bit_reverse(u32 x, int bits) { return __builtin_bitreverse32(x) >> (32 - bits); }
+
+// Position in the NTT domain (bit-reversed order of the odd exponents 2k+1)
+// that holds the value at exponent g*e, for the automorphism X -> X^g.
+__device__ __forceinline__ u32 galois_source(u32 k, u32 g, int log_n) {
+  u32 e = 2u * bit_reverse(k, log_n) + 1u;
+  u32 e2 = (g * e) & ((2u << log_n) - 1u);  // only the low log_n + 1 bits matter
+  return bit_reverse((e2 - 1u) >> 1, log_n);
+}

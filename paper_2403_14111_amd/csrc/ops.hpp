@@ -1,0 +1,99 @@
+// CKKS operations on device ciphertexts (host orchestration of the kernels).
+#pragma once
+#include <map>
+#include <memory>
+#include <tuple>
+#include <utility>
+
+#include "hetal_internal.hpp"
+
+namespace hetal {
+
+// A ciphertext in a pool buffer sized for its level (move-only).
+struct Cipher {
+  Context* c = nullptr;
+  u64* d = nullptr;
+  int level = -1;
+  double scale = 0.0;
+
+  Cipher() = default;
+  Cipher(Context& ctx, int lv) : c(&ctx), d(ctx.pool.get(ctx.ct_words(lv))), level(lv) {}
+  ~Cipher() {
+    if (d) c->pool.put(d);
+  }
+  Cipher(Cipher&& o) noexcept : c(o.c), d(o.d), level(o.level), scale(o.scale) { o.d = nullptr; }
+  Cipher& operator=(Cipher&& o) noexcept {
+    if (this != &o) {
+      if (d) c->pool.put(d);
+      c = o.c;
+      d = o.d;
+      level = o.level;
+      scale = o.scale;
+      o.d = nullptr;
+    }
+    return *this;
+  }
+  Cipher(const Cipher&) = delete;
+  Cipher& operator=(const Cipher&) = delete;
+  u64* c0() const { return d; }
+  u64* c1() const { return d + c->poly_words(level); }
+};
+
+// A read-only view of a ciphertext owned elsewhere (caller memory or a Cipher).
+struct CtView {
+  const u64* d;
+  int level;
+  double scale;
+};
+
+inline CtView view(const Cipher& x) { return CtView{x.d, x.level, x.scale}; }
+
+struct SecretKeyDev {
+  u64* s = nullptr;  // [nprimes][N], NTT form
+};
+
+struct KeySet {
+  u64* relin = nullptr;
+  std::map<u32, u64*> galois;
+  const u64* get(u32 g) const {
+    auto it = galois.find(g);
+    return it == galois.end() ? nullptr : it->second;
+  }
+};
+
+u32 galois_rot(const Context& c, int r);
+u32 galois_conj(const Context& c);
+
+// Elementary operations writing into `out` (a buffer with room for the result).
+void op_add(Context& c, CtView a, CtView b, u64* out, double* scale_out, bool subtract);
+void op_mul_i(Context& c, CtView a, u64* out);
+void op_mod_drop(Context& c, CtView a, int level, u64* out);
+void op_rescale(Context& c, CtView a, u64* out);
+void op_cmult(Context& c, CtView a, const u64* pt, u64* out);
+void op_hmult(Context& c, const KeySet& k, CtView a, CtView b, u64* out);
+void op_galois(Context& c, const KeySet& k, CtView a, u32 g, u64* out);
+
+// Same on pool ciphertexts.
+Cipher add(Context& c, CtView a, CtView b);
+Cipher sub(Context& c, CtView a, CtView b);
+Cipher mul_i(Context& c, CtView a);
+Cipher mod_drop(Context& c, CtView a, int level);
+Cipher rescale(Context& c, CtView a);
+Cipher hmult(Context& c, const KeySet& k, CtView a, CtView b);
+Cipher rotate(Context& c, const KeySet& k, CtView a, int r);
+Cipher conjugate(Context& c, const KeySet& k, CtView a);
+
+// Masks: slot patterns of one s0 x s1 block, encoded at `level` with scale q_level.
+enum MaskKind { MASK_OFFDIAG_CPLX = 0, MASK_FIRST_COL = 1, MASK_LEFT_COLS = 2 };
+struct MaskCache {
+  std::map<std::tuple<int, int, int, int, int, double, int>, u64*> pts;
+  ~MaskCache();
+  Context* c = nullptr;
+};
+const u64* mask_pt(Context& c, MaskCache& cache, MaskKind kind, int k, int cc, int s0, int s1, double t, int level);
+Cipher cmult_mask(Context& c, MaskCache& cache, CtView a, MaskKind kind, int k, int cc, int s0, int s1, double t);
+
+void encode_slots(Context& c, const double* d_re, const double* d_im, int count, size_t slot_stride, int level,
+                  double scale, u64* out, size_t out_stride);
+
+}  // namespace hetal

@@ -1,0 +1,483 @@
+// RNS kernels for gfx950: hybrid key switching (ModUp, the key inner product
+// with the Galois automorphism fused into its loads, ModDown), rescale, and
+// the elementwise operations.  All of these stream limbs through HBM once;
+// each thread handles one coefficient index, so consecutive lanes touch
+// consecutive words of a limb.
+#include "hetal_internal.hpp"
+
+namespace hetal {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline dim3 grid_for(const Context& c, int y, int z) { return dim3((unsigned)(c.n / TPB), (unsigned)y, (unsigned)z); }
+
+// ---------------------------------------------------------------- ModUp
+// For digit j (blockIdx.y): rows of the digit copy the NTT-form input; every
+// other row of the extended basis q_0..q_l, p_0..p_{K-1} receives the fast
+// basis conversion of the digit's coefficient-form residues
+//   sum_i [x_i (D/d_i)^-1]_{d_i} (D/d_i) mod t    (128-bit lazy sum, one Barrett).
+__global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef, const u64* __restrict__ ntt_in,
+                                                    size_t in_stride, u64* __restrict__ dt, size_t dt_stride,
+                                                    const ModUpTab* __restrict__ tabs, const ModInfo* __restrict__ mods,
+                                                    int log_n, int level, int num_q, int num_p) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int ext = l + num_p;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int jd = blockIdx.y;
+  const ModUpTab& tb = tabs[jd];
+  const u64* __restrict__ cf = coef + blockIdx.z * in_stride;
+  const u64* __restrict__ ni = ntt_in + blockIdx.z * in_stride;
+  u64* __restrict__ out = dt + blockIdx.z * dt_stride + (size_t)jd * ext * n;
+  u64 y[MAX_ALPHA];
+#pragma unroll
+  for (int i = 0; i < MAX_ALPHA; ++i) {
+    if (i < tb.nsrc) {
+      const int s = tb.first + i;
+      y[i] = mul_shoup(cf[(size_t)s * n + k], tb.dinv[i], tb.dinv_sh[i], mods[s].q);
+    }
+  }
+  for (int r = 0; r < ext; ++r) {
+    if (r >= tb.first && r < tb.first + tb.nsrc) {
+      out[(size_t)r * n + k] = ni[(size_t)r * n + k];
+      continue;
+    }
+    const int t = r < l ? r : num_q + (r - l);
+    U128 acc = {0, 0};
+#pragma unroll
+    for (int i = 0; i < MAX_ALPHA; ++i)
+      if (i < tb.nsrc) acc_wide(acc, mul_wide(y[i], tb.dhat[i][t]));
+    out[(size_t)r * n + k] = reduce128(acc, mods[t]);
+  }
+}
+
+// ---------------------------------------------------------------- key inner product
+// acc_b[r][k] = sum_j dt_j[r][src(k)] * b_j[t][k], acc_a likewise, where src is
+// the Galois gather of the automorphism (identity for g = 1) and t the global
+// prime of extended row r.  The key streams through once; dt is re-read per item.
+struct IpArgs {
+  const u64* key[MAX_BATCH];
+  u32 g[MAX_BATCH];
+};
+
+__global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restrict__ dt, size_t dt_stride,
+                                                            u64* __restrict__ acc, size_t acc_stride, IpArgs args,
+                                                            const ModInfo* __restrict__ mods, int log_n, int level,
+                                                            int num_q, int num_p, int nprimes, int beta) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int ext = l + num_p;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int r = blockIdx.y;
+  const int item = blockIdx.z;
+  const int t = r < l ? r : num_q + (r - l);
+  const u32 g = args.g[item];
+  const u64* __restrict__ key = args.key[item];
+  const u64* __restrict__ d = dt + item * dt_stride + (size_t)r * n;
+  const u32 src = g == 1 ? (u32)k : galois_source((u32)k, g, log_n);
+  U128 sb = {0, 0}, sa = {0, 0};
+  for (int j = 0; j < beta; ++j) {
+    const u64 x = d[(size_t)j * ext * n + src];
+    const u64 kb = key[((size_t)(2 * j) * nprimes + t) * n + k];
+    const u64 ka = key[((size_t)(2 * j + 1) * nprimes + t) * n + k];
+    acc_wide(sb, mul_wide(x, kb));
+    acc_wide(sa, mul_wide(x, ka));
+  }
+  const ModInfo m = mods[t];
+  u64* __restrict__ o = acc + item * acc_stride;
+  o[(size_t)r * n + k] = reduce128(sb, m);
+  o[(size_t)(ext + r) * n + k] = reduce128(sa, m);
+}
+
+// ---------------------------------------------------------------- ModDown
+// Centred conversion of the special-prime part (coefficient form) to each q_i:
+// y_k = [x_k (P/p_k)^-1]_{p_k} taken in (-p_k/2, p_k/2]; conv_i = sum_k y_k (P/p_k) mod q_i.
+__global__ void __launch_bounds__(TPB) moddown_conv_kernel(const u64* __restrict__ acc, size_t acc_stride,
+                                                           u64* __restrict__ conv, size_t conv_stride,
+                                                           const ModDownTab* __restrict__ tab,
+                                                           const ModInfo* __restrict__ mods, int log_n, int level,
+                                                           int num_q, int num_p) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int ext = l + num_p;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int poly = blockIdx.y;
+  const u64* __restrict__ a = acc + blockIdx.z * acc_stride + (size_t)poly * ext * n;
+  u64* __restrict__ o = conv + blockIdx.z * conv_stride + (size_t)poly * l * n;
+  u64 y[MAX_K];
+  bool neg[MAX_K];
+#pragma unroll
+  for (int kk = 0; kk < MAX_K; ++kk) {
+    if (kk < num_p) {
+      const u64 pk = mods[num_q + kk].q;
+      u64 v = mul_shoup(a[(size_t)(l + kk) * n + k], tab->pkinv[kk], tab->pkinv_sh[kk], pk);
+      neg[kk] = v > (pk >> 1);
+      y[kk] = neg[kk] ? pk - v : v;
+    }
+  }
+  for (int i = 0; i < l; ++i) {
+    const ModInfo m = mods[i];
+    U128 s = {0, 0};
+#pragma unroll
+    for (int kk = 0; kk < MAX_K; ++kk) {
+      if (kk < num_p) {
+        const u64 h = tab->phat[kk][i];
+        acc_wide(s, mul_wide(y[kk], neg[kk] ? m.q - h : h));
+      }
+    }
+    o[(size_t)i * n + k] = reduce128(s, m);
+  }
+}
+
+// out_p[i] = (acc_p[i] - conv_p[i]) P^-1 + add_p[i]  (add_0 gathered by the Galois map when asked).
+struct CombineArgs {
+  const u64* add0;
+  size_t add0_stride;
+  const u64* add1;
+  size_t add1_stride;
+  u32 g[MAX_BATCH];
+  int gather;
+};
+
+__global__ void __launch_bounds__(TPB) moddown_combine_kernel(const u64* __restrict__ acc, size_t acc_stride,
+                                                              const u64* __restrict__ conv, size_t conv_stride,
+                                                              u64* __restrict__ out, size_t out_stride,
+                                                              CombineArgs ca, const ModDownTab* __restrict__ tab,
+                                                              const ModInfo* __restrict__ mods, int log_n, int level,
+                                                              int num_p) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int ext = l + num_p;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int item = blockIdx.z;
+  const u64 q = mods[i].q;
+  const u64 pinv = tab->pinv[i], pinv_sh = tab->pinv_sh[i];
+  const u64* __restrict__ a = acc + item * acc_stride;
+  const u64* __restrict__ cv = conv + item * conv_stride;
+  u64* __restrict__ o = out + item * out_stride;
+  u64 v0 = mul_shoup(sub_mod(a[(size_t)i * n + k], cv[(size_t)i * n + k], q), pinv, pinv_sh, q);
+  u64 v1 = mul_shoup(sub_mod(a[(size_t)(ext + i) * n + k], cv[(size_t)(l + i) * n + k], q), pinv, pinv_sh, q);
+  if (ca.add0) {
+    const u32 g = ca.g[item];
+    const u32 src = (ca.gather && g != 1) ? galois_source((u32)k, g, log_n) : (u32)k;
+    v0 = add_mod(v0, ca.add0[item * ca.add0_stride + (size_t)i * n + src], q);
+  }
+  if (ca.add1) v1 = add_mod(v1, ca.add1[item * ca.add1_stride + (size_t)i * n + k], q);
+  o[(size_t)i * n + k] = v0;
+  o[(size_t)(l + i) * n + k] = v1;
+}
+
+// ---------------------------------------------------------------- rescale
+// top[p][k] = coefficient-form limb `level` of poly p; spread[p][i][k] = [top]_centred mod q_i.
+__global__ void __launch_bounds__(TPB) rescale_spread_kernel(const u64* __restrict__ top, size_t top_stride,
+                                                             u64* __restrict__ spread, size_t spread_stride,
+                                                             const ModInfo* __restrict__ mods, int log_n, int level) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int poly = blockIdx.y;
+  const u64 qt = mods[level].q;
+  const u64 x = top[blockIdx.z * top_stride + (size_t)poly * n + k];
+  const bool negative = x > (qt >> 1);
+  const u64 mag = negative ? qt - x : x;
+  u64* __restrict__ o = spread + blockIdx.z * spread_stride + (size_t)poly * level * n;
+  for (int i = 0; i < level; ++i) {
+    const ModInfo m = mods[i];
+    const u64 r = reduce64(mag, m);
+    o[(size_t)i * n + k] = negative ? neg_mod(r, m.q) : r;
+  }
+}
+
+// out[p][i] = (in[p][i] - spread[p][i]) * q_level^-1 mod q_i, i < level.
+__global__ void __launch_bounds__(TPB) rescale_combine_kernel(const u64* __restrict__ in, size_t in_stride,
+                                                              const u64* __restrict__ spread, size_t spread_stride,
+                                                              u64* __restrict__ out, size_t out_stride,
+                                                              const RescaleTab* __restrict__ tab,
+                                                              const ModInfo* __restrict__ mods, int log_n, int level) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y % level;
+  const int poly = blockIdx.y / level;
+  const u64 q = mods[i].q;
+  const u64* __restrict__ a = in + blockIdx.z * in_stride + ((size_t)poly * (level + 1) + i) * n;
+  const u64* __restrict__ s = spread + blockIdx.z * spread_stride + ((size_t)poly * level + i) * n;
+  u64* __restrict__ o = out + blockIdx.z * out_stride + ((size_t)poly * level + i) * n;
+  o[k] = mul_shoup(sub_mod(a[k], s[k], q), tab->inv[i], tab->inv_sh[i], q);
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void __launch_bounds__(TPB) add_kernel(const u64* __restrict__ a, const u64* __restrict__ b,
+                                                  u64* __restrict__ o, const ModInfo* __restrict__ mods, int log_n,
+                                                  int period, int sub) {
+  const int n = 1 << log_n;
+  const size_t idx = (size_t)blockIdx.y * n + blockIdx.x * TPB + threadIdx.x;
+  const u64 q = mods[blockIdx.y % period].q;
+  o[idx] = sub ? sub_mod(a[idx], b[idx], q) : add_mod(a[idx], b[idx], q);
+}
+
+__global__ void __launch_bounds__(TPB) mul_rows_kernel(const u64* __restrict__ a, const u64* __restrict__ b,
+                                                       u64* __restrict__ o, const ModInfo* __restrict__ mods,
+                                                       int log_n, int period, int b_period) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int row = blockIdx.y;
+  const ModInfo m = mods[row % period];
+  o[(size_t)row * n + k] = mul_mod(a[(size_t)row * n + k], b[(size_t)(row % b_period) * n + k], m);
+}
+
+// Multiplication by X^(N/2): the value at exponent e = 2 brev(k) + 1 is
+// multiplied by i_q^e = i_q (e = 1 mod 4, k < N/2) or -i_q (k >= N/2).
+__global__ void __launch_bounds__(TPB) mul_i_kernel(const u64* __restrict__ a, u64* __restrict__ o,
+                                                    const ModInfo* __restrict__ mods,
+                                                    const PrimeConsts* __restrict__ pc, int log_n, int period) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int pr = blockIdx.y % period;
+  const u64 q = mods[pr].q;
+  const size_t idx = (size_t)blockIdx.y * n + k;
+  u64 v = mul_shoup(a[idx], pc[pr].iq, pc[pr].iq_sh, q);
+  o[idx] = k < (n >> 1) ? v : neg_mod(v, q);
+}
+
+__global__ void __launch_bounds__(TPB) galois_kernel(const u64* __restrict__ a, u64* __restrict__ o, int log_n,
+                                                     u32 g) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const size_t row = (size_t)blockIdx.y * n;
+  o[row + k] = a[row + galois_source((u32)k, g, log_n)];
+}
+
+// d0 = a0 b0, d1 = a0 b1 + a1 b0 (written to d01 = [2][l][N]), d2 = a1 b1.
+__global__ void __launch_bounds__(TPB) tensor_kernel(const u64* __restrict__ a, const u64* __restrict__ b,
+                                                     u64* __restrict__ d01, u64* __restrict__ d2,
+                                                     const ModInfo* __restrict__ mods, int log_n, int level) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y;
+  const ModInfo m = mods[i];
+  const size_t i0 = (size_t)i * n + k, i1 = (size_t)(l + i) * n + k;
+  const u64 a0 = a[i0], a1 = a[i1], b0 = b[i0], b1 = b[i1];
+  U128 cross = mul_wide(a0, b1);
+  acc_wide(cross, mul_wide(a1, b0));
+  d01[i0] = mul_mod(a0, b0, m);
+  d01[i1] = reduce128(cross, m);
+  d2[i0] = mul_mod(a1, b1, m);
+}
+
+// out[r][k] = coeffs[k] mod prime(r) for the rows of a row table.
+__global__ void __launch_bounds__(TPB) reduce_signed_kernel(const i64* __restrict__ coeffs, size_t coeff_stride,
+                                                            u64* __restrict__ out, size_t out_stride,
+                                                            const int2* __restrict__ rows,
+                                                            const ModInfo* __restrict__ mods, int log_n) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int2 rj = rows[blockIdx.y];
+  const ModInfo m = mods[rj.y];
+  const i64 v = coeffs[blockIdx.z * coeff_stride + k];
+  const u64 mag = v < 0 ? (u64)(-v) : (u64)v;
+  const u64 r = reduce64(mag, m);
+  out[blockIdx.z * out_stride + (size_t)rj.x * n + k] = v < 0 ? neg_mod(r, m.q) : r;
+}
+
+// ct = (-a s + m + e, a), all in NTT form.
+__global__ void __launch_bounds__(TPB) encrypt_kernel(const u64* __restrict__ a, const u64* __restrict__ e,
+                                                      const u64* __restrict__ m, const u64* __restrict__ s,
+                                                      u64* __restrict__ ct, const ModInfo* __restrict__ mods,
+                                                      int log_n, int level) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y;
+  const ModInfo md = mods[i];
+  const size_t idx = (size_t)i * n + k;
+  const u64 av = a[idx];
+  u64 v = neg_mod(mul_mod(av, s[idx], md), md.q);
+  v = add_mod(v, m[idx], md.q);
+  v = add_mod(v, e[idx], md.q);
+  ct[idx] = v;
+  ct[(size_t)(l + i) * n + k] = av;
+}
+
+__global__ void __launch_bounds__(TPB) decrypt_kernel(const u64* __restrict__ ct, const u64* __restrict__ s,
+                                                      u64* __restrict__ m, const ModInfo* __restrict__ mods,
+                                                      int log_n, int level) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y;
+  const ModInfo md = mods[i];
+  const size_t idx = (size_t)i * n + k;
+  m[idx] = add_mod(ct[idx], mul_mod(ct[(size_t)(l + i) * n + k], s[idx], md), md.q);
+}
+
+// key[j][0][t] = -a_j s + e_j + (t in digit j ? (P mod q_t) s' : 0); key[j][1][t] = a_j (NTT form).
+__global__ void __launch_bounds__(TPB) keygen_kernel(const u64* __restrict__ a, const u64* __restrict__ e,
+                                                     const u64* __restrict__ s, const u64* __restrict__ sp,
+                                                     u64* __restrict__ key, const ModInfo* __restrict__ mods,
+                                                     const PrimeConsts* __restrict__ pc, int log_n, int nprimes,
+                                                     int num_q, int alpha) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int t = blockIdx.y;
+  const int j = blockIdx.z;
+  const ModInfo md = mods[t];
+  const size_t in_idx = ((size_t)j * nprimes + t) * n + k;
+  const size_t sk_idx = (size_t)t * n + k;
+  const u64 av = a[in_idx];
+  u64 v = neg_mod(mul_mod(av, s[sk_idx], md), md.q);
+  v = add_mod(v, e[in_idx], md.q);
+  if (t < num_q && t / alpha == j) v = add_mod(v, mul_shoup(sp[sk_idx], pc[t].pmod, pc[t].pmod_sh, md.q), md.q);
+  key[((size_t)(2 * j) * nprimes + t) * n + k] = v;
+  key[((size_t)(2 * j + 1) * nprimes + t) * n + k] = av;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+void key_switch(Context& c, const KsJob& job) {
+  const int level = job.level;
+  const int l = level + 1;
+  const int ext = l + c.num_p;
+  const int beta = c.beta(level);
+  const int m = job.count;
+  if (m < 1 || m > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "key switch batch size");
+  const bool hoisted = job.in_stride == 0;
+  const int m_in = hoisted ? 1 : m;
+  const size_t n = c.n;
+  const size_t poly = (size_t)l * n;
+  const size_t dt_words = (size_t)beta * ext * n;
+  const size_t acc_words = 2 * (size_t)ext * n;
+  const size_t conv_words = 2 * poly;
+
+  // ModUp reads the coefficient-form copy and the NTT-form input at one stride.
+  if (!hoisted && m > 1 && job.in_stride != poly)
+    fail(HETAL_E_INVALID_ARG, "batched key switch inputs must be packed polynomial after polynomial");
+
+  // 1. coefficient form of the input
+  Tmp coef(c.pool, m_in * poly);
+  HCHECK(hipMemcpyAsync(coef.p, job.in, m_in * poly * 8, hipMemcpyDeviceToDevice, c.stream));
+  RowsRef ct_rows = c.rows(ROWS_CT, level);
+  ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l});
+
+  // 2. ModUp of every digit, then the NTT of the converted rows
+  Tmp dt(c.pool, m_in * dt_words);
+  hipLaunchKernelGGL(modup_kernel, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, job.in, poly, dt.p,
+                     dt_words, c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level, c.num_q, c.num_p);
+  c.count_launch();
+  ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level));
+
+  // 3. inner product with the keys, automorphism applied on the loads
+  Tmp acc(c.pool, m * acc_words);
+  IpArgs ip;
+  for (int i = 0; i < MAX_BATCH; ++i) {
+    ip.key[i] = i < m ? job.item[i].key : nullptr;
+    ip.g[i] = i < m ? job.item[i].g : 1;
+  }
+  hipLaunchKernelGGL(inner_product_kernel, grid_for(c, ext, m), dim3(TPB), 0, c.stream, dt.p,
+                     hoisted ? (size_t)0 : dt_words, acc.p, acc_words, ip, c.d_mod, c.log_n, level, c.num_q, c.num_p,
+                     c.nprimes, beta);
+  c.count_launch();
+
+  // 4. ModDown: special rows to coefficient form, centred conversion, NTT, combine
+  ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level));
+  Tmp conv(c.pool, m * conv_words);
+  hipLaunchKernelGGL(moddown_conv_kernel, grid_for(c, 2, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
+                     conv_words, c.d_moddown, c.d_mod, c.log_n, level, c.num_q, c.num_p);
+  c.count_launch();
+  ntt_forward(c, conv, conv_words, m, ct_rows);
+  CombineArgs ca;
+  ca.add0 = job.add0;
+  ca.add0_stride = job.add0_stride;
+  ca.add1 = job.add1;
+  ca.add1_stride = job.add1_stride;
+  ca.gather = job.add0_galois ? 1 : 0;
+  for (int i = 0; i < MAX_BATCH; ++i) ca.g[i] = i < m ? job.item[i].g : 1;
+  hipLaunchKernelGGL(moddown_combine_kernel, grid_for(c, l, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
+                     conv_words, job.out, job.out_stride, ca, c.d_moddown, c.d_mod, c.log_n, level, c.num_p);
+  c.count_launch();
+  c.counters[5] += m;
+}
+
+void k_add(Context& c, const u64* a, const u64* b, u64* out, int rows, int period) {
+  hipLaunchKernelGGL(add_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n, period, 0);
+  c.count_launch();
+}
+
+void k_sub(Context& c, const u64* a, const u64* b, u64* out, int rows, int period) {
+  hipLaunchKernelGGL(add_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n, period, 1);
+  c.count_launch();
+}
+
+void k_mul_rows(Context& c, const u64* a, const u64* b, u64* out, int rows, int period, int b_period) {
+  hipLaunchKernelGGL(mul_rows_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n,
+                     period, b_period);
+  c.count_launch();
+}
+
+void k_mul_i(Context& c, const u64* a, u64* out, int rows, int period) {
+  hipLaunchKernelGGL(mul_i_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, out, c.d_mod, c.d_pc, c.log_n,
+                     period);
+  c.count_launch();
+}
+
+void k_galois(Context& c, const u64* a, u64* out, int rows, int period, u32 g) {
+  (void)period;
+  hipLaunchKernelGGL(galois_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, out, c.log_n, g);
+  c.count_launch();
+}
+
+void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int level) {
+  hipLaunchKernelGGL(tensor_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, a, b, d01, d2, c.d_mod, c.log_n,
+                     level);
+  c.count_launch();
+}
+
+void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
+  const size_t n = c.n;
+  Tmp top(c.pool, (size_t)batch * 2 * n);
+  for (int b = 0; b < batch; ++b)
+    for (int p = 0; p < 2; ++p)
+      HCHECK(hipMemcpyAsync(top.p + ((size_t)b * 2 + p) * n, in + b * in_stride + ((size_t)p * (level + 1) + level) * n,
+                            n * 8, hipMemcpyDeviceToDevice, c.stream));
+  ntt_inverse(c, top, 2 * n, batch, c.rows(ROWS_TOP, level));
+  Tmp spread(c.pool, (size_t)batch * 2 * level * n);
+  hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, batch), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
+                     2 * (size_t)level * n, c.d_mod, c.log_n, level);
+  c.count_launch();
+  ntt_forward(c, spread, 2 * (size_t)level * n, batch, c.rows(ROWS_CT, level - 1));
+  hipLaunchKernelGGL(rescale_combine_kernel, grid_for(c, 2 * level, batch), dim3(TPB), 0, c.stream, in, in_stride,
+                     spread.p, 2 * (size_t)level * n, out, out_stride, c.d_rescale + level, c.d_mod, c.log_n, level);
+  c.count_launch();
+  c.counters[4] += batch;
+}
+
+void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
+                     size_t out_stride) {
+  hipLaunchKernelGGL(reduce_signed_kernel, grid_for(c, rows.count, batch), dim3(TPB), 0, c.stream, coeffs,
+                     coeff_stride, out, out_stride, rows.d, c.d_mod, c.log_n);
+  c.count_launch();
+}
+
+void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level) {
+  hipLaunchKernelGGL(encrypt_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, a_ntt, e_ntt, m, s, ct, c.d_mod,
+                     c.log_n, level);
+  c.count_launch();
+}
+
+void k_decrypt(Context& c, const u64* ct, const u64* s, u64* m, int level) {
+  hipLaunchKernelGGL(decrypt_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, ct, s, m, c.d_mod, c.log_n,
+                     level);
+  c.count_launch();
+}
+
+void k_keygen(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* s, const u64* sp, u64* key) {
+  hipLaunchKernelGGL(keygen_kernel, grid_for(c, c.nprimes, c.dnum), dim3(TPB), 0, c.stream, a_ntt, e_ntt, s, sp, key,
+                     c.d_mod, c.d_pc, c.log_n, c.nprimes, c.num_q, c.alpha);
+  c.count_launch();
+}
+
+}  // namespace hetal

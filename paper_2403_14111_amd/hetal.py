@@ -1,0 +1,444 @@
+"""Python binding of libhetal.so (include/hetal.h): argument marshalling only.
+
+Device memory for ciphertexts, plaintexts and matrices comes from PyTorch
+(torch tensors on the current CUDA/HIP device, holding the 64-bit words); the
+library's HIP stream is PyTorch's current stream at context creation.  Every
+computation runs in the library's kernels.  If the library is not built, the
+import fails loudly: there is no other implementation behind these calls.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libhetal.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhetal.so is not built (%s); run __graft_entry__.build() or "
+                      "python paper_2403_14111_amd/build.py" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+ERRORS = {-1: "E_INVALID_ARG", -2: "E_SHAPE", -3: "E_LEVEL", -4: "E_NO_KEY", -5: "E_SCALE", -6: "E_OOM",
+          -7: "E_DEVICE", -8: "E_PARAMS", -9: "E_OVERFLOW"}
+
+
+class HetalError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_int), ("num_q", ctypes.c_int), ("num_p", ctypes.c_int), ("dnum", ctypes.c_int),
+                ("q0_bits", ctypes.c_int), ("q_bits", ctypes.c_int)]
+
+
+class _Ct(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("capacity", ctypes.c_size_t), ("level", ctypes.c_int),
+                ("scale", ctypes.c_double)]
+
+
+class _Mat(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("capacity", ctypes.c_size_t), ("n_rb", ctypes.c_int),
+                ("n_cb", ctypes.c_int), ("s0", ctypes.c_int), ("s1", ctypes.c_int), ("level", ctypes.c_int),
+                ("scale", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dblp = ctypes.POINTER(ctypes.c_double)
+_intp = ctypes.POINTER(ctypes.c_int)
+_ctp = ctypes.POINTER(_Ct)
+_matp = ctypes.POINTER(_Mat)
+
+_SIGS = {
+    "hetal_last_error": (ctypes.c_char_p, []),
+    "hetal_ctx_create": (ctypes.c_int, [ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
+    "hetal_ctx_destroy": (None, [_vp]),
+    "hetal_ctx_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "hetal_ctx_info": (ctypes.c_int, [_vp, _intp, _intp, _intp, _intp]),
+    "hetal_ctx_primes": (ctypes.c_int, [_vp, _u64p]),
+    "hetal_synchronize": (ctypes.c_int, [_vp]),
+    "hetal_galois_rot": (ctypes.c_uint64, [_vp, ctypes.c_int]),
+    "hetal_galois_conj": (ctypes.c_uint64, [_vp]),
+    "hetal_sk_create": (ctypes.c_int, [_vp, _i64p, ctypes.POINTER(_vp)]),
+    "hetal_sk_destroy": (None, [_vp]),
+    "hetal_keys_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
+    "hetal_keys_destroy": (None, [_vp]),
+    "hetal_keys_gen_relin": (ctypes.c_int, [_vp, _vp, _vp, _u64p, _i64p]),
+    "hetal_keys_gen_galois": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint64, _u64p, _i64p]),
+    "hetal_encode": (ctypes.c_int, [_vp, _dblp, _dblp, ctypes.c_int, ctypes.c_double, _ctp]),
+    "hetal_decode": (ctypes.c_int, [_vp, _ctp, _dblp, _dblp]),
+    "hetal_encrypt": (ctypes.c_int, [_vp, _vp, _ctp, _u64p, _i64p, _ctp]),
+    "hetal_decrypt": (ctypes.c_int, [_vp, _vp, _ctp, _ctp]),
+    "hetal_add": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
+    "hetal_sub": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
+    "hetal_mul_i": (ctypes.c_int, [_vp, _ctp, _ctp]),
+    "hetal_cmult": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
+    "hetal_hmult": (ctypes.c_int, [_vp, _vp, _ctp, _ctp, _ctp]),
+    "hetal_hrot": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_int, _ctp]),
+    "hetal_conj": (ctypes.c_int, [_vp, _vp, _ctp, _ctp]),
+    "hetal_rescale": (ctypes.c_int, [_vp, _ctp, _ctp]),
+    "hetal_mod_drop": (ctypes.c_int, [_vp, _ctp, ctypes.c_int, _ctp]),
+    "hetal_ct_to_coeff": (ctypes.c_int, [_vp, _ctp, _u64p]),
+    "hetal_pt_to_coeff": (ctypes.c_int, [_vp, _ctp, _u64p]),
+    "hetal_ct_from_coeff": (ctypes.c_int, [_vp, _u64p, ctypes.c_int, ctypes.c_double, _ctp]),
+    "hetal_mat_encrypt": (ctypes.c_int, [_vp, _vp, _dblp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         _u64p, _i64p, _matp]),
+    "hetal_mat_decrypt": (ctypes.c_int, [_vp, _vp, _matp, _dblp]),
+    "hetal_enc_matmul_abt": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
+    "hetal_enc_matmul_atb": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
+    "hetal_required_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
+    "hetal_counters_get": (ctypes.c_int, [_vp, _i64p]),
+    "hetal_counters_reset": (ctypes.c_int, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(rc):
+    if rc != OK:
+        raise HetalError(rc, _lib.hetal_last_error().decode())
+
+
+def _u64(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(_u64p)
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_i64p)
+
+
+def _dbl(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dblp)
+
+
+PRESETS = {
+    # 2^12 ring, q_0 (50-bit) + 4 x 40-bit, one special prime, one prime per digit.
+    "toy": dict(log_n=12, num_q=5, num_p=1, dnum=5, q0_bits=50, q_bits=40),
+    # 2^16 ring, q_0 (50-bit) + 11 x 40-bit, three special primes, dnum = 4.
+    "n16l12": dict(log_n=16, num_q=12, num_p=3, dnum=4, q0_bits=50, q_bits=40),
+}
+
+
+class Ciphertext:
+    """Device buffer ([2][level+1][N] words) + level + scale.  Also used for plaintexts ([level+1][N])."""
+
+    def __init__(self, ctx, level, words, scale=0.0):
+        self.ctx = ctx
+        self.buf = torch.empty(words, dtype=torch.int64, device=ctx.device)
+        self.level = level
+        self.scale = scale
+
+    def _struct(self):
+        return _Ct(self.buf.data_ptr(), self.buf.numel(), self.level, self.scale)
+
+
+class Matrix:
+    def __init__(self, ctx, words, s0, level, scale):
+        self.ctx = ctx
+        self.buf = torch.empty(max(words, 1), dtype=torch.int64, device=ctx.device)
+        self.n_rb = self.n_cb = 0
+        self.s0 = s0
+        self.s1 = ctx.slots // s0
+        self.level = level
+        self.scale = scale
+
+    def _struct(self):
+        return _Mat(self.buf.data_ptr(), self.buf.numel(), self.n_rb, self.n_cb, self.s0, self.s1, self.level,
+                    self.scale)
+
+    def _update(self, m):
+        self.n_rb, self.n_cb, self.s0, self.s1, self.level, self.scale = m.n_rb, m.n_cb, m.s0, m.s1, m.level, m.scale
+
+
+class Context:
+    def __init__(self, preset="toy", device="cuda:0", **overrides):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HETAL library needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        cfg = dict(PRESETS[preset]) if isinstance(preset, str) else dict(preset)
+        cfg.update(overrides)
+        self.params = Params(**cfg)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(_lib.hetal_ctx_create(ctypes.byref(self.params), _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        n, slots, ml, npr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.hetal_ctx_info(h, ctypes.byref(n), ctypes.byref(slots), ctypes.byref(ml), ctypes.byref(npr)))
+        self.n, self.slots, self.max_level, self.num_primes = n.value, slots.value, ml.value, npr.value
+        pr = np.zeros(self.num_primes, dtype=np.uint64)
+        _check(_lib.hetal_ctx_primes(h, pr.ctypes.data_as(_u64p)))
+        self.primes = [int(x) for x in pr]
+        self.num_q = cfg["num_q"]
+        self.num_p = cfg["num_p"]
+        self.dnum = cfg["dnum"]
+        self.q = self.primes[:self.num_q]
+        self.p = self.primes[self.num_q:]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.hetal_ctx_destroy(h)
+            self._h = None
+
+    # -- sizes / buffers --
+    def ct_words(self, level):
+        return 2 * (level + 1) * self.n
+
+    def new_ct(self, level):
+        return Ciphertext(self, level, self.ct_words(level))
+
+    def new_pt(self, level):
+        return Ciphertext(self, level, (level + 1) * self.n)
+
+    def galois_rot(self, r):
+        return int(_lib.hetal_galois_rot(self._h, int(r)))
+
+    def galois_conj(self):
+        return int(_lib.hetal_galois_conj(self._h))
+
+    def synchronize(self):
+        _check(_lib.hetal_synchronize(self._h))
+
+    def counters(self):
+        out = np.zeros(8, dtype=np.int64)
+        _check(_lib.hetal_counters_get(self._h, out.ctypes.data_as(_i64p)))
+        return dict(zip(["rot", "conj", "mult", "cmult", "rescale", "keyswitch", "ntt_limbs", "launches"],
+                        [int(x) for x in out]))
+
+    def reset_counters(self):
+        _check(_lib.hetal_counters_reset(self._h))
+
+    # -- keys --
+    def sk_create(self, s_coeffs):
+        s, sp = _i64(s_coeffs)
+        assert s.shape == (self.n,)
+        return SecretKey(self, s, sp)
+
+    def keys_create(self):
+        return KeySet(self)
+
+    # -- encoding / encryption --
+    def encode(self, z, level, scale):
+        z = np.asarray(z, dtype=np.complex128)
+        assert z.shape == (self.slots,)
+        re, rp = _dbl(z.real)
+        im, ip = _dbl(z.imag)
+        pt = self.new_pt(level)
+        s = pt._struct()
+        _check(_lib.hetal_encode(self._h, rp, ip, level, float(scale), ctypes.byref(s)))
+        pt.level, pt.scale = s.level, s.scale
+        return pt
+
+    def decode(self, pt):
+        re = np.empty(self.slots)
+        im = np.empty(self.slots)
+        s = pt._struct()
+        _check(_lib.hetal_decode(self._h, ctypes.byref(s), re.ctypes.data_as(_dblp), im.ctypes.data_as(_dblp)))
+        return re + 1j * im
+
+    def encrypt(self, sk, pt, a, e):
+        a, ap = _u64(a)
+        e, ep = _i64(e)
+        assert a.shape == (pt.level + 1, self.n) and e.shape == (self.n,)
+        out = self.new_ct(pt.level)
+        s = out._struct()
+        _check(_lib.hetal_encrypt(self._h, sk._h, ctypes.byref(pt._struct()), ap, ep, ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def decrypt(self, sk, ct):
+        pt = self.new_pt(ct.level)
+        s = pt._struct()
+        _check(_lib.hetal_decrypt(self._h, sk._h, ctypes.byref(ct._struct()), ctypes.byref(s)))
+        pt.level, pt.scale = s.level, s.scale
+        return pt
+
+    # -- homomorphic operations --
+    def _unary(self, fn, a, out_level, *args):
+        out = self.new_ct(out_level)
+        s = out._struct()
+        _check(fn(self._h, *args, ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def add(self, a, b):
+        return self._unary(_lib.hetal_add, a, a.level, ctypes.byref(a._struct()), ctypes.byref(b._struct()))
+
+    def sub(self, a, b):
+        return self._unary(_lib.hetal_sub, a, a.level, ctypes.byref(a._struct()), ctypes.byref(b._struct()))
+
+    def mul_i(self, a):
+        return self._unary(_lib.hetal_mul_i, a, a.level, ctypes.byref(a._struct()))
+
+    def cmult(self, a, pt):
+        return self._unary(_lib.hetal_cmult, a, a.level, ctypes.byref(a._struct()), ctypes.byref(pt._struct()))
+
+    def hmult(self, keys, a, b):
+        out = self.new_ct(a.level)
+        s = out._struct()
+        _check(_lib.hetal_hmult(self._h, keys._h, ctypes.byref(a._struct()), ctypes.byref(b._struct()),
+                                ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def hrot(self, keys, a, r):
+        out = self.new_ct(a.level)
+        s = out._struct()
+        _check(_lib.hetal_hrot(self._h, keys._h, ctypes.byref(a._struct()), int(r), ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def conj(self, keys, a):
+        out = self.new_ct(a.level)
+        s = out._struct()
+        _check(_lib.hetal_conj(self._h, keys._h, ctypes.byref(a._struct()), ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def rescale(self, a):
+        return self._unary(_lib.hetal_rescale, a, max(a.level - 1, 0), ctypes.byref(a._struct()))
+
+    def mod_drop(self, a, level):
+        return self._unary(_lib.hetal_mod_drop, a, max(min(level, a.level), 0), ctypes.byref(a._struct()),
+                           int(level))
+
+    # -- canonical forms --
+    def ct_to_coeff(self, ct):
+        out = np.empty((2, ct.level + 1, self.n), dtype=np.uint64)
+        _check(_lib.hetal_ct_to_coeff(self._h, ctypes.byref(ct._struct()), out.ctypes.data_as(_u64p)))
+        return out
+
+    def pt_to_coeff(self, pt):
+        out = np.empty((pt.level + 1, self.n), dtype=np.uint64)
+        _check(_lib.hetal_pt_to_coeff(self._h, ctypes.byref(pt._struct()), out.ctypes.data_as(_u64p)))
+        return out
+
+    def ct_from_coeff(self, coeffs, scale):
+        c, cp = _u64(coeffs)
+        level = c.shape[1] - 1
+        out = self.new_ct(level)
+        s = out._struct()
+        _check(_lib.hetal_ct_from_coeff(self._h, cp, level, float(scale), ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    # -- matrices --
+    def mat_blocks(self, rows, cols, s0, tiling=0, c=1):
+        s1 = self.slots // s0
+        if tiling == 1:
+            return 1, -(-cols // s1)
+        if tiling == 2:
+            return -(-rows // s0), 1
+        return -(-rows // s0), -(-cols // s1)
+
+    def mat_encrypt(self, sk, mat, s0, level, scale, a, e, tiling=0, c=1):
+        mat, mp = _dbl(mat)
+        rows, cols = mat.shape
+        n_rb, n_cb = self.mat_blocks(rows, cols, s0, tiling, c)
+        a, ap = _u64(a)
+        e, ep = _i64(e)
+        assert a.shape == (n_rb * n_cb, level + 1, self.n) and e.shape == (n_rb * n_cb, self.n), (a.shape, e.shape)
+        m = Matrix(self, n_rb * n_cb * self.ct_words(level), s0, level, scale)
+        s = m._struct()
+        _check(_lib.hetal_mat_encrypt(self._h, sk._h, mp, rows, cols, int(tiling), int(c), ap, ep, ctypes.byref(s)))
+        m._update(s)
+        return m
+
+    def mat_decrypt(self, sk, m):
+        out = np.empty((m.n_rb * m.s0, m.n_cb * m.s1))
+        _check(_lib.hetal_mat_decrypt(self._h, sk._h, ctypes.byref(m._struct()), out.ctypes.data_as(_dblp)))
+        return out
+
+    def mat_block(self, m, b):
+        """Ciphertext view of block b (shares the matrix's memory)."""
+        w = self.ct_words(m.level)
+        ct = Ciphertext.__new__(Ciphertext)
+        ct.ctx, ct.buf, ct.level, ct.scale = self, m.buf[b * w:(b + 1) * w], m.level, m.scale
+        return ct
+
+    def enc_matmul_abt(self, keys, a, bbar, c, t=1.0):
+        out = Matrix(self, a.n_rb * self.ct_words(min(a.level, bbar.level) - 3) if min(a.level, bbar.level) >= 3
+                     else 1, a.s0, 0, 0.0)
+        s = out._struct()
+        _check(_lib.hetal_enc_matmul_abt(self._h, keys._h, ctypes.byref(a._struct()), ctypes.byref(bbar._struct()),
+                                         int(c), float(t), ctypes.byref(s)))
+        out._update(s)
+        return out
+
+    def enc_matmul_atb(self, keys, abar, b, c, t=1.0):
+        lvl = max(abar.level, b.level)
+        out = Matrix(self, b.n_cb * self.ct_words(lvl), b.s0, 0, 0.0)
+        s = out._struct()
+        _check(_lib.hetal_enc_matmul_atb(self._h, keys._h, ctypes.byref(abar._struct()), ctypes.byref(b._struct()),
+                                         int(c), float(t), ctypes.byref(s)))
+        out._update(s)
+        return out
+
+    def required_rot_steps(self, op, c, s0):
+        n = ctypes.c_int(0)
+        _check(_lib.hetal_required_rot_steps(self._h, int(op), int(c), int(s0), None, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        _check(_lib.hetal_required_rot_steps(self._h, int(op), int(c), int(s0), out.ctypes.data_as(_i32p),
+                                             ctypes.byref(n)))
+        return [int(x) for x in out[:n.value]]
+
+
+class SecretKey:
+    def __init__(self, ctx, s, sp):
+        self.ctx = ctx
+        h = _vp()
+        _check(_lib.hetal_sk_create(ctx._h, sp, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.hetal_sk_destroy(self._h)
+            self._h = None
+
+
+class KeySet:
+    def __init__(self, ctx):
+        self.ctx = ctx
+        h = _vp()
+        _check(_lib.hetal_keys_create(ctx._h, ctypes.byref(h)))
+        self._h = h
+        self.galois = set()
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.hetal_keys_destroy(self._h)
+            self._h = None
+
+    def gen_relin(self, sk, a, e):
+        a, ap = _u64(a)
+        e, ep = _i64(e)
+        c = self.ctx
+        assert a.shape == (c.dnum, c.num_primes, c.n) and e.shape == (c.dnum, c.n)
+        _check(_lib.hetal_keys_gen_relin(c._h, self._h, sk._h, ap, ep))
+
+    def gen_galois(self, sk, g, a, e):
+        a, ap = _u64(a)
+        e, ep = _i64(e)
+        c = self.ctx
+        assert a.shape == (c.dnum, c.num_primes, c.n) and e.shape == (c.dnum, c.n)
+        _check(_lib.hetal_keys_gen_galois(c._h, self._h, sk._h, int(g), ap, ep))
+        self.galois.add(int(g))

@@ -11,3 +11,17 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library through its C ABI)")
     config.addinivalue_line("markers", "slow: full-size (N=2^16) oracle runs, tens of seconds")
+
+
+def pytest_collection_modifyitems(config, items):
+    try:
+        import torch
+        have_gpu = torch.cuda.is_available()
+    except Exception:
+        have_gpu = False
+    if have_gpu:
+        return
+    skip = pytest.mark.skip(reason="needs a ROCm GPU")
+    for item in items:
+        if "gpu" in item.keywords:
+            item.add_marker(skip)
