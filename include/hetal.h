@@ -224,6 +224,17 @@ int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int c, int s0, int32_
 int hetal_counters_get(const hetal_ctx* ctx, int64_t* out8);
 int hetal_counters_reset(hetal_ctx* ctx);
 
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch (adds two event records per launch while enabled).  Classes:
+ * [0] NTT / inverse NTT passes, [1] ModUp basis conversion, [2] key inner
+ * product, [3] ModDown basis conversion, [4] ModDown combine, [5] rescale,
+ * [6] elementwise, [7] encode / decode.  enable(on) clears what was
+ * collected; get synchronises and returns, per class, the summed kernel
+ * time in ms, the launch count and the summed algorithmic HBM bytes (each
+ * operand read once and each result written once). */
+int hetal_timing_enable(hetal_ctx* ctx, int on);
+int hetal_timing_get(hetal_ctx* ctx, double* ms8, int64_t* launches8, double* bytes8);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,314 @@
+// Batched CKKS operations: many ciphertexts at one level per launch, so that
+// every launch spans enough limbs to fill the 256 CUs, and ciphertexts that
+// share a key share its HBM reads.  Each item goes through exactly the same
+// key switches and rescales as it would alone, so results are bit-identical
+// to the one-at-a-time operations.
+#include <algorithm>
+
+#include "ops.hpp"
+
+namespace hetal {
+
+namespace {
+
+constexpr int TPB = 256;
+
+struct PtrArgs {
+  const u64* a[MAX_BATCH];
+  const u64* b[MAX_BATCH];
+};
+
+// d01[item] = (a0 b0, a0 b1 + a1 b0), d2[item] = a1 b1.
+__global__ void __launch_bounds__(TPB) tensor_batch_kernel(PtrArgs p, u64* __restrict__ d01, u64* __restrict__ d2,
+                                                           const ModInfo* __restrict__ mods, int log_n, int level) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int item = blockIdx.z;
+  const ModInfo m = mods[i];
+  const u64* __restrict__ a = p.a[item];
+  const u64* __restrict__ b = p.b[item];
+  const size_t i0 = (size_t)i * n + k, i1 = (size_t)(l + i) * n + k;
+  const u64 a0 = a[i0], a1 = a[i1], b0 = b[i0], b1 = b[i1];
+  U128 cross = mul_wide(a0, b1);
+  acc_wide(cross, mul_wide(a1, b0));
+  u64* __restrict__ o = d01 + (size_t)item * 2 * l * n;
+  o[i0] = mul_mod(a0, b0, m);
+  o[i1] = reduce128(cross, m);
+  d2[(size_t)item * l * n + i0] = mul_mod(a1, b1, m);
+}
+
+// out[item][p][i] = a[item][p][i] * pt_item[i].
+__global__ void __launch_bounds__(TPB) cmult_batch_kernel(const u64* __restrict__ a, size_t a_stride, PtrArgs p,
+                                                          u64* __restrict__ out, const ModInfo* __restrict__ mods,
+                                                          int log_n, int level) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int row = blockIdx.y;  // 0 .. 2l-1
+  const int i = row % l;
+  const int item = blockIdx.z;
+  const ModInfo m = mods[i];
+  out[(size_t)item * 2 * l * n + (size_t)row * n + k] =
+      mul_mod(a[item * a_stride + (size_t)row * n + k], p.a[item][(size_t)i * n + k], m);
+}
+
+// out[g][row] = sum_t a[g * per + t][row].
+__global__ void __launch_bounds__(TPB) sum_groups_kernel(const u64* __restrict__ a, size_t a_stride, int per,
+                                                         u64* __restrict__ out, const ModInfo* __restrict__ mods,
+                                                         int log_n, int level) {
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int row = blockIdx.y;
+  const int g = blockIdx.z;
+  const u64 q = mods[row % l].q;
+  const u64* __restrict__ src = a + (size_t)g * per * a_stride + (size_t)row * n + k;
+  u64 s = 0;
+  for (int t = 0; t < per; ++t) s = add_mod(s, src[(size_t)t * a_stride], q);
+  out[(size_t)g * 2 * l * n + (size_t)row * n + k] = s;
+}
+
+dim3 grid3(const Context& c, int y, int z) { return dim3((unsigned)(c.n / TPB), (unsigned)y, (unsigned)z); }
+
+void check_same(BView a, BView b) {
+  if (a.level != b.level || a.count != b.count) fail(HETAL_E_LEVEL, "batch operands differ in level or count");
+  if (std::abs(a.scale - b.scale) > 1e-9 * std::max(std::abs(a.scale), std::abs(b.scale)))
+    fail(HETAL_E_SCALE, "batch operands with different scales");
+}
+
+bool packed(const Context& c, BView a) { return a.stride == c.ct_words(a.level); }
+
+Batch to_packed(Context& c, BView a) {
+  Batch o(c, a.level, a.count);
+  const size_t w = c.ct_words(a.level);
+  if (a.stride >= w) {
+    HCHECK(hipMemcpy2DAsync(o.d, w * 8, a.d, a.stride * 8, w * 8, a.count, hipMemcpyDeviceToDevice, c.stream));
+  } else {  // broadcast (stride 0): one ciphertext repeated
+    for (int i = 0; i < a.count; ++i)
+      HCHECK(hipMemcpyAsync(o.d + (size_t)i * w, a.d + (size_t)i * a.stride, w * 8, hipMemcpyDeviceToDevice,
+                            c.stream));
+  }
+  o.scale = a.scale;
+  return o;
+}
+
+}  // namespace
+
+Batch b_pack(Context& c, const std::vector<CtView>& items) {
+  if (items.empty()) fail(HETAL_E_INVALID_ARG, "empty batch");
+  Batch o(c, items[0].level, (int)items.size());
+  const size_t w = c.ct_words(o.level);
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (items[i].level != o.level) fail(HETAL_E_LEVEL, "batch items at different levels");
+    HCHECK(hipMemcpyAsync(o.d + i * w, items[i].d, w * 8, hipMemcpyDeviceToDevice, c.stream));
+  }
+  o.scale = items[0].scale;
+  return o;
+}
+
+static Batch b_addsub(Context& c, BView a, BView b, bool subtract) {
+  check_same(a, b);
+  Batch pa, pb;
+  if (!packed(c, a)) {
+    pa = to_packed(c, a);
+    a = pa.v();
+  }
+  if (!packed(c, b)) {
+    pb = to_packed(c, b);
+    b = pb.v();
+  }
+  Batch o(c, a.level, a.count);
+  const int l = a.level + 1;
+  if (subtract) k_sub(c, a.d, b.d, o.d, 2 * l * a.count, l);
+  else k_add(c, a.d, b.d, o.d, 2 * l * a.count, l);
+  o.scale = a.scale;
+  return o;
+}
+
+Batch b_add(Context& c, BView a, BView b) { return b_addsub(c, a, b, false); }
+Batch b_sub(Context& c, BView a, BView b) { return b_addsub(c, a, b, true); }
+
+Batch b_mul_i(Context& c, BView a) {
+  Batch pa;
+  if (!packed(c, a)) {
+    pa = to_packed(c, a);
+    a = pa.v();
+  }
+  Batch o(c, a.level, a.count);
+  const int l = a.level + 1;
+  k_mul_i(c, a.d, o.d, 2 * l * a.count, l);
+  o.scale = a.scale;
+  return o;
+}
+
+Batch b_mod_drop(Context& c, BView a, int level) {
+  if (level > a.level || level < 0) fail(HETAL_E_LEVEL, "mod_drop target level out of range");
+  Batch o(c, level, a.count);
+  const size_t rows = c.poly_words(level), src_poly = c.poly_words(a.level);
+  // 2 count blocks of `rows` words: block (i, p) starts at i * stride + p * src_poly
+  if (a.stride == 2 * src_poly) {
+    HCHECK(hipMemcpy2DAsync(o.d, rows * 8, a.d, src_poly * 8, rows * 8, 2 * (size_t)a.count, hipMemcpyDeviceToDevice,
+                            c.stream));
+  } else if (a.stride < 2 * src_poly) {  // broadcast view
+    for (int i = 0; i < a.count; ++i)
+      for (int p = 0; p < 2; ++p)
+        HCHECK(hipMemcpyAsync(o.d + ((size_t)i * 2 + p) * rows, a.d + (size_t)i * a.stride + p * src_poly, rows * 8,
+                              hipMemcpyDeviceToDevice, c.stream));
+  } else {
+    for (int p = 0; p < 2; ++p)
+      HCHECK(hipMemcpy2DAsync(o.d + p * rows, 2 * rows * 8, a.d + p * src_poly, a.stride * 8, rows * 8, a.count,
+                              hipMemcpyDeviceToDevice, c.stream));
+  }
+  o.scale = a.scale;
+  return o;
+}
+
+Batch b_rescale(Context& c, BView a) {
+  if (a.level < 1) fail(HETAL_E_LEVEL, "no level left to rescale");
+  Batch o(c, a.level - 1, a.count);
+  k_rescale(c, a.d, o.d, a.level, a.count, a.stride, c.ct_words(a.level - 1));
+  o.scale = a.scale / (double)c.primes[a.level];
+  return o;
+}
+
+static void run_rotations(Context& c, const KeySet& k, const u64* in0, size_t in_stride, int count, bool hoisted,
+                          const std::vector<u32>& gal, int level, u64* out) {
+  const size_t poly = c.poly_words(level), w = c.ct_words(level);
+  for (int first = 0; first < count; first += MAX_BATCH) {
+    const int m = std::min(MAX_BATCH, count - first);
+    KsJob job;
+    job.level = level;
+    job.count = m;
+    job.in = (hoisted ? in0 : in0 + (size_t)first * in_stride) + poly;
+    job.in_stride = hoisted ? 0 : in_stride;
+    for (int i = 0; i < m; ++i) {
+      const u32 g = gal[first + i];
+      const u64* key = k.get(g);
+      if (!key) fail(HETAL_E_NO_KEY, "no key for Galois element " + std::to_string(g));
+      job.item[i] = KsItem{key, g};
+    }
+    job.out = out + (size_t)first * w;
+    job.out_stride = w;
+    job.add0 = hoisted ? in0 : in0 + (size_t)first * in_stride;
+    job.add0_stride = hoisted ? 0 : in_stride;
+    job.add0_galois = true;
+    key_switch(c, job);
+  }
+}
+
+Batch b_rotate(Context& c, const KeySet& k, BView a, const std::vector<int>& steps) {
+  if (steps.size() != 1 && (int)steps.size() != a.count) fail(HETAL_E_INVALID_ARG, "one step or one per item");
+  std::vector<u32> gal(a.count);
+  for (int i = 0; i < a.count; ++i) gal[i] = galois_rot(c, steps.size() == 1 ? steps[0] : steps[i]);
+  for (u32 g : gal)
+    if (g == 1) fail(HETAL_E_INVALID_ARG, "identity rotation inside a batch");
+  Batch o(c, a.level, a.count);
+  run_rotations(c, k, a.d, a.stride, a.count, false, gal, a.level, o.d);
+  o.scale = a.scale;
+  c.counters[0] += a.count;
+  return o;
+}
+
+Batch b_rotate_hoisted(Context& c, const KeySet& k, CtView a, const std::vector<int>& steps) {
+  const int count = (int)steps.size();
+  std::vector<u32> gal(count);
+  for (int i = 0; i < count; ++i) {
+    gal[i] = galois_rot(c, steps[i]);
+    if (gal[i] == 1) fail(HETAL_E_INVALID_ARG, "identity rotation inside a batch");
+  }
+  Batch o(c, a.level, count);
+  run_rotations(c, k, a.d, 0, count, true, gal, a.level, o.d);
+  o.scale = a.scale;
+  c.counters[0] += count;
+  return o;
+}
+
+Batch b_conj(Context& c, const KeySet& k, BView a) {
+  std::vector<u32> gal(a.count, galois_conj(c));
+  Batch o(c, a.level, a.count);
+  run_rotations(c, k, a.d, a.stride, a.count, false, gal, a.level, o.d);
+  o.scale = a.scale;
+  c.counters[1] += a.count;
+  return o;
+}
+
+Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b) {
+  if (a.size() != b.size() || a.empty()) fail(HETAL_E_INVALID_ARG, "hmult batch operand counts differ");
+  if (!k.relin) fail(HETAL_E_NO_KEY, "relinearisation key missing");
+  const int level = a[0].level, count = (int)a.size(), l = level + 1;
+  for (int i = 0; i < count; ++i)
+    if (a[i].level != level || b[i].level != level) fail(HETAL_E_LEVEL, "hmult operands at different levels");
+  Batch o(c, level, count);
+  const size_t poly = c.poly_words(level), w = c.ct_words(level);
+  for (int first = 0; first < count; first += MAX_BATCH) {
+    const int m = std::min(MAX_BATCH, count - first);
+    Tmp d01(c.pool, (size_t)m * w), d2(c.pool, (size_t)m * poly);
+    PtrArgs p;
+    for (int i = 0; i < MAX_BATCH; ++i) {
+      p.a[i] = i < m ? a[first + i].d : nullptr;
+      p.b[i] = i < m ? b[first + i].d : nullptr;
+    }
+    c.begin_launch();
+    hipLaunchKernelGGL(tensor_batch_kernel, grid3(c, l, m), dim3(TPB), 0, c.stream, p, d01.p, d2.p, c.d_mod, c.log_n,
+                       level);
+    c.end_launch(KC_ELEMWISE, 8.0 * c.n * l * 7.0 * m);
+    KsJob job;
+    job.level = level;
+    job.count = m;
+    job.in = d2;
+    job.in_stride = poly;
+    for (int i = 0; i < m; ++i) job.item[i] = KsItem{k.relin, 1};
+    job.out = o.d + (size_t)first * w;
+    job.out_stride = w;
+    job.add0 = d01;
+    job.add0_stride = w;
+    job.add1 = d01.p + poly;
+    job.add1_stride = w;
+    key_switch(c, job);
+  }
+  o.scale = a[0].scale * b[0].scale;
+  c.counters[2] += count;
+  return o;
+}
+
+Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks) {
+  if (masks.size() != 1 && (int)masks.size() != a.count) fail(HETAL_E_INVALID_ARG, "one mask or one per item");
+  const int l = a.level + 1;
+  Batch o(c, a.level, a.count);
+  for (int first = 0; first < a.count; first += MAX_BATCH) {
+    const int m = std::min(MAX_BATCH, a.count - first);
+    PtrArgs p;
+    for (int i = 0; i < MAX_BATCH; ++i) {
+      p.b[i] = nullptr;
+      if (i < m) {
+        const MaskSpec& s = masks.size() == 1 ? masks[0] : masks[first + i];
+        p.a[i] = mask_pt(c, mc, s.kind, s.k, s.cc, s.s0, s.s1, s.t, a.level);
+      } else {
+        p.a[i] = nullptr;
+      }
+    }
+    c.begin_launch();
+    hipLaunchKernelGGL(cmult_batch_kernel, grid3(c, 2 * l, m), dim3(TPB), 0, c.stream, a.d + (size_t)first * a.stride,
+                       a.stride, p, o.d + (size_t)first * c.ct_words(a.level), c.d_mod, c.log_n, a.level);
+    c.end_launch(KC_ELEMWISE, 8.0 * c.n * l * 5.0 * m);
+  }
+  o.scale = a.scale * (double)c.primes[a.level];
+  c.counters[3] += a.count;
+  return o;
+}
+
+Batch b_sum_groups(Context& c, BView a, int groups) {
+  if (groups < 1 || a.count % groups) fail(HETAL_E_INVALID_ARG, "group count must divide the batch");
+  const int per = a.count / groups, l = a.level + 1;
+  Batch o(c, a.level, groups);
+  c.begin_launch();
+  hipLaunchKernelGGL(sum_groups_kernel, grid3(c, 2 * l, groups), dim3(TPB), 0, c.stream, a.d, a.stride, per, o.d,
+                     c.d_mod, c.log_n, a.level);
+  c.end_launch(KC_ELEMWISE, 8.0 * c.n * 2.0 * l * (a.count + groups));
+  o.scale = a.scale;
+  return o;
+}
+
+}  // namespace hetal

@@ -119,6 +119,11 @@ void hetal_ctx_destroy(hetal_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->c.stream);
   for (auto& kv : ctx->masks.pts) ctx->c.pool.put(kv.second);
   ctx->masks.pts.clear();
+  for (auto& t : ctx->c.timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (auto e : ctx->c.ev_free) (void)hipEventDestroy(e);
   context_free(ctx->c);
   delete ctx;
 }
@@ -562,19 +567,17 @@ static void check_mat(const Context& c, const hetal_mat* m, const char* what) {
   need(m->capacity >= (size_t)m->n_rb * m->n_cb * c.ct_words(m->level), HETAL_E_INVALID_ARG, "matrix capacity too small");
 }
 
-static void store_blocks(Context& c, std::vector<Cipher>& res, hetal_mat* out, int n_rb, int n_cb, int s0, int s1) {
-  const int lv = res[0].level;
+static void store_blocks(Context& c, const Batch& res, hetal_mat* out, int n_rb, int n_cb, int s0, int s1) {
+  const int lv = res.level;
   need(out && out->data, HETAL_E_INVALID_ARG, "output matrix");
-  need(out->capacity >= res.size() * c.ct_words(lv), HETAL_E_INVALID_ARG, "output capacity too small");
-  for (size_t b = 0; b < res.size(); ++b)
-    HCHECK(hipMemcpyAsync(out->data + b * c.ct_words(lv), res[b].d, c.ct_words(lv) * 8, hipMemcpyDeviceToDevice,
-                          c.stream));
+  need(out->capacity >= (size_t)res.count * c.ct_words(lv), HETAL_E_INVALID_ARG, "output capacity too small");
+  HCHECK(hipMemcpyAsync(out->data, res.d, (size_t)res.count * c.ct_words(lv) * 8, hipMemcpyDeviceToDevice, c.stream));
   out->n_rb = n_rb;
   out->n_cb = n_cb;
   out->s0 = s0;
   out->s1 = s1;
   out->level = lv;
-  out->scale = res[0].scale;
+  out->scale = res.scale;
 }
 
 int hetal_enc_matmul_abt(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* a, const hetal_mat* bbar, int cc,
@@ -589,7 +592,7 @@ int hetal_enc_matmul_abt(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
     std::vector<CtView> av = block_views(c, a), bv = block_views(c, bbar);
     std::vector<std::vector<CtView>> A(a->n_rb);
     for (int i = 0; i < a->n_rb; ++i) A[i].assign(av.begin() + i * a->n_cb, av.begin() + (i + 1) * a->n_cb);
-    std::vector<Cipher> res = diag_abt(c, keys->set, ctx->masks, A, bv, cc, a->s0, a->s1, t);
+    Batch res = diag_abt_batch(c, keys->set, ctx->masks, A, bv, cc, a->s0, a->s1, t);
     store_blocks(c, res, out, a->n_rb, 1, a->s0, a->s1);
   });
 }
@@ -606,7 +609,7 @@ int hetal_enc_matmul_atb(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
     std::vector<CtView> av = block_views(c, abar), bv = block_views(c, b);
     std::vector<std::vector<CtView>> B(b->n_rb);
     for (int i = 0; i < b->n_rb; ++i) B[i].assign(bv.begin() + i * b->n_cb, bv.begin() + (i + 1) * b->n_cb);
-    std::vector<Cipher> res = diag_atb(c, keys->set, ctx->masks, av, B, cc, b->s0, b->s1, t);
+    Batch res = diag_atb_batch(c, keys->set, ctx->masks, av, B, cc, b->s0, b->s1, t);
     store_blocks(c, res, out, 1, b->n_cb, b->s0, b->s1);
   });
 }
@@ -634,6 +637,43 @@ int hetal_counters_reset(hetal_ctx* ctx) {
   return guarded([&] {
     need(ctx, HETAL_E_INVALID_ARG, "null context");
     std::memset(ctx->c.counters, 0, sizeof(ctx->c.counters));
+  });
+}
+
+static void recycle_timed(Context& c) {
+  for (auto& t : c.timed) {
+    c.ev_free.push_back(t.start);
+    c.ev_free.push_back(t.stop);
+  }
+  c.timed.clear();
+}
+
+int hetal_timing_enable(hetal_ctx* ctx, int on) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    HCHECK(hipStreamSynchronize(ctx->c.stream));
+    recycle_timed(ctx->c);
+    ctx->c.timing = on != 0;
+  });
+}
+
+int hetal_timing_get(hetal_ctx* ctx, double* ms8, int64_t* launches8, double* bytes8) {
+  return guarded([&] {
+    need(ctx && ms8 && launches8 && bytes8, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    HCHECK(hipStreamSynchronize(c.stream));
+    for (int k = 0; k < NUM_KC; ++k) {
+      ms8[k] = 0.0;
+      launches8[k] = 0;
+      bytes8[k] = 0.0;
+    }
+    for (auto& t : c.timed) {
+      float ms = 0.f;
+      HCHECK(hipEventElapsedTime(&ms, t.start, t.stop));
+      ms8[t.cls] += ms;
+      launches8[t.cls] += 1;
+      bytes8[t.cls] += t.bytes;
+    }
   });
 }
 

@@ -258,9 +258,10 @@ void run_dft(Context& c, double* z, int batch, int sign) {
   const int log_m = c.log_n + 1;
   const int m = 1 << log_m;
   for (int lh = 0; lh < log_m; ++lh) {
-    hipLaunchKernelGGL(dft_stage_kernel, dim3((m / 2 + EB - 1) / EB, batch), dim3(EB), 0, c.stream, z, c.d_roots,
+    c.begin_launch();
+  hipLaunchKernelGGL(dft_stage_kernel, dim3((m / 2 + EB - 1) / EB, batch), dim3(EB), 0, c.stream, z, c.d_roots,
                        log_m, lh, sign);
-    c.count_launch();
+    c.end_launch(KC_ENCODE, 0.0);
   }
 }
 
@@ -269,8 +270,9 @@ void run_dft(Context& c, double* z, int batch, int sign) {
 void make_roots(Context& c) {
   const int log_m = c.log_n + 1;
   const int m = 1 << log_m;
+  c.begin_launch();
   hipLaunchKernelGGL(roots_kernel, dim3((m + EB - 1) / EB), dim3(EB), 0, c.stream, c.d_roots, log_m);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
 }
 
 void k_encode(Context& c, const double* d_re, const double* d_im, int count, size_t slot_stride, int level,
@@ -279,13 +281,15 @@ void k_encode(Context& c, const double* d_re, const double* d_im, int count, siz
   Tmp zbuf(c.pool, (size_t)count * m * 4);
   double* z = reinterpret_cast<double*>(zbuf.p);
   HCHECK(hipMemsetAsync(z, 0, (size_t)count * m * 4 * sizeof(double), c.stream));
+  c.begin_launch();
   hipLaunchKernelGGL(encode_scatter_kernel, dim3((c.slots + EB - 1) / EB, count), dim3(EB), 0, c.stream, d_re, d_im,
                      slot_stride, c.d_pow5, z, c.log_n);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
   run_dft(c, z, count, -1);
+  c.begin_launch();
   hipLaunchKernelGGL(encode_round_kernel, dim3((c.n + EB - 1) / EB, count), dim3(EB), 0, c.stream, z, out, out_stride,
                      c.d_mod, c.log_n, level, scale, d_status);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
   RowsRef rows = c.rows(ROWS_CT, level);
   ntt_forward(c, out, out_stride, count, RowsRef{rows.d, level + 1});
 }
@@ -309,20 +313,23 @@ void k_decode(Context& c, const u64* m_coeff, int level, double scale, double* d
     }
     q0_inv = (u64)r;
   }
+  c.begin_launch();
   hipLaunchKernelGGL(decode_scatter_kernel, dim3((c.n + EB - 1) / EB), dim3(EB), 0, c.stream, m_coeff, limbs, c.d_mod,
                      c.d_pc, z, c.log_n, q0_inv);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
   run_dft(c, z, 1, +1);
+  c.begin_launch();
   hipLaunchKernelGGL(decode_gather_kernel, dim3((c.slots + EB - 1) / EB), dim3(EB), 0, c.stream, z, c.d_pow5, scale,
                      d_re, d_im, c.log_n);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
 }
 
 void k_block_layout(Context& c, const double* d_mat, int rows, int cols, int tiling, int c_rep, int s0, int s1,
                     int n_rb, int n_cb, double* d_slots) {
+  c.begin_launch();
   hipLaunchKernelGGL(block_layout_kernel, dim3((s0 * s1 + EB - 1) / EB, n_rb * n_cb), dim3(EB), 0, c.stream, d_mat,
                      rows, cols, tiling, c_rep, s0, s1, n_cb, d_slots);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
 }
 
 }  // namespace hetal

@@ -30,7 +30,7 @@ struct Error : std::runtime_error {
 constexpr int MAX_PRIMES = 32;
 constexpr int MAX_ALPHA = 8;
 constexpr int MAX_K = 8;
-constexpr int MAX_BATCH = 16;
+constexpr int MAX_BATCH = 32;
 
 // Fast basis conversion constants of one digit at one level (ModUp).
 struct ModUpTab {
@@ -98,6 +98,15 @@ struct Tmp {
   operator u64*() const { return p; }
 };
 
+// Kernel classes for the optional per-launch HIP-event timing.
+enum KernelClass { KC_NTT = 0, KC_MODUP, KC_INNER, KC_MODDOWN, KC_COMBINE, KC_RESCALE, KC_ELEMWISE, KC_ENCODE, NUM_KC };
+
+struct TimedLaunch {
+  hipEvent_t start, stop;
+  int cls;
+  double bytes;  // algorithmic HBM bytes of the launch
+};
+
 enum RowTable { ROWS_CT = 0, ROWS_MODUP, ROWS_SPECIAL, ROWS_TOP, ROWS_ALL, ROWS_ALL2, ROWS_EXT, NUM_ROW_TABLES };
 
 struct RowsRef {
@@ -130,6 +139,34 @@ struct Context {
   Pool pool;
   int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
+  // Optional timing: events recorded on `stream` around every kernel launch.
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<TimedLaunch> timed;
+  hipEvent_t pending_start = nullptr;
+  hipEvent_t take_event() {
+    if (ev_free.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+      return e;
+    }
+    hipEvent_t e = ev_free.back();
+    ev_free.pop_back();
+    return e;
+  }
+  void begin_launch() {
+    if (!timing) return;
+    pending_start = take_event();
+    (void)hipEventRecord(pending_start, stream);
+  }
+  void end_launch(int cls, double bytes) {
+    counters[7] += 1;
+    if (!timing) return;
+    hipEvent_t e = take_event();
+    (void)hipEventRecord(e, stream);
+    timed.push_back(TimedLaunch{pending_start, e, cls, bytes});
+  }
+
   RowsRef rows(RowTable t, int level) const {
     return RowsRef{d_rows + row_off[t][level], row_cnt[t][level]};
   }
@@ -138,7 +175,6 @@ struct Context {
   size_t poly_words(int level) const { return (size_t)(level + 1) * n; }
   size_t ct_words(int level) const { return 2 * poly_words(level); }
   size_t key_words() const { return (size_t)dnum * 2 * nprimes * n; }
-  void count_launch(int k = 1) { counters[7] += k; }
 };
 
 void context_init(Context& c, const hetal_params& p, hipStream_t stream);
@@ -156,7 +192,9 @@ struct KsItem {
 };
 
 // Hybrid key switching of `count` polynomials at `level` (NTT form, [l][N] each,
-// in_stride apart; in_stride = 0 with hoisted: one input shared by all items).
+// in_stride apart; in_stride = 0: one input shared by all items, whose ModUp
+// is then computed once -- hoisting, bit-identical because ModUp precedes the
+// automorphism).  count <= MAX_BATCH.
 // out_i = (add0_i gathered by g_i (if add0) + ModDown(sum_j tau_g(ModUp_j(d)) * b_j),
 //          add1_i (if add1) + ModDown(sum_j tau_g(ModUp_j(d)) * a_j)).
 struct KsJob {

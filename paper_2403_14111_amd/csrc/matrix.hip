@@ -13,9 +13,14 @@
 //    dropping moduli; masks are encoded with scale q_level, so CMult + rescale
 //    keeps the scale; a block product sum is relinearised per product and
 //    rescaled once.
-// Every step runs as device kernels; the sequence of rounding operations
-// (key switches, rescales) is fixed by the algorithm, so reordering
-// independent work cannot change a single bit of the result.
+//
+// Schedule on the GPU: the c/2 iterations of the k-loop and all blocks run in
+// lockstep as batches.  Same-key rotations (the CS / RS steps, the B_cplx
+// rotation, the conjugations, every relinearisation) form one key-switch
+// batch each, which reads the key once; the RU / RotLeft rotations of one
+// ciphertext by k = 1 .. c/2-1 share one ModUp (hoisting).  Each ciphertext
+// still goes through exactly the key switches and rescales the algorithm
+// prescribes, so the result is bit-identical to the sequential schedule.
 #include <algorithm>
 #include <vector>
 
@@ -32,55 +37,74 @@ int log2_exact(int x, const char* what) {
   return r;
 }
 
-Cipher col_sum(Context& c, const KeySet& k, MaskCache& mc, Cipher x, int s0, int s1) {
-  const int lg = log2_exact(s1, "s1");
-  for (int m = 0; m < lg; ++m) {
-    Cipher r = rotate(c, k, view(x), 1 << m);
-    x = add(c, view(x), view(r));
-  }
-  Cipher masked = cmult_mask(c, mc, view(x), MASK_FIRST_COL, 0, 0, s0, s1, 1.0);
-  x = rescale(c, view(masked));
-  for (int m = 0; m < lg; ++m) {
-    Cipher r = rotate(c, k, view(x), -(1 << m));
-    x = add(c, view(x), view(r));
-  }
-  return x;
-}
-
-Cipher row_sum(Context& c, const KeySet& k, Cipher x, int s0, int s1) {
-  const int lg = log2_exact(s0, "s0");
-  for (int m = 0; m < lg; ++m) {
-    Cipher r = rotate(c, k, view(x), (1 << m) * s1);
-    x = add(c, view(x), view(r));
-  }
-  return x;
-}
-
-// RL(A, k) (Alg. 2): columns rotated left by k within each row; one level.
-Cipher rot_left_cols(Context& c, const KeySet& k, MaskCache& mc, CtView a, int kk, int s0, int s1) {
-  Cipher a1 = rotate(c, k, a, kk);
-  Cipher a2m = cmult_mask(c, mc, view(a1), MASK_LEFT_COLS, kk, 0, s0, s1, 1.0);
-  Cipher a2 = rescale(c, view(a2m));
-  Cipher a1d = mod_drop(c, view(a1), a2.level);
-  Cipher rest = sub(c, view(a1d), view(a2));
-  Cipher back = rotate(c, k, view(rest), -s1);
-  return add(c, view(a2), view(back));
-}
-
-// PRU(B, k) (Alg. 3): the last k columns move up by one row; one level.
-Cipher partial_rot_up(Context& c, const KeySet& k, MaskCache& mc, CtView b, int kk, int s0, int s1) {
-  Cipher bpm = cmult_mask(c, mc, b, MASK_LEFT_COLS, kk, 0, s0, s1, 1.0);
-  Cipher bp = rescale(c, view(bpm));
-  Cipher bd = mod_drop(c, b, bp.level);
-  Cipher rest = sub(c, view(bd), view(bp));
-  Cipher up = rotate(c, k, view(rest), s1);
-  return add(c, view(bp), view(up));
-}
-
 void check_block_shape(const Context& c, int s0, int s1) {
   if (s0 < 1 || s1 < 1 || (long)s0 * s1 != c.slots) fail(HETAL_E_SHAPE, "s0 * s1 must equal the slot count N/2");
   log2_exact(s0, "s0");
   log2_exact(s1, "s1");
+}
+
+BView one(CtView x) { return BView{x.d, x.level, 1, x.scale, 0}; }
+
+// CS on every item of a batch.
+Batch col_sum(Context& c, const KeySet& k, MaskCache& mc, Batch x, int s0, int s1) {
+  const int lg = log2_exact(s1, "s1");
+  for (int m = 0; m < lg; ++m) {
+    Batch r = b_rotate(c, k, x.v(), {1 << m});
+    x = b_add(c, x.v(), r.v());
+  }
+  Batch masked = b_cmult_masks(c, mc, x.v(), {MaskSpec{MASK_FIRST_COL, 0, 0, s0, s1, 1.0}});
+  x = b_rescale(c, masked.v());
+  for (int m = 0; m < lg; ++m) {
+    Batch r = b_rotate(c, k, x.v(), {-(1 << m)});
+    x = b_add(c, x.v(), r.v());
+  }
+  return x;
+}
+
+// RS on every item of a batch.
+Batch row_sum(Context& c, const KeySet& k, Batch x, int s0, int s1) {
+  const int lg = log2_exact(s0, "s0");
+  for (int m = 0; m < lg; ++m) {
+    Batch r = b_rotate(c, k, x.v(), {(1 << m) * s1});
+    x = b_add(c, x.v(), r.v());
+  }
+  return x;
+}
+
+// Completes RL (Alg. 2) from A1 = Lrot(A, k_i) (item i): A2 = rescale(A1 * D_{k_i}),
+// RL = A2 + Rrot(A1 - A2, s1).  One level.
+Batch rot_left_finish(Context& c, const KeySet& k, MaskCache& mc, const Batch& a1, const std::vector<int>& ks, int s0,
+                      int s1) {
+  std::vector<MaskSpec> masks;
+  for (int kk : ks) masks.push_back(MaskSpec{MASK_LEFT_COLS, kk, 0, s0, s1, 1.0});
+  Batch a2m = b_cmult_masks(c, mc, a1.v(), masks);
+  Batch a2 = b_rescale(c, a2m.v());
+  Batch a1d = b_mod_drop(c, a1.v(), a2.level);
+  Batch rest = b_sub(c, a1d.v(), a2.v());
+  Batch back = b_rotate(c, k, rest.v(), {-s1});
+  return b_add(c, a2.v(), back.v());
+}
+
+// PRU (Alg. 3) of one ciphertext b for k = ks[i]: B' = rescale(b * D_k),
+// PRU = B' + Lrot(b - B', s1).  One level.
+Batch partial_rot_up(Context& c, const KeySet& k, MaskCache& mc, CtView b, const std::vector<int>& ks, int s0, int s1) {
+  const int m = (int)ks.size();
+  std::vector<MaskSpec> masks;
+  for (int kk : ks) masks.push_back(MaskSpec{MASK_LEFT_COLS, kk, 0, s0, s1, 1.0});
+  BView bc = BView{b.d, b.level, m, b.scale, 0};
+  Batch bpm = b_cmult_masks(c, mc, bc, masks);
+  Batch bp = b_rescale(c, bpm.v());
+  Batch bd = b_mod_drop(c, one(b), bp.level);
+  Batch rest = b_sub(c, BView{bd.d, bd.level, m, bd.scale, 0}, bp.v());
+  Batch up = b_rotate(c, k, rest.v(), {s1});
+  return b_add(c, bp.v(), up.v());
+}
+
+// A view at `level`: the input itself, or a copy with the upper limbs dropped (kept in `hold`).
+CtView at_level(Context& c, CtView x, int level, std::vector<Batch>& hold) {
+  if (x.level == level) return x;
+  hold.push_back(b_mod_drop(c, one(x), level));
+  return hold.back().item(0);
 }
 
 }  // namespace
@@ -109,8 +133,19 @@ std::vector<int> required_rot_steps(const Context& c, int op, int cc, int s0) {
   return steps;
 }
 
-std::vector<Cipher> diag_abt(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,
-                             const std::vector<CtView>& Bbar, int cc, int s0, int s1, double t) {
+std::vector<Cipher> to_ciphers(Context& c, const Batch& b) {
+  std::vector<Cipher> out;
+  for (int i = 0; i < b.count; ++i) {
+    Cipher x(c, b.level);
+    HCHECK(hipMemcpyAsync(x.d, b.item(i).d, c.ct_words(b.level) * 8, hipMemcpyDeviceToDevice, c.stream));
+    x.scale = b.scale;
+    out.push_back(std::move(x));
+  }
+  return out;
+}
+
+Batch diag_abt_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,
+                     const std::vector<CtView>& Bbar, int cc, int s0, int s1, double t) {
   check_block_shape(c, s0, s1);
   if (cc < 2 || cc > s0 || s1 % cc || (cc & (cc - 1))) fail(HETAL_E_SHAPE, "need 1 < c <= s0, c a power of two dividing s1");
   const int n_a = (int)A.size(), n_b = (int)Bbar.size();
@@ -123,44 +158,54 @@ std::vector<Cipher> diag_abt(Context& c, const KeySet& k, MaskCache& mc, const s
   for (auto& x : Bbar) lv = std::min(lv, x.level);
   if (lv < 3) fail(HETAL_E_LEVEL, "DiagABT needs three levels");
   const int half = cc / 2;
-  std::vector<std::vector<Cipher>> a(n_a);
+  std::vector<Batch> hold;
+  std::vector<std::vector<CtView>> a(n_a);
   for (int i = 0; i < n_a; ++i)
-    for (int j = 0; j < n_b; ++j) a[i].push_back(mod_drop(c, A[i][j], lv));
-  std::vector<Cipher> bc;
-  for (int j = 0; j < n_b; ++j) {
-    Cipher b = mod_drop(c, Bbar[j], lv);
-    Cipher r = rotate(c, k, view(b), half * s1);
-    Cipher ri = mul_i(c, view(r));
-    bc.push_back(add(c, view(b), view(ri)));
+    for (int j = 0; j < n_b; ++j) a[i].push_back(at_level(c, A[i][j], lv, hold));
+  std::vector<CtView> bv;
+  for (int j = 0; j < n_b; ++j) bv.push_back(at_level(c, Bbar[j], lv, hold));
+  Batch bp = b_pack(c, bv);
+
+  // B_cplx = Bbar + i RU(Bbar, c/2)
+  Batch rb = b_rotate(c, k, bp.v(), {half * s1});
+  Batch rbi = b_mul_i(c, rb.v());
+  Batch bc = b_add(c, bp.v(), rbi.v());
+
+  // RU(B_cplx, k) for k = 1 .. c/2 - 1, hoisted per block
+  std::vector<Batch> bk(n_b);
+  if (half > 1) {
+    std::vector<int> steps;
+    for (int kk = 1; kk < half; ++kk) steps.push_back(kk * s1);
+    for (int j = 0; j < n_b; ++j) bk[j] = b_rotate_hoisted(c, k, bc.item(j), steps);
   }
-  std::vector<Cipher> X(n_a);
-  for (int kk = 0; kk < half; ++kk) {
-    std::vector<Cipher> bk;
-    if (kk > 0)
-      for (int j = 0; j < n_b; ++j) bk.push_back(rotate(c, k, view(bc[j]), kk * s1));
-    for (int i = 0; i < n_a; ++i) {
-      Cipher r;
+
+  // products A_ij * B_kj in the order (i, k, j): sums over j are contiguous groups
+  std::vector<CtView> pa, pb;
+  for (int i = 0; i < n_a; ++i)
+    for (int kk = 0; kk < half; ++kk)
       for (int j = 0; j < n_b; ++j) {
-        Cipher p = hmult(c, k, view(a[i][j]), kk == 0 ? view(bc[j]) : view(bk[j]));
-        r = j == 0 ? std::move(p) : add(c, view(r), view(p));
+        pa.push_back(a[i][j]);
+        pb.push_back(kk == 0 ? bc.item(j) : bk[j].item(kk - 1));
       }
-      r = rescale(c, view(r));
-      r = col_sum(c, k, mc, std::move(r), s0, s1);
-      Cipher rm = cmult_mask(c, mc, view(r), MASK_OFFDIAG_CPLX, kk, cc, s0, s1, t);
-      r = rescale(c, view(rm));
-      X[i] = kk == 0 ? std::move(r) : add(c, view(X[i]), view(r));
-    }
-  }
-  std::vector<Cipher> out;
-  for (int i = 0; i < n_a; ++i) {
-    Cipher cj = conjugate(c, k, view(X[i]));
-    out.push_back(add(c, view(X[i]), view(cj)));
-  }
-  return out;
+  Batch prod = b_hmult(c, k, pa, pb);
+  Batch r = b_sum_groups(c, prod.v(), n_a * half);
+  prod = Batch();
+  r = b_rescale(c, r.v());
+
+  r = col_sum(c, k, mc, std::move(r), s0, s1);
+
+  std::vector<MaskSpec> masks;
+  for (int i = 0; i < n_a; ++i)
+    for (int kk = 0; kk < half; ++kk) masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, kk, cc, s0, s1, t});
+  Batch rm = b_cmult_masks(c, mc, r.v(), masks);
+  r = b_rescale(c, rm.v());
+  Batch x = b_sum_groups(c, r.v(), n_a);
+  Batch xc = b_conj(c, k, x.v());
+  return b_add(c, x.v(), xc.v());
 }
 
-std::vector<Cipher> diag_atb(Context& c, const KeySet& k, MaskCache& mc, const std::vector<CtView>& Abar,
-                             const std::vector<std::vector<CtView>>& B, int cc, int s0, int s1, double t) {
+Batch diag_atb_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<CtView>& Abar,
+                     const std::vector<std::vector<CtView>>& B, int cc, int s0, int s1, double t) {
   check_block_shape(c, s0, s1);
   if (cc < 2 || cc > s1 || s1 % cc || (cc & (cc - 1))) fail(HETAL_E_SHAPE, "need 1 < c, c a power of two dividing s1");
   const int n_a = (int)Abar.size();
@@ -176,63 +221,87 @@ std::vector<Cipher> diag_atb(Context& c, const KeySet& k, MaskCache& mc, const s
   const int lstar = use_pru ? std::min(lA - 1, lB - 1) : std::min(lA - 2, lB);
   if (lstar < 2) fail(HETAL_E_LEVEL, "DiagATB needs more levels");
   const int half = cc / 2;
-  std::vector<Cipher> ac;
-  for (int i = 0; i < n_a; ++i) {
-    Cipher a = mod_drop(c, Abar[i], lA);
-    Cipher rl = rot_left_cols(c, k, mc, view(a), half, s0, s1);
-    Cipher ad = mod_drop(c, view(a), rl.level);
-    Cipher rli = mul_i(c, view(rl));
-    ac.push_back(add(c, view(ad), view(rli)));
-  }
-  std::vector<std::vector<Cipher>> bd(n_a);
+  std::vector<Batch> hold;
+  std::vector<CtView> av;
+  for (int i = 0; i < n_a; ++i) av.push_back(at_level(c, Abar[i], lA, hold));
+  Batch ap = b_pack(c, av);
+  std::vector<std::vector<CtView>> bview(n_a);
   for (int i = 0; i < n_a; ++i)
-    for (int j = 0; j < n_b; ++j) bd[i].push_back(mod_drop(c, B[i][j], lB));
-  std::vector<Cipher> X(n_b);
-  for (int kk = 0; kk < half; ++kk) {
-    std::vector<Cipher> ak;
-    std::vector<std::vector<Cipher>> bk(n_a);
-    for (int i = 0; i < n_a; ++i) {
-      if (use_pru) {
-        if (kk == 0) ak.push_back(mod_drop(c, view(ac[i]), lstar));
-        else {
-          Cipher r = rotate(c, k, view(ac[i]), kk);
-          ak.push_back(mod_drop(c, view(r), lstar));
-        }
-        for (int j = 0; j < n_b; ++j) {
-          if (kk == 0) bk[i].push_back(mod_drop(c, view(bd[i][j]), lstar));
-          else {
-            Cipher p = partial_rot_up(c, k, mc, view(bd[i][j]), kk, s0, s1);
-            bk[i].push_back(mod_drop(c, view(p), lstar));
-          }
-        }
-      } else {
-        if (kk == 0) ak.push_back(mod_drop(c, view(ac[i]), lstar));
-        else {
-          Cipher r = rot_left_cols(c, k, mc, view(ac[i]), kk, s0, s1);
-          ak.push_back(mod_drop(c, view(r), lstar));
-        }
-        for (int j = 0; j < n_b; ++j) bk[i].push_back(mod_drop(c, view(bd[i][j]), lstar));
-      }
+    for (int j = 0; j < n_b; ++j) bview[i].push_back(at_level(c, B[i][j], lB, hold));
+
+  // A_cplx = Abar + i RL(Abar, c/2)
+  Batch a1 = b_rotate(c, k, ap.v(), {half});
+  Batch rl = rot_left_finish(c, k, mc, a1, std::vector<int>(n_a, half), s0, s1);
+  Batch apd = b_mod_drop(c, ap.v(), rl.level);
+  Batch rli = b_mul_i(c, rl.v());
+  Batch ac = b_add(c, apd.v(), rli.v());
+  a1 = Batch();
+
+  std::vector<int> ks, steps;
+  for (int kk = 1; kk < half; ++kk) {
+    ks.push_back(kk);
+    steps.push_back(kk);
+  }
+  // A_k[i][kk] and B_k[i][j][kk] at lstar
+  std::vector<std::vector<CtView>> ak(n_a, std::vector<CtView>(half));
+  std::vector<std::vector<std::vector<CtView>>> bk(n_a, std::vector<std::vector<CtView>>(n_b, std::vector<CtView>(half)));
+  for (int i = 0; i < n_a; ++i) {
+    ak[i][0] = at_level(c, ac.item(i), lstar, hold);
+    if (half > 1) {
+      Batch rk = b_rotate_hoisted(c, k, ac.item(i), steps);
+      if (!use_pru) rk = rot_left_finish(c, k, mc, rk, ks, s0, s1);
+      hold.push_back(rk.level == lstar ? std::move(rk) : b_mod_drop(c, rk.v(), lstar));
+      for (int kk = 1; kk < half; ++kk) ak[i][kk] = hold.back().item(kk - 1);
     }
     for (int j = 0; j < n_b; ++j) {
-      Cipher r;
-      for (int i = 0; i < n_a; ++i) {
-        Cipher p = hmult(c, k, view(ak[i]), view(bk[i][j]));
-        r = i == 0 ? std::move(p) : add(c, view(r), view(p));
+      CtView bd = at_level(c, bview[i][j], lstar, hold);
+      bk[i][j][0] = bd;
+      if (half > 1) {
+        if (use_pru) {
+          Batch pr = partial_rot_up(c, k, mc, bview[i][j], ks, s0, s1);
+          hold.push_back(pr.level == lstar ? std::move(pr) : b_mod_drop(c, pr.v(), lstar));
+          for (int kk = 1; kk < half; ++kk) bk[i][j][kk] = hold.back().item(kk - 1);
+        } else {
+          for (int kk = 1; kk < half; ++kk) bk[i][j][kk] = bd;
+        }
       }
-      r = rescale(c, view(r));
-      r = row_sum(c, k, std::move(r), s0, s1);
-      Cipher rm = cmult_mask(c, mc, view(r), MASK_OFFDIAG_CPLX, -kk, cc, s0, s1, t);
-      r = rescale(c, view(rm));
-      X[j] = kk == 0 ? std::move(r) : add(c, view(X[j]), view(r));
     }
   }
-  std::vector<Cipher> out;
-  for (int j = 0; j < n_b; ++j) {
-    Cipher cj = conjugate(c, k, view(X[j]));
-    out.push_back(add(c, view(X[j]), view(cj)));
-  }
-  return out;
+
+  // products in the order (j, k, i): sums over i are contiguous groups
+  std::vector<CtView> pa, pb;
+  for (int j = 0; j < n_b; ++j)
+    for (int kk = 0; kk < half; ++kk)
+      for (int i = 0; i < n_a; ++i) {
+        pa.push_back(ak[i][kk]);
+        pb.push_back(bk[i][j][kk]);
+      }
+  Batch prod = b_hmult(c, k, pa, pb);
+  Batch r = b_sum_groups(c, prod.v(), n_b * half);
+  prod = Batch();
+  hold.clear();
+  r = b_rescale(c, r.v());
+
+  r = row_sum(c, k, std::move(r), s0, s1);
+
+  std::vector<MaskSpec> masks;
+  for (int j = 0; j < n_b; ++j)
+    for (int kk = 0; kk < half; ++kk) masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, -kk, cc, s0, s1, t});
+  Batch rm = b_cmult_masks(c, mc, r.v(), masks);
+  r = b_rescale(c, rm.v());
+  Batch x = b_sum_groups(c, r.v(), n_b);
+  Batch xc = b_conj(c, k, x.v());
+  return b_add(c, x.v(), xc.v());
+}
+
+std::vector<Cipher> diag_abt(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,
+                             const std::vector<CtView>& Bbar, int cc, int s0, int s1, double t) {
+  return to_ciphers(c, diag_abt_batch(c, k, mc, A, Bbar, cc, s0, s1, t));
+}
+
+std::vector<Cipher> diag_atb(Context& c, const KeySet& k, MaskCache& mc, const std::vector<CtView>& Abar,
+                             const std::vector<std::vector<CtView>>& B, int cc, int s0, int s1, double t) {
+  return to_ciphers(c, diag_atb_batch(c, k, mc, Abar, B, cc, s0, s1, t));
 }
 
 }  // namespace hetal

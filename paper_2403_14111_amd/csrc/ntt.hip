@@ -202,6 +202,7 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   const int nsub = c.n / sub;
   dim3 grid(nsub / per_wg, rows.count, batch), block(NTT_THREADS);
   const ulonglong2* tw = INV ? c.d_tw_inv : c.d_tw_fwd;
+  c.begin_launch();
   switch (L) {
 #define HETAL_NTT_CASE(LL)                                                                                      \
   case LL:                                                                                                    \
@@ -217,7 +218,7 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
     default:
       fail(HETAL_E_PARAMS, "unsupported NTT pass size");
   }
-  c.count_launch();
+  c.end_launch(KC_NTT, 16.0 * c.n * rows.count * batch);  // every residue read and written once
 }
 
 }  // namespace

@@ -222,8 +222,9 @@ const u64* mask_pt(Context& c, MaskCache& cache, MaskKind kind, int k, int cc, i
   Tmp vals(c.pool, 2 * (size_t)s);
   double* re = reinterpret_cast<double*>(vals.p);
   double* im = re + s;
+  c.begin_launch();
   hipLaunchKernelGGL(mask_kernel, dim3((s + 255) / 256), dim3(256), 0, c.stream, re, im, (int)kind, k, cc, s0, s1, t);
-  c.count_launch();
+  c.end_launch(KC_ENCODE, 0.0);
   u64* pt = c.pool.get(c.poly_words(level));
   encode_slots(c, re, im, 1, 0, level, (double)c.primes[level], pt, 0);
   cache.pts[key] = pt;

@@ -97,3 +97,74 @@ void encode_slots(Context& c, const double* d_re, const double* d_im, int count,
                   double scale, u64* out, size_t out_stride);
 
 }  // namespace hetal
+
+namespace hetal {
+
+// `count` ciphertexts at one level and scale, item i at d + i * stride words.
+struct BView {
+  const u64* d;
+  int level;
+  int count;
+  double scale;
+  size_t stride;
+  CtView item(int i) const { return CtView{d + (size_t)i * stride, level, scale}; }
+  BView sub(int first, int n) const { return BView{d + (size_t)first * stride, level, n, scale, stride}; }
+};
+
+// A packed batch in one pool buffer (move-only).
+struct Batch {
+  Context* c = nullptr;
+  u64* d = nullptr;
+  int level = -1;
+  int count = 0;
+  double scale = 0.0;
+
+  Batch() = default;
+  Batch(Context& ctx, int lv, int n) : c(&ctx), d(ctx.pool.get(ctx.ct_words(lv) * (size_t)n)), level(lv), count(n) {}
+  ~Batch() {
+    if (d) c->pool.put(d);
+  }
+  Batch(Batch&& o) noexcept : c(o.c), d(o.d), level(o.level), count(o.count), scale(o.scale) { o.d = nullptr; }
+  Batch& operator=(Batch&& o) noexcept {
+    if (this != &o) {
+      if (d) c->pool.put(d);
+      c = o.c;
+      d = o.d;
+      level = o.level;
+      count = o.count;
+      scale = o.scale;
+      o.d = nullptr;
+    }
+    return *this;
+  }
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
+  BView v() const { return BView{d, level, count, scale, c->ct_words(level)}; }
+  CtView item(int i) const { return v().item(i); }
+};
+
+struct MaskSpec {
+  MaskKind kind;
+  int k, cc, s0, s1;
+  double t;
+};
+
+Batch b_pack(Context& c, const std::vector<CtView>& items);
+Batch b_add(Context& c, BView a, BView b);
+Batch b_sub(Context& c, BView a, BView b);
+Batch b_mul_i(Context& c, BView a);
+Batch b_mod_drop(Context& c, BView a, int level);
+Batch b_rescale(Context& c, BView a);
+// Item i rotated left by steps[i] (steps.size() == 1: the same step for all).
+Batch b_rotate(Context& c, const KeySet& k, BView a, const std::vector<int>& steps);
+// One ciphertext rotated by each step, sharing one ModUp (hoisting).
+Batch b_rotate_hoisted(Context& c, const KeySet& k, CtView a, const std::vector<int>& steps);
+Batch b_conj(Context& c, const KeySet& k, BView a);
+// Mult (tensor + relinearisation) of the pairs (a[i], b[i]), all at one level.
+Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
+// CMult of item i by mask masks[i] (or masks[0] for all), each encoded at the batch level with scale q_level.
+Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks);
+// out[g] = sum over t < per of a[g * per + t], per = a.count / groups.
+Batch b_sum_groups(Context& c, BView a, int groups);
+
+}  // namespace hetal

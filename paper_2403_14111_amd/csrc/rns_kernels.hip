@@ -18,8 +18,9 @@ inline dim3 grid_for(const Context& c, int y, int z) { return dim3((unsigned)(c.
 // other row of the extended basis q_0..q_l, p_0..p_{K-1} receives the fast
 // basis conversion of the digit's coefficient-form residues
 //   sum_i [x_i (D/d_i)^-1]_{d_i} (D/d_i) mod t    (128-bit lazy sum, one Barrett).
-__global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef, const u64* __restrict__ ntt_in,
-                                                    size_t in_stride, u64* __restrict__ dt, size_t dt_stride,
+__global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef, size_t coef_stride,
+                                                    const u64* __restrict__ ntt_in, size_t in_stride,
+                                                    u64* __restrict__ dt, size_t dt_stride,
                                                     const ModUpTab* __restrict__ tabs, const ModInfo* __restrict__ mods,
                                                     int log_n, int level, int num_q, int num_p) {
   const int n = 1 << log_n;
@@ -28,7 +29,7 @@ __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int jd = blockIdx.y;
   const ModUpTab& tb = tabs[jd];
-  const u64* __restrict__ cf = coef + blockIdx.z * in_stride;
+  const u64* __restrict__ cf = coef + blockIdx.z * coef_stride;
   const u64* __restrict__ ni = ntt_in + blockIdx.z * in_stride;
   u64* __restrict__ out = dt + blockIdx.z * dt_stride + (size_t)jd * ext * n;
   u64 y[MAX_ALPHA];
@@ -89,6 +90,48 @@ __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restric
   u64* __restrict__ o = acc + item * acc_stride;
   o[(size_t)r * n + k] = reduce128(sb, m);
   o[(size_t)(ext + r) * n + k] = reduce128(sa, m);
+}
+
+// Same, for `count` items that share one key and Galois element: the key
+// words are loaded once per coefficient and reused for every item.
+__global__ void __launch_bounds__(TPB) inner_product_shared_kernel(const u64* __restrict__ dt, size_t dt_stride,
+                                                                   u64* __restrict__ acc, size_t acc_stride,
+                                                                   const u64* __restrict__ key, u32 g, int count,
+                                                                   const ModInfo* __restrict__ mods, int log_n,
+                                                                   int level, int num_q, int num_p, int nprimes,
+                                                                   int beta) {
+  constexpr int MAXB = 8;  // digits held in registers (dnum <= 8 for this kernel)
+  const int n = 1 << log_n;
+  const int l = level + 1;
+  const int ext = l + num_p;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int r = blockIdx.y;
+  const int t = r < l ? r : num_q + (r - l);
+  const u32 src = g == 1 ? (u32)k : galois_source((u32)k, g, log_n);
+  u64 kb[MAXB], ka[MAXB];
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j) {
+    if (j < beta) {
+      kb[j] = key[((size_t)(2 * j) * nprimes + t) * n + k];
+      ka[j] = key[((size_t)(2 * j + 1) * nprimes + t) * n + k];
+    }
+  }
+  const ModInfo m = mods[t];
+  for (int item = 0; item < count; ++item) {
+    const u64* __restrict__ d = dt + item * dt_stride + (size_t)r * n;
+    U128 sb = {0, 0}, sa = {0, 0};
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) {
+      if (j < beta) {
+        const u64 x = d[(size_t)j * ext * n + src];
+        acc_wide(sb, mul_wide(x, kb[j]));
+        acc_wide(sa, mul_wide(x, ka[j]));
+      }
+    }
+    u64* __restrict__ o = acc + item * acc_stride;
+    o[(size_t)r * n + k] = reduce128(sb, m);
+    o[(size_t)(ext + r) * n + k] = reduce128(sa, m);
+  }
 }
 
 // ---------------------------------------------------------------- ModDown
@@ -353,41 +396,59 @@ void key_switch(Context& c, const KsJob& job) {
   const size_t acc_words = 2 * (size_t)ext * n;
   const size_t conv_words = 2 * poly;
 
-  // ModUp reads the coefficient-form copy and the NTT-form input at one stride.
-  if (!hoisted && m > 1 && job.in_stride != poly)
-    fail(HETAL_E_INVALID_ARG, "batched key switch inputs must be packed polynomial after polynomial");
-
-  // 1. coefficient form of the input
+  // 1. coefficient form of the input(s)
   Tmp coef(c.pool, m_in * poly);
-  HCHECK(hipMemcpyAsync(coef.p, job.in, m_in * poly * 8, hipMemcpyDeviceToDevice, c.stream));
+  if (m_in == 1 || job.in_stride == poly) {
+    HCHECK(hipMemcpyAsync(coef.p, job.in, m_in * poly * 8, hipMemcpyDeviceToDevice, c.stream));
+  } else {
+    HCHECK(hipMemcpy2DAsync(coef.p, poly * 8, job.in, job.in_stride * 8, poly * 8, m_in, hipMemcpyDeviceToDevice,
+                            c.stream));
+  }
   RowsRef ct_rows = c.rows(ROWS_CT, level);
   ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l});
 
   // 2. ModUp of every digit, then the NTT of the converted rows
   Tmp dt(c.pool, m_in * dt_words);
-  hipLaunchKernelGGL(modup_kernel, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, job.in, poly, dt.p,
-                     dt_words, c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level, c.num_q, c.num_p);
-  c.count_launch();
+  c.begin_launch();
+  hipLaunchKernelGGL(modup_kernel, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, poly, job.in,
+                     job.in_stride, dt.p, dt_words, c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level,
+                     c.num_q, c.num_p);
+  // reads: each digit's coefficient-form and NTT-form limbs (2l rows in all); writes beta * ext rows
+  c.end_launch(KC_MODUP, 8.0 * n * m_in * (2.0 * l + (double)beta * ext));
   ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level));
 
   // 3. inner product with the keys, automorphism applied on the loads
   Tmp acc(c.pool, m * acc_words);
-  IpArgs ip;
-  for (int i = 0; i < MAX_BATCH; ++i) {
-    ip.key[i] = i < m ? job.item[i].key : nullptr;
-    ip.g[i] = i < m ? job.item[i].g : 1;
+  bool shared = !hoisted && beta <= 8;
+  for (int i = 1; i < m && shared; ++i) shared = job.item[i].key == job.item[0].key && job.item[i].g == job.item[0].g;
+  if (shared) {
+    c.begin_launch();
+    hipLaunchKernelGGL(inner_product_shared_kernel, grid_for(c, ext, 1), dim3(TPB), 0, c.stream, dt.p, dt_words, acc.p,
+                       acc_words, job.item[0].key, job.item[0].g, m, c.d_mod, c.log_n, level, c.num_q, c.num_p,
+                       c.nprimes, beta);
+    // reads: the extended digits of every item and 2 beta ext key rows once; writes 2 ext rows per item
+    c.end_launch(KC_INNER, 8.0 * n * ((double)m * beta * ext + 2.0 * beta * ext + (double)m * 2.0 * ext));
+  } else {
+    IpArgs ip;
+    for (int i = 0; i < MAX_BATCH; ++i) {
+      ip.key[i] = i < m ? job.item[i].key : nullptr;
+      ip.g[i] = i < m ? job.item[i].g : 1;
+    }
+    c.begin_launch();
+    hipLaunchKernelGGL(inner_product_kernel, grid_for(c, ext, m), dim3(TPB), 0, c.stream, dt.p,
+                       hoisted ? (size_t)0 : dt_words, acc.p, acc_words, ip, c.d_mod, c.log_n, level, c.num_q,
+                       c.num_p, c.nprimes, beta);
+    // reads: the extended digits (once per input) and 2 beta ext key rows per item; writes 2 ext rows per item
+    c.end_launch(KC_INNER, 8.0 * n * ((double)m_in * beta * ext + (double)m * (2.0 * beta * ext + 2.0 * ext)));
   }
-  hipLaunchKernelGGL(inner_product_kernel, grid_for(c, ext, m), dim3(TPB), 0, c.stream, dt.p,
-                     hoisted ? (size_t)0 : dt_words, acc.p, acc_words, ip, c.d_mod, c.log_n, level, c.num_q, c.num_p,
-                     c.nprimes, beta);
-  c.count_launch();
 
   // 4. ModDown: special rows to coefficient form, centred conversion, NTT, combine
   ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level));
   Tmp conv(c.pool, m * conv_words);
+  c.begin_launch();
   hipLaunchKernelGGL(moddown_conv_kernel, grid_for(c, 2, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
                      conv_words, c.d_moddown, c.d_mod, c.log_n, level, c.num_q, c.num_p);
-  c.count_launch();
+  c.end_launch(KC_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
   ntt_forward(c, conv, conv_words, m, ct_rows);
   CombineArgs ca;
   ca.add0 = job.add0;
@@ -396,88 +457,107 @@ void key_switch(Context& c, const KsJob& job) {
   ca.add1_stride = job.add1_stride;
   ca.gather = job.add0_galois ? 1 : 0;
   for (int i = 0; i < MAX_BATCH; ++i) ca.g[i] = i < m ? job.item[i].g : 1;
+  c.begin_launch();
   hipLaunchKernelGGL(moddown_combine_kernel, grid_for(c, l, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
                      conv_words, job.out, job.out_stride, ca, c.d_moddown, c.d_mod, c.log_n, level, c.num_p);
-  c.count_launch();
+  c.end_launch(KC_COMBINE, 8.0 * n * m * (4.0 * l + (job.add0 ? l : 0) + (job.add1 ? l : 0) + 2.0 * l));
   c.counters[5] += m;
 }
 
 void k_add(Context& c, const u64* a, const u64* b, u64* out, int rows, int period) {
+  c.begin_launch();
   hipLaunchKernelGGL(add_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n, period, 0);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 24.0 * c.n * rows);
 }
 
 void k_sub(Context& c, const u64* a, const u64* b, u64* out, int rows, int period) {
+  c.begin_launch();
   hipLaunchKernelGGL(add_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n, period, 1);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 24.0 * c.n * rows);
 }
 
 void k_mul_rows(Context& c, const u64* a, const u64* b, u64* out, int rows, int period, int b_period) {
+  c.begin_launch();
   hipLaunchKernelGGL(mul_rows_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n,
                      period, b_period);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 24.0 * c.n * rows);
 }
 
 void k_mul_i(Context& c, const u64* a, u64* out, int rows, int period) {
+  c.begin_launch();
   hipLaunchKernelGGL(mul_i_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, out, c.d_mod, c.d_pc, c.log_n,
                      period);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 16.0 * c.n * rows);
 }
 
 void k_galois(Context& c, const u64* a, u64* out, int rows, int period, u32 g) {
   (void)period;
+  c.begin_launch();
   hipLaunchKernelGGL(galois_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, out, c.log_n, g);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 16.0 * c.n * rows);
 }
 
 void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int level) {
+  c.begin_launch();
   hipLaunchKernelGGL(tensor_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, a, b, d01, d2, c.d_mod, c.log_n,
                      level);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 8.0 * c.n * (level + 1) * 7);
 }
 
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
   const size_t n = c.n;
   Tmp top(c.pool, (size_t)batch * 2 * n);
-  for (int b = 0; b < batch; ++b)
-    for (int p = 0; p < 2; ++p)
-      HCHECK(hipMemcpyAsync(top.p + ((size_t)b * 2 + p) * n, in + b * in_stride + ((size_t)p * (level + 1) + level) * n,
-                            n * 8, hipMemcpyDeviceToDevice, c.stream));
+  for (int p = 0; p < 2; ++p) {
+    const u64* src = in + ((size_t)p * (level + 1) + level) * n;
+    if (batch == 1) {
+      HCHECK(hipMemcpyAsync(top.p + p * n, src, n * 8, hipMemcpyDeviceToDevice, c.stream));
+    } else {
+      if (in_stride < n) fail(HETAL_E_INVALID_ARG, "rescale of a broadcast batch");
+      HCHECK(hipMemcpy2DAsync(top.p + p * n, 2 * n * 8, src, in_stride * 8, n * 8, batch, hipMemcpyDeviceToDevice,
+                              c.stream));
+    }
+  }
   ntt_inverse(c, top, 2 * n, batch, c.rows(ROWS_TOP, level));
   Tmp spread(c.pool, (size_t)batch * 2 * level * n);
+  c.begin_launch();
   hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, batch), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
                      2 * (size_t)level * n, c.d_mod, c.log_n, level);
-  c.count_launch();
+  c.end_launch(KC_RESCALE, 8.0 * n * batch * (2.0 + 2.0 * level));
   ntt_forward(c, spread, 2 * (size_t)level * n, batch, c.rows(ROWS_CT, level - 1));
+  c.begin_launch();
   hipLaunchKernelGGL(rescale_combine_kernel, grid_for(c, 2 * level, batch), dim3(TPB), 0, c.stream, in, in_stride,
                      spread.p, 2 * (size_t)level * n, out, out_stride, c.d_rescale + level, c.d_mod, c.log_n, level);
-  c.count_launch();
+  c.end_launch(KC_RESCALE, 8.0 * n * batch * 6.0 * level);
   c.counters[4] += batch;
 }
 
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
                      size_t out_stride) {
+  c.begin_launch();
   hipLaunchKernelGGL(reduce_signed_kernel, grid_for(c, rows.count, batch), dim3(TPB), 0, c.stream, coeffs,
                      coeff_stride, out, out_stride, rows.d, c.d_mod, c.log_n);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 8.0 * c.n * (double)rows.count * batch);
 }
 
 void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level) {
+  c.begin_launch();
   hipLaunchKernelGGL(encrypt_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, a_ntt, e_ntt, m, s, ct, c.d_mod,
                      c.log_n, level);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 40.0 * c.n * (level + 1));
 }
 
 void k_decrypt(Context& c, const u64* ct, const u64* s, u64* m, int level) {
+  c.begin_launch();
   hipLaunchKernelGGL(decrypt_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, ct, s, m, c.d_mod, c.log_n,
                      level);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 32.0 * c.n * (level + 1));
 }
 
 void k_keygen(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* s, const u64* sp, u64* key) {
+  c.begin_launch();
   hipLaunchKernelGGL(keygen_kernel, grid_for(c, c.nprimes, c.dnum), dim3(TPB), 0, c.stream, a_ntt, e_ntt, s, sp, key,
                      c.d_mod, c.d_pc, c.log_n, c.nprimes, c.num_q, c.alpha);
-  c.count_launch();
+  c.end_launch(KC_ELEMWISE, 48.0 * c.n * c.nprimes * c.dnum);
 }
 
 }  // namespace hetal
