@@ -174,7 +174,8 @@ Batch b_rescale(Context& c, BView a) {
 }
 
 static void run_rotations(Context& c, const KeySet& k, const u64* in0, size_t in_stride, int count, bool hoisted,
-                          const std::vector<u32>& gal, int level, u64* out) {
+                          const std::vector<u32>& gal, int level, u64* out, const u64* addx = nullptr,
+                          size_t addx_stride = 0) {
   const size_t poly = c.poly_words(level), w = c.ct_words(level);
   for (int first = 0; first < count; first += MAX_BATCH) {
     const int m = std::min(MAX_BATCH, count - first);
@@ -194,6 +195,10 @@ static void run_rotations(Context& c, const KeySet& k, const u64* in0, size_t in
     job.add0 = hoisted ? in0 : in0 + (size_t)first * in_stride;
     job.add0_stride = hoisted ? 0 : in_stride;
     job.add0_galois = true;
+    if (addx) {
+      job.addx = addx + (size_t)first * addx_stride;
+      job.addx_stride = addx_stride;
+    }
     key_switch(c, job);
   }
 }
@@ -208,6 +213,28 @@ Batch b_rotate(Context& c, const KeySet& k, BView a, const std::vector<int>& ste
   run_rotations(c, k, a.d, a.stride, a.count, false, gal, a.level, o.d);
   o.scale = a.scale;
   c.counters[0] += a.count;
+  return o;
+}
+
+Batch b_rotate_add(Context& c, const KeySet& k, BView a, int step, const BView* addend) {
+  const u32 g = galois_rot(c, step);
+  if (g == 1) fail(HETAL_E_INVALID_ARG, "identity rotation inside a batch");
+  BView x = addend ? *addend : a;
+  if (x.level != a.level || x.count != a.count) fail(HETAL_E_LEVEL, "addend batch differs in level or count");
+  if (std::abs(x.scale - a.scale) > 1e-9 * std::abs(a.scale)) fail(HETAL_E_SCALE, "addend with a different scale");
+  Batch o(c, a.level, a.count);
+  run_rotations(c, k, a.d, a.stride, a.count, false, std::vector<u32>(a.count, g), a.level, o.d, x.d, x.stride);
+  o.scale = a.scale;
+  c.counters[0] += a.count;
+  return o;
+}
+
+Batch b_conj_add(Context& c, const KeySet& k, BView a) {
+  Batch o(c, a.level, a.count);
+  run_rotations(c, k, a.d, a.stride, a.count, false, std::vector<u32>(a.count, galois_conj(c)), a.level, o.d, a.d,
+                a.stride);
+  o.scale = a.scale;
+  c.counters[1] += a.count;
   return o;
 }
 

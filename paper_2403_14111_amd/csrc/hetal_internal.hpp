@@ -181,16 +181,26 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream);
 void context_free(Context& c);
 
 // ---------------------------------------------------------------- kernels
+// Optional separate input of a transform: row r of item b is read from
+// p + b * batch_stride + (r * row_mul + row_add) * N (the output stays at base).
+struct NttSrc {
+  const u64* p = nullptr;
+  size_t batch_stride = 0;
+  int row_mul = 1, row_add = 0;
+};
+
 // NTT over `rows` (row index inside a batch item, prime index) of `batch`
 // items spaced batch_stride words apart.  Input and output reduced to [0, q).
-void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows);
-void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows);
+void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{});
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{});
 
 struct KsItem {
   const u64* key;  // [dnum][2][nprimes][N]
   u32 g;           // Galois element (1: none)
 };
 
+// The input polynomials must stay untouched until the switch is done (the
+// digits' own rows are read from them by the inner product).
 // Hybrid key switching of `count` polynomials at `level` (NTT form, [l][N] each,
 // in_stride apart; in_stride = 0: one input shared by all items, whose ModUp
 // is then computed once -- hoisting, bit-identical because ModUp precedes the
@@ -210,6 +220,8 @@ struct KsJob {
   bool add0_galois = false;
   const u64* add1 = nullptr;
   size_t add1_stride = 0;
+  const u64* addx = nullptr;  // optional: a ciphertext added to the result (x + Lrot(x))
+  size_t addx_stride = 0;
 };
 void key_switch(Context& c, const KsJob& job);
 

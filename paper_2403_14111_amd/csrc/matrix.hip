@@ -48,26 +48,17 @@ BView one(CtView x) { return BView{x.d, x.level, 1, x.scale, 0}; }
 // CS on every item of a batch.
 Batch col_sum(Context& c, const KeySet& k, MaskCache& mc, Batch x, int s0, int s1) {
   const int lg = log2_exact(s1, "s1");
-  for (int m = 0; m < lg; ++m) {
-    Batch r = b_rotate(c, k, x.v(), {1 << m});
-    x = b_add(c, x.v(), r.v());
-  }
+  for (int m = 0; m < lg; ++m) x = b_rotate_add(c, k, x.v(), 1 << m);
   Batch masked = b_cmult_masks(c, mc, x.v(), {MaskSpec{MASK_FIRST_COL, 0, 0, s0, s1, 1.0}});
   x = b_rescale(c, masked.v());
-  for (int m = 0; m < lg; ++m) {
-    Batch r = b_rotate(c, k, x.v(), {-(1 << m)});
-    x = b_add(c, x.v(), r.v());
-  }
+  for (int m = 0; m < lg; ++m) x = b_rotate_add(c, k, x.v(), -(1 << m));
   return x;
 }
 
 // RS on every item of a batch.
 Batch row_sum(Context& c, const KeySet& k, Batch x, int s0, int s1) {
   const int lg = log2_exact(s0, "s0");
-  for (int m = 0; m < lg; ++m) {
-    Batch r = b_rotate(c, k, x.v(), {(1 << m) * s1});
-    x = b_add(c, x.v(), r.v());
-  }
+  for (int m = 0; m < lg; ++m) x = b_rotate_add(c, k, x.v(), (1 << m) * s1);
   return x;
 }
 
@@ -81,8 +72,8 @@ Batch rot_left_finish(Context& c, const KeySet& k, MaskCache& mc, const Batch& a
   Batch a2 = b_rescale(c, a2m.v());
   Batch a1d = b_mod_drop(c, a1.v(), a2.level);
   Batch rest = b_sub(c, a1d.v(), a2.v());
-  Batch back = b_rotate(c, k, rest.v(), {-s1});
-  return b_add(c, a2.v(), back.v());
+  BView a2v = a2.v();
+  return b_rotate_add(c, k, rest.v(), -s1, &a2v);
 }
 
 // PRU (Alg. 3) of one ciphertext b for k = ks[i]: B' = rescale(b * D_k),
@@ -96,8 +87,8 @@ Batch partial_rot_up(Context& c, const KeySet& k, MaskCache& mc, CtView b, const
   Batch bp = b_rescale(c, bpm.v());
   Batch bd = b_mod_drop(c, one(b), bp.level);
   Batch rest = b_sub(c, BView{bd.d, bd.level, m, bd.scale, 0}, bp.v());
-  Batch up = b_rotate(c, k, rest.v(), {s1});
-  return b_add(c, bp.v(), up.v());
+  BView bpv = bp.v();
+  return b_rotate_add(c, k, rest.v(), s1, &bpv);
 }
 
 // A view at `level`: the input itself, or a copy with the upper limbs dropped (kept in `hold`).
@@ -200,8 +191,7 @@ Batch diag_abt_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vect
   Batch rm = b_cmult_masks(c, mc, r.v(), masks);
   r = b_rescale(c, rm.v());
   Batch x = b_sum_groups(c, r.v(), n_a);
-  Batch xc = b_conj(c, k, x.v());
-  return b_add(c, x.v(), xc.v());
+  return b_conj_add(c, k, x.v());
 }
 
 Batch diag_atb_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<CtView>& Abar,
@@ -290,8 +280,7 @@ Batch diag_atb_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vect
   Batch rm = b_cmult_masks(c, mc, r.v(), masks);
   r = b_rescale(c, rm.v());
   Batch x = b_sum_groups(c, r.v(), n_b);
-  Batch xc = b_conj(c, k, x.v());
-  return b_add(c, x.v(), xc.v());
+  return b_conj_add(c, k, x.v());
 }
 
 std::vector<Cipher> diag_abt(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,

@@ -29,12 +29,37 @@ struct U128 {
   u64 lo, hi;
 };
 
-__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) { return __umul64hi(a, b); }
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+
+// High 64 bits of a * b, from 32-bit halves:
+//   x = a0 b1 + hi(a0 b0), y = a1 b0 + lo(x), hi = a1 b1 + hi(x) + hi(y)
+// (each partial sum fits in 64 bits; one v_mul_hi_u32, three v_mad_u64_u32).
+__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) {
+  const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+  const u64 x = (u64)a0 * b1 + __umulhi(a0, b0);
+  const u64 y = (u64)a1 * b0 + lo32(x);
+  return (u64)a1 * b1 + ((u64)hi32(x) + hi32(y));
+}
+
+// floor(a * b / 2^64) - e with e in {0, 1, 2}: the high word without the
+// carries out of the low partial products (a1 b1 + hi(a0 b1) + hi(a1 b0)).
+__device__ __forceinline__ u64 mulhi64_lazy(u64 a, u64 b) {
+  const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+  return (u64)a1 * b1 + ((u64)__umulhi(a0, b1) + __umulhi(a1, b0));
+}
+
+// Low 64 bits of a * b: a0 b0 + ((a0 b1 + a1 b0) mod 2^32) 2^32.
+__device__ __forceinline__ u64 mullo64(u64 a, u64 b) {
+  const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+  const u32 cross = a0 * b1 + a1 * b0;
+  return (u64)a0 * b0 + ((u64)cross << 32);
+}
 
 __device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
   U128 r;
-  r.lo = a * b;
-  r.hi = __umul64hi(a, b);
+  r.lo = mullo64(a, b);
+  r.hi = mulhi64(a, b);
   return r;
 }
 
@@ -46,8 +71,15 @@ __device__ __forceinline__ void acc_wide(U128& acc, U128 x) {
 
 // a*w mod q lazily: result in [0, 2q) for any a < 2^64.
 __device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 wp, u64 q) {
-  u64 h = __umul64hi(a, wp);
-  return a * w - h * q;
+  const u64 h = mulhi64(a, wp);
+  return mullo64(a, w) - mullo64(h, q);
+}
+
+// a*w mod q, lazier: with the quotient estimate of mulhi64_lazy (at most 3
+// below floor(a w / q)) the result lies in [0, 4q), for any a < 2^64.
+__device__ __forceinline__ u64 mul_shoup_lazy4(u64 a, u64 w, u64 wp, u64 q) {
+  const u64 h = mulhi64_lazy(a, wp);
+  return mullo64(a, w) - mullo64(h, q);
 }
 
 __device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
@@ -55,13 +87,13 @@ __device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
 __device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 wp, u64 q) { return csub(mul_shoup_lazy(a, w, wp, q), q); }
 
 // x mod q for x < 2^64, through Shoup multiplication by 1.
-__device__ __forceinline__ u64 reduce64(u64 x, const ModInfo& m) { return csub(x - __umul64hi(x, m.one_sh) * m.q, m.q); }
+__device__ __forceinline__ u64 reduce64(u64 x, const ModInfo& m) { return csub(x - mullo64(mulhi64(x, m.one_sh), m.q), m.q); }
 
 // x mod q for x < 2^(b+64).
 __device__ __forceinline__ u64 reduce128(U128 x, const ModInfo& m) {
   u64 t = (x.hi << (64 - m.b)) | (x.lo >> m.b);
-  u64 qh = __umul64hi(t, m.mu);
-  u64 r = x.lo - qh * m.q;
+  u64 qh = mulhi64(t, m.mu);
+  u64 r = x.lo - mullo64(qh, m.q);
   r = csub(r, m.q);
   return csub(r, m.q);
 }

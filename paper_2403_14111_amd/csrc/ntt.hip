@@ -18,9 +18,13 @@
 //  * Loads and stores are arranged so that the 16 threads of a sub-transform
 //    (contiguous pass) or 16 neighbouring columns (strided pass) touch 128
 //    contiguous bytes.
-//  * Forward butterflies are lazy: X' = X + T, Y' = X + 2q - T with
-//    T = Shoup(Y * W) in [0, 2q); values stay below (1 + 2 log N) q < 2^56
-//    and one Shoup reduction by 1 finishes.  Inverse butterflies keep [0, 2q).
+//  * Butterflies are lazy.  T = Y * W mod q comes from Shoup's method with a
+//    quotient estimate that skips the carries of the low partial products
+//    (3 integer multiplies fewer, and no 64-bit register shuffles): it is at
+//    most 3 below the exact quotient, so T lies in [0, 4q).  Forward:
+//    X' = X + T, Y' = X + 4q - T; values stay below (1 + 4 log N) q < 2^57
+//    and one exact Shoup reduction by 1 finishes.  Inverse: values kept in
+//    [0, 4q) by one conditional subtraction of 4q on the sum.
 #include "hetal_internal.hpp"
 
 namespace hetal {
@@ -32,23 +36,36 @@ constexpr int NTT_R = 16;
 
 __device__ __forceinline__ int pad_idx(int v) { return v + (v >> 4); }
 
-__device__ __forceinline__ void fwd_bfly(u64& x, u64& y, ulonglong2 w, u64 q, u64 q2) {
-  u64 t = mul_shoup_lazy(y, w.x, w.y, q);
-  y = x + q2 - t;
+__device__ __forceinline__ void fwd_bfly(u64& x, u64& y, ulonglong2 w, u64 q, u64 q4) {
+  u64 t = mul_shoup_lazy4(y, w.x, w.y, q);
+  y = x + q4 - t;
   x = x + t;
 }
 
-__device__ __forceinline__ void inv_bfly(u64& x, u64& y, ulonglong2 w, u64 q, u64 q2) {
+__device__ __forceinline__ void inv_bfly(u64& x, u64& y, ulonglong2 w, u64 q, u64 q4) {
   u64 s = x + y;
-  s = s >= q2 ? s - q2 : s;
-  u64 d = x + q2 - y;
-  y = mul_shoup_lazy(d, w.x, w.y, q);
+  s = s >= q4 ? s - q4 : s;
+  u64 d = x + q4 - y;
+  y = mul_shoup_lazy4(d, w.x, w.y, q);
   x = s;
 }
 
+// Workgroups are numbered so that the batch items sharing one (row, chunk) --
+// and so one twiddle range -- run back to back on the same XCD (workgroups
+// are dealt to the 8 XCDs round robin), where the twiddles stay in its L2.
+struct PassArgs {
+  u64* base;
+  size_t batch_stride;
+  const u64* src;       // input of this pass (null: in place)
+  size_t src_batch_stride;
+  int src_row_mul, src_row_add;  // input row = row * mul + add
+  int groups;           // (row, chunk) pairs
+  int batch;
+  int wg_per_poly;
+};
+
 template <int L, bool INV>
-__global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__ base, size_t batch_stride,
-                                                              const int2* __restrict__ rows,
+__global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const ulonglong2* __restrict__ tw,
                                                               const ModInfo* __restrict__ mods,
                                                               const PrimeConsts* __restrict__ pc, int log_n, int s0,
@@ -62,26 +79,36 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
   const int n = 1 << log_n;
   const int log_stride = log_n - s0 - L;
   const int stride = 1 << log_stride;
-  const int2 rj = rows[blockIdx.y];
-  u64* __restrict__ a = base + (size_t)blockIdx.z * batch_stride + (size_t)rj.x * n;
+  const int wg = blockIdx.x;
+  const int per_block = 8 * pa.batch;
+  const int item = (wg % per_block) >> 3;
+  const int group = (wg / per_block) * 8 + (wg & 7);
+  if (group >= pa.groups) return;
+  const int rowi = group / pa.wg_per_poly;
+  const int chunk = group - rowi * pa.wg_per_poly;
+  const int2 rj = rows[rowi];
+  u64* __restrict__ a = pa.base + (size_t)item * pa.batch_stride + (size_t)rj.x * n;
+  const u64* __restrict__ ain =
+      pa.src ? pa.src + (size_t)item * pa.src_batch_stride + (size_t)(rj.x * pa.src_row_mul + pa.src_row_add) * n : a;
   const u64 q = mods[rj.y].q;
-  const u64 q2 = 2 * q;
+  const u64 q4 = 4 * q;
   const ulonglong2* __restrict__ w = tw + (size_t)rj.y * n;
 
   const int tid = threadIdx.x;
   const bool contiguous = (stride == 1);
   const int sl = contiguous ? tid / T : tid % S;
   const int j = contiguous ? tid % T : tid / S;
-  const int sub = blockIdx.x * S + sl;
+  const int sub = chunk * S + sl;
   const int hi = sub >> log_stride;
   const int lo = sub & (stride - 1);
   u64* __restrict__ p = a + ((size_t)hi << (log_stride + L)) + lo;
+  const u64* __restrict__ pin = ain + ((size_t)hi << (log_stride + L)) + lo;
   u64* __restrict__ ls = lds + sl * PAD;
   u64 x[NTT_R];
 
   if (!INV) {
 #pragma unroll
-    for (int u = 0; u < NTT_R; ++u) x[u] = p[(size_t)(j + T * u) << log_stride];
+    for (int u = 0; u < NTT_R; ++u) x[u] = pin[(size_t)(j + T * u) << log_stride];
     // stages 0..3: element v = j + T u is held in x[u]
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
@@ -91,7 +118,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
         if (u & hu) continue;
         const int v = j + T * u;
         const int blk = (hi << l) | (v >> (L - l));
-        fwd_bfly(x[u], x[u + hu], w[(1 << (s0 + l)) + blk], q, q2);
+        fwd_bfly(x[u], x[u + hu], w[(1 << (s0 + l)) + blk], q, q4);
       }
     }
     if (L > 4) {
@@ -109,7 +136,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
           if (u & half) continue;
           const int v = 16 * j + u;
           const int blk = (hi << l) | (v >> (L - l));
-          fwd_bfly(x[u], x[u + half], w[(1 << (s0 + l)) + blk], q, q2);
+          fwd_bfly(x[u], x[u + half], w[(1 << (s0 + l)) + blk], q, q4);
         }
       }
     }
@@ -138,13 +165,13 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
     // ownership v = 16 j + u for stages L-1 .. 4
     if (L > 4 && contiguous) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) ls[pad_idx(j + T * u)] = p[(size_t)(j + T * u) << log_stride];
+      for (int u = 0; u < NTT_R; ++u) ls[pad_idx(j + T * u)] = pin[(size_t)(j + T * u) << log_stride];
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = ls[pad_idx(16 * j + u)];
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = p[(size_t)(16 * j + u) << log_stride];
+      for (int u = 0; u < NTT_R; ++u) x[u] = pin[(size_t)(16 * j + u) << log_stride];
     }
     if (L > 4) {
 #pragma unroll
@@ -155,7 +182,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
           if (u & half) continue;
           const int v = 16 * j + u;
           const int blk = (hi << l) | (v >> (L - l));
-          inv_bfly(x[u], x[u + half], w[(1 << (s0 + l)) + blk], q, q2);
+          inv_bfly(x[u], x[u + half], w[(1 << (s0 + l)) + blk], q, q4);
         }
       }
       if (contiguous) __syncthreads();
@@ -178,17 +205,17 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
         if (l == 0 && merge_ninv) {
           const PrimeConsts k = pc[rj.y];
           u64 s = x[u] + x[u + hu];
-          u64 d = x[u] + q2 - x[u + hu];
-          x[u] = mul_shoup_lazy(s, k.ninv, k.ninv_sh, q);
-          x[u + hu] = mul_shoup_lazy(d, k.w1ninv, k.w1ninv_sh, q);
+          u64 d = x[u] + q4 - x[u + hu];
+          x[u] = mul_shoup_lazy4(s, k.ninv, k.ninv_sh, q);
+          x[u + hu] = mul_shoup_lazy4(d, k.w1ninv, k.w1ninv_sh, q);
         } else {
-          inv_bfly(x[u], x[u + hu], w[(1 << (s0 + l)) + blk], q, q2);
+          inv_bfly(x[u], x[u + hu], w[(1 << (s0 + l)) + blk], q, q4);
         }
       }
     }
     if (final_pass) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = csub(x[u], q);
+      for (int u = 0; u < NTT_R; ++u) x[u] = csub(csub(x[u], 2 * q), q);
     }
 #pragma unroll
     for (int u = 0; u < NTT_R; ++u) p[(size_t)(j + T * u) << log_stride] = x[u];
@@ -196,18 +223,30 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(u64* __restrict__
 }
 
 template <bool INV>
-void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0, int final_pass) {
+void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0, int final_pass,
+                 const NttSrc& src) {
   const int sub = 1 << L;
   const int per_wg = NTT_THREADS * NTT_R / sub;  // sub-transforms per workgroup
   const int nsub = c.n / sub;
-  dim3 grid(nsub / per_wg, rows.count, batch), block(NTT_THREADS);
+  PassArgs pa;
+  pa.base = base;
+  pa.batch_stride = batch_stride;
+  pa.src = src.p;
+  pa.src_batch_stride = src.batch_stride;
+  pa.src_row_mul = src.row_mul;
+  pa.src_row_add = src.row_add;
+  pa.wg_per_poly = nsub / per_wg;
+  pa.groups = pa.wg_per_poly * rows.count;
+  pa.batch = batch;
+  const int padded = (pa.groups + 7) / 8 * 8;
+  dim3 grid((unsigned)(padded * batch)), block(NTT_THREADS);
   const ulonglong2* tw = INV ? c.d_tw_inv : c.d_tw_fwd;
   c.begin_launch();
   switch (L) {
-#define HETAL_NTT_CASE(LL)                                                                                      \
-  case LL:                                                                                                    \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV>), grid, block, 0, c.stream, base, batch_stride, rows.d, tw, \
-                       c.d_mod, c.d_pc, c.log_n, s0, final_pass);                                            \
+#define HETAL_NTT_CASE(LL)                                                                                \
+  case LL:                                                                                              \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, c.d_pc, \
+                       c.log_n, s0, final_pass);                                                        \
     break;
     HETAL_NTT_CASE(4)
     HETAL_NTT_CASE(5)
@@ -223,19 +262,19 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
 
 }  // namespace
 
-void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows) {
+void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
-  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, 0);
-  launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, 1);
+  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, 0, src);
+  launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, 1, NttSrc{});
   c.counters[6] += (int64_t)rows.count * batch;
 }
 
-void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows) {
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
-  launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, 0);
-  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, 1);
+  launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, 0, src);
+  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, 1, NttSrc{});
   c.counters[6] += (int64_t)rows.count * batch;
 }
 

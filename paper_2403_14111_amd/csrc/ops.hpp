@@ -157,6 +157,11 @@ Batch b_mod_drop(Context& c, BView a, int level);
 Batch b_rescale(Context& c, BView a);
 // Item i rotated left by steps[i] (steps.size() == 1: the same step for all).
 Batch b_rotate(Context& c, const KeySet& k, BView a, const std::vector<int>& steps);
+// addend[i] + Lrot(a[i], step) for every item (addend defaults to a itself),
+// the addition fused into the key switch's last kernel.
+Batch b_rotate_add(Context& c, const KeySet& k, BView a, int step, const BView* addend = nullptr);
+// a[i] + conj(a[i]).
+Batch b_conj_add(Context& c, const KeySet& k, BView a);
 // One ciphertext rotated by each step, sharing one ModUp (hoisting).
 Batch b_rotate_hoisted(Context& c, const KeySet& k, CtView a, const std::vector<int>& steps);
 Batch b_conj(Context& c, const KeySet& k, BView a);

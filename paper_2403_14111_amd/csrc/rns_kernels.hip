@@ -14,8 +14,7 @@ constexpr int TPB = 256;
 inline dim3 grid_for(const Context& c, int y, int z) { return dim3((unsigned)(c.n / TPB), (unsigned)y, (unsigned)z); }
 
 // ---------------------------------------------------------------- ModUp
-// For digit j (blockIdx.y): rows of the digit copy the NTT-form input; every
-// other row of the extended basis q_0..q_l, p_0..p_{K-1} receives the fast
+// For digit j (blockIdx.y): every row of the extended basis outside the digit q_0..q_l, p_0..p_{K-1} receives the fast
 // basis conversion of the digit's coefficient-form residues
 //   sum_i [x_i (D/d_i)^-1]_{d_i} (D/d_i) mod t    (128-bit lazy sum, one Barrett).
 __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef, size_t coef_stride,
@@ -30,7 +29,6 @@ __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef
   const int jd = blockIdx.y;
   const ModUpTab& tb = tabs[jd];
   const u64* __restrict__ cf = coef + blockIdx.z * coef_stride;
-  const u64* __restrict__ ni = ntt_in + blockIdx.z * in_stride;
   u64* __restrict__ out = dt + blockIdx.z * dt_stride + (size_t)jd * ext * n;
   u64 y[MAX_ALPHA];
 #pragma unroll
@@ -41,10 +39,7 @@ __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef
     }
   }
   for (int r = 0; r < ext; ++r) {
-    if (r >= tb.first && r < tb.first + tb.nsrc) {
-      out[(size_t)r * n + k] = ni[(size_t)r * n + k];
-      continue;
-    }
+    if (r >= tb.first && r < tb.first + tb.nsrc) continue;  // the digit's own rows are read from the input
     const int t = r < l ? r : num_q + (r - l);
     U128 acc = {0, 0};
 #pragma unroll
@@ -64,9 +59,10 @@ struct IpArgs {
 };
 
 __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restrict__ dt, size_t dt_stride,
+                                                            const u64* __restrict__ in, size_t in_stride,
                                                             u64* __restrict__ acc, size_t acc_stride, IpArgs args,
                                                             const ModInfo* __restrict__ mods, int log_n, int level,
-                                                            int num_q, int num_p, int nprimes, int beta) {
+                                                            int num_q, int num_p, int nprimes, int beta, int alpha) {
   const int n = 1 << log_n;
   const int l = level + 1;
   const int ext = l + num_p;
@@ -77,10 +73,12 @@ __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restric
   const u32 g = args.g[item];
   const u64* __restrict__ key = args.key[item];
   const u64* __restrict__ d = dt + item * dt_stride + (size_t)r * n;
+  const u64* __restrict__ own = in + item * in_stride + (size_t)r * n;
+  const int rd = r < l ? r / alpha : -1;  // the digit that row r belongs to
   const u32 src = g == 1 ? (u32)k : galois_source((u32)k, g, log_n);
   U128 sb = {0, 0}, sa = {0, 0};
   for (int j = 0; j < beta; ++j) {
-    const u64 x = d[(size_t)j * ext * n + src];
+    const u64 x = j == rd ? own[src] : d[(size_t)j * ext * n + src];
     const u64 kb = key[((size_t)(2 * j) * nprimes + t) * n + k];
     const u64 ka = key[((size_t)(2 * j + 1) * nprimes + t) * n + k];
     acc_wide(sb, mul_wide(x, kb));
@@ -95,11 +93,12 @@ __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restric
 // Same, for `count` items that share one key and Galois element: the key
 // words are loaded once per coefficient and reused for every item.
 __global__ void __launch_bounds__(TPB) inner_product_shared_kernel(const u64* __restrict__ dt, size_t dt_stride,
+                                                                   const u64* __restrict__ in, size_t in_stride,
                                                                    u64* __restrict__ acc, size_t acc_stride,
                                                                    const u64* __restrict__ key, u32 g, int count,
                                                                    const ModInfo* __restrict__ mods, int log_n,
                                                                    int level, int num_q, int num_p, int nprimes,
-                                                                   int beta) {
+                                                                   int beta, int alpha) {
   constexpr int MAXB = 8;  // digits held in registers (dnum <= 8 for this kernel)
   const int n = 1 << log_n;
   const int l = level + 1;
@@ -117,13 +116,15 @@ __global__ void __launch_bounds__(TPB) inner_product_shared_kernel(const u64* __
     }
   }
   const ModInfo m = mods[t];
+  const int rd = r < l ? r / alpha : -1;  // the digit that row r belongs to
   for (int item = 0; item < count; ++item) {
     const u64* __restrict__ d = dt + item * dt_stride + (size_t)r * n;
+    const u64* __restrict__ own = in + item * in_stride + (size_t)r * n;
     U128 sb = {0, 0}, sa = {0, 0};
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
       if (j < beta) {
-        const u64 x = d[(size_t)j * ext * n + src];
+        const u64 x = j == rd ? own[src] : d[(size_t)j * ext * n + src];
         acc_wide(sb, mul_wide(x, kb[j]));
         acc_wide(sa, mul_wide(x, ka[j]));
       }
@@ -180,6 +181,8 @@ struct CombineArgs {
   size_t add0_stride;
   const u64* add1;
   size_t add1_stride;
+  const u64* addx;  // optional ciphertext [2][l][N] added to both outputs (x + Lrot(x) in one pass)
+  size_t addx_stride;
   u32 g[MAX_BATCH];
   int gather;
 };
@@ -209,6 +212,11 @@ __global__ void __launch_bounds__(TPB) moddown_combine_kernel(const u64* __restr
     v0 = add_mod(v0, ca.add0[item * ca.add0_stride + (size_t)i * n + src], q);
   }
   if (ca.add1) v1 = add_mod(v1, ca.add1[item * ca.add1_stride + (size_t)i * n + k], q);
+  if (ca.addx) {
+    const u64* x = ca.addx + item * ca.addx_stride;
+    v0 = add_mod(v0, x[(size_t)i * n + k], q);
+    v1 = add_mod(v1, x[(size_t)(l + i) * n + k], q);
+  }
   o[(size_t)i * n + k] = v0;
   o[(size_t)(l + i) * n + k] = v1;
 }
@@ -396,16 +404,13 @@ void key_switch(Context& c, const KsJob& job) {
   const size_t acc_words = 2 * (size_t)ext * n;
   const size_t conv_words = 2 * poly;
 
-  // 1. coefficient form of the input(s)
+  // 1. coefficient form of the input(s): the inverse NTT reads the input in place of a copy
   Tmp coef(c.pool, m_in * poly);
-  if (m_in == 1 || job.in_stride == poly) {
-    HCHECK(hipMemcpyAsync(coef.p, job.in, m_in * poly * 8, hipMemcpyDeviceToDevice, c.stream));
-  } else {
-    HCHECK(hipMemcpy2DAsync(coef.p, poly * 8, job.in, job.in_stride * 8, poly * 8, m_in, hipMemcpyDeviceToDevice,
-                            c.stream));
-  }
   RowsRef ct_rows = c.rows(ROWS_CT, level);
-  ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l});
+  NttSrc src;
+  src.p = job.in;
+  src.batch_stride = hoisted ? 0 : job.in_stride;
+  ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l}, src);
 
   // 2. ModUp of every digit, then the NTT of the converted rows
   Tmp dt(c.pool, m_in * dt_words);
@@ -413,8 +418,8 @@ void key_switch(Context& c, const KsJob& job) {
   hipLaunchKernelGGL(modup_kernel, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, poly, job.in,
                      job.in_stride, dt.p, dt_words, c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level,
                      c.num_q, c.num_p);
-  // reads: each digit's coefficient-form and NTT-form limbs (2l rows in all); writes beta * ext rows
-  c.end_launch(KC_MODUP, 8.0 * n * m_in * (2.0 * l + (double)beta * ext));
+  // reads: each digit's coefficient-form limbs (l rows in all); writes the beta * ext - l rows outside the digits
+  c.end_launch(KC_MODUP, 8.0 * n * m_in * ((double)beta * ext));
   ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level));
 
   // 3. inner product with the keys, automorphism applied on the loads
@@ -423,9 +428,9 @@ void key_switch(Context& c, const KsJob& job) {
   for (int i = 1; i < m && shared; ++i) shared = job.item[i].key == job.item[0].key && job.item[i].g == job.item[0].g;
   if (shared) {
     c.begin_launch();
-    hipLaunchKernelGGL(inner_product_shared_kernel, grid_for(c, ext, 1), dim3(TPB), 0, c.stream, dt.p, dt_words, acc.p,
-                       acc_words, job.item[0].key, job.item[0].g, m, c.d_mod, c.log_n, level, c.num_q, c.num_p,
-                       c.nprimes, beta);
+    hipLaunchKernelGGL(inner_product_shared_kernel, grid_for(c, ext, 1), dim3(TPB), 0, c.stream, dt.p, dt_words,
+                       job.in, job.in_stride, acc.p, acc_words, job.item[0].key, job.item[0].g, m, c.d_mod, c.log_n,
+                       level, c.num_q, c.num_p, c.nprimes, beta, c.alpha);
     // reads: the extended digits of every item and 2 beta ext key rows once; writes 2 ext rows per item
     c.end_launch(KC_INNER, 8.0 * n * ((double)m * beta * ext + 2.0 * beta * ext + (double)m * 2.0 * ext));
   } else {
@@ -436,8 +441,8 @@ void key_switch(Context& c, const KsJob& job) {
     }
     c.begin_launch();
     hipLaunchKernelGGL(inner_product_kernel, grid_for(c, ext, m), dim3(TPB), 0, c.stream, dt.p,
-                       hoisted ? (size_t)0 : dt_words, acc.p, acc_words, ip, c.d_mod, c.log_n, level, c.num_q,
-                       c.num_p, c.nprimes, beta);
+                       hoisted ? (size_t)0 : dt_words, job.in, hoisted ? (size_t)0 : job.in_stride, acc.p, acc_words,
+                       ip, c.d_mod, c.log_n, level, c.num_q, c.num_p, c.nprimes, beta, c.alpha);
     // reads: the extended digits (once per input) and 2 beta ext key rows per item; writes 2 ext rows per item
     c.end_launch(KC_INNER, 8.0 * n * ((double)m_in * beta * ext + (double)m * (2.0 * beta * ext + 2.0 * ext)));
   }
@@ -455,12 +460,15 @@ void key_switch(Context& c, const KsJob& job) {
   ca.add0_stride = job.add0_stride;
   ca.add1 = job.add1;
   ca.add1_stride = job.add1_stride;
+  ca.addx = job.addx;
+  ca.addx_stride = job.addx_stride;
   ca.gather = job.add0_galois ? 1 : 0;
   for (int i = 0; i < MAX_BATCH; ++i) ca.g[i] = i < m ? job.item[i].g : 1;
   c.begin_launch();
   hipLaunchKernelGGL(moddown_combine_kernel, grid_for(c, l, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
                      conv_words, job.out, job.out_stride, ca, c.d_moddown, c.d_mod, c.log_n, level, c.num_p);
-  c.end_launch(KC_COMBINE, 8.0 * n * m * (4.0 * l + (job.add0 ? l : 0) + (job.add1 ? l : 0) + 2.0 * l));
+  c.end_launch(KC_COMBINE,
+               8.0 * n * m * (4.0 * l + (job.add0 ? l : 0) + (job.add1 ? l : 0) + (job.addx ? 2.0 * l : 0) + 2.0 * l));
   c.counters[5] += m;
 }
 
@@ -507,17 +515,12 @@ void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int lev
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
   const size_t n = c.n;
   Tmp top(c.pool, (size_t)batch * 2 * n);
-  for (int p = 0; p < 2; ++p) {
-    const u64* src = in + ((size_t)p * (level + 1) + level) * n;
-    if (batch == 1) {
-      HCHECK(hipMemcpyAsync(top.p + p * n, src, n * 8, hipMemcpyDeviceToDevice, c.stream));
-    } else {
-      if (in_stride < n) fail(HETAL_E_INVALID_ARG, "rescale of a broadcast batch");
-      HCHECK(hipMemcpy2DAsync(top.p + p * n, 2 * n * 8, src, in_stride * 8, n * 8, batch, hipMemcpyDeviceToDevice,
-                              c.stream));
-    }
-  }
-  ntt_inverse(c, top, 2 * n, batch, c.rows(ROWS_TOP, level));
+  NttSrc src;
+  src.p = in;
+  src.batch_stride = in_stride;
+  src.row_mul = level + 1;  // top row of poly p: p (level + 1) + level
+  src.row_add = level;
+  ntt_inverse(c, top, 2 * n, batch, c.rows(ROWS_TOP, level), src);
   Tmp spread(c.pool, (size_t)batch * 2 * level * n);
   c.begin_launch();
   hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, batch), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
