@@ -12,8 +12,9 @@
 //    last 8 stages on contiguous 256-point chunks.  Each pass reads and
 //    writes the limb once (2 x 1 MiB of HBM traffic per limb and transform).
 //  * 256 threads per workgroup, 16 residues per thread in registers: four
-//    stages run in registers, one LDS transpose (padded by one word per 16 to
-//    keep the strided reads conflict-free) switches the ownership, the
+//    stages run in registers, one LDS transpose (padded by one word per 16,
+//    and with an odd slice length per sub-transform, so that both access
+//    patterns are free of bank conflicts) switches the ownership, the
 //    remaining stages run in registers again.
 //  * Loads and stores are arranged so that the 16 threads of a sub-transform
 //    (contiguous pass) or 16 neighbouring columns (strided pass) touch 128
@@ -64,7 +65,7 @@ struct PassArgs {
   int wg_per_poly;
 };
 
-template <int L, bool INV>
+template <int L, bool INV, bool CONTIG>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const ulonglong2* __restrict__ tw,
                                                               const ModInfo* __restrict__ mods,
@@ -73,7 +74,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   constexpr int SUB = 1 << L;
   constexpr int T = SUB / NTT_R;        // threads per sub-transform
   constexpr int S = NTT_THREADS / T;    // sub-transforms per workgroup
-  constexpr int PAD = SUB + SUB / 16;
+  // one word of padding per 16 keeps strided reads of a sub-transform on distinct banks; the odd
+  // slice length spreads neighbouring sub-transforms (read in lockstep by the strided pass) as well
+  constexpr int PAD = SUB + SUB / 16 + 1;
   __shared__ u64 lds[S * PAD];
 
   const int n = 1 << log_n;
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   const ulonglong2* __restrict__ w = tw + (size_t)rj.y * n;
 
   const int tid = threadIdx.x;
-  const bool contiguous = (stride == 1);
+  constexpr bool contiguous = CONTIG;  // stride == 1
   const int sl = contiguous ? tid / T : tid % S;
   const int j = contiguous ? tid % T : tid / S;
   const int sub = chunk * S + sl;
@@ -242,17 +245,19 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   dim3 grid((unsigned)(padded * batch)), block(NTT_THREADS);
   const ulonglong2* tw = INV ? c.d_tw_inv : c.d_tw_fwd;
   c.begin_launch();
-  switch (L) {
-#define HETAL_NTT_CASE(LL)                                                                                \
-  case LL:                                                                                              \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, c.d_pc, \
-                       c.log_n, s0, final_pass);                                                        \
+  const bool contiguous = s0 + L == c.log_n;
+  switch (L * 2 + (contiguous ? 1 : 0)) {
+#define HETAL_NTT_CASE(LL, CC)                                                                           \
+  case LL * 2 + CC:                                                                                    \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, \
+                       c.d_pc, c.log_n, s0, final_pass);                                               \
     break;
-    HETAL_NTT_CASE(4)
-    HETAL_NTT_CASE(5)
-    HETAL_NTT_CASE(6)
-    HETAL_NTT_CASE(7)
-    HETAL_NTT_CASE(8)
+    HETAL_NTT_CASE(4, 0)
+    HETAL_NTT_CASE(5, 0)
+    HETAL_NTT_CASE(6, 0)
+    HETAL_NTT_CASE(7, 0)
+    HETAL_NTT_CASE(8, 0)
+    HETAL_NTT_CASE(8, 1)
 #undef HETAL_NTT_CASE
     default:
       fail(HETAL_E_PARAMS, "unsupported NTT pass size");
