@@ -194,8 +194,9 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
     }
     for (int x = 0; x < n; ++x) {
       const u64 wf = pw[brev((u32)x, c.log_n)], wi = pwi[brev((u32)x, c.log_n)];
-      twf[(size_t)i * n + x] = make_ulonglong2(wf, shoup(wf, q));
-      twi[(size_t)i * n + x] = make_ulonglong2(wi, shoup(wi, q));
+      const size_t at = (size_t)i * n + ntt_twiddle_slot(x, c.log_n);
+      twf[at] = make_ulonglong2(wf, shoup(wf, q));
+      twi[at] = make_ulonglong2(wi, shoup(wi, q));
     }
     PrimeConsts& k = c.h_pc[i];
     k.ninv = invm((u64)n % q, q);

@@ -60,6 +60,23 @@ struct RescaleTab {
 
 // Per prime: N^-1, and psi^-brev(1) N^-1 (the last inverse butterfly with N^-1 merged);
 // i_q = psi^(N/2), a square root of -1 (multiplication by X^(N/2) in the NTT domain).
+// Position of twiddle x (the one of forward stage s, x in [2^s, 2^(s+1))) in the twiddle tables.
+// The last 8 stages run on 256-point chunks, and in their stages 4..7 the 16 threads of a chunk
+// each take a different twiddle of the stage's 2^l for chunk c: thread j takes entries
+// j 2^(l-4) + i, i < 2^(l-4).  Those 2^l entries are stored i-major (slot 16 i + j) so that one
+// load instruction of the 16 threads reads 256 contiguous bytes.  All other twiddles are in place.
+inline int ntt_twiddle_slot(int x, int log_n) {
+  const int s0 = log_n - 8;
+  if (x < (1 << (s0 + 4))) return x;
+  const int s = 31 - __builtin_clz((unsigned)x);
+  const int l = s - s0;
+  const int base = 1 << s;
+  const int c = (x - base) >> l;
+  const int k = (x - base) & ((1 << l) - 1);
+  const int m = l - 4;
+  return base + (c << l) + (((k & ((1 << m) - 1)) << 4) | (k >> m));
+}
+
 struct PrimeConsts {
   u64 ninv, ninv_sh;
   u64 w1ninv, w1ninv_sh;
@@ -121,8 +138,8 @@ struct Context {
   hipStream_t stream = nullptr;
 
   ModInfo* d_mod = nullptr;          // [nprimes]
-  ulonglong2* d_tw_fwd = nullptr;    // [nprimes][N]: (psi^brev(x), Shoup)
-  ulonglong2* d_tw_inv = nullptr;    // [nprimes][N]: (psi^-brev(x), Shoup)
+  ulonglong2* d_tw_fwd = nullptr;    // [nprimes][N]: (psi^brev(x), Shoup) at ntt_twiddle_slot(x)
+  ulonglong2* d_tw_inv = nullptr;    // [nprimes][N]: (psi^-brev(x), Shoup) at ntt_twiddle_slot(x)
   PrimeConsts* d_pc = nullptr;       // [nprimes]
   ModUpTab* d_modup = nullptr;       // [num_q levels][dnum]
   ModDownTab* d_moddown = nullptr;   // one table (rows q_0..q_{num_q-1})

@@ -82,6 +82,27 @@ __device__ __forceinline__ u64 mul_shoup_lazy4(u64 a, u64 w, u64 wp, u64 q) {
   return mullo64(a, w) - mullo64(h, q);
 }
 
+// The same product with the subtraction folded into multiply-adds: a*w - h*q = a*w + h*nq (mod 2^64)
+// with nq = 2^64 - q, so both low partial products chain into one 64-bit multiply-add and the four
+// cross products into the high word.  Result in [0, 4q) for any a < 2^64.
+__device__ __forceinline__ u64 mul_shoup_lazy4n(u64 a, u64 w, u64 wp, u64 nq) {
+  const u32 a0 = lo32(a), a1 = hi32(a);
+  const u64 h = mulhi64_lazy(a, wp);
+  const u32 h0 = lo32(h), h1 = hi32(h);
+  const u64 lo = (u64)a0 * lo32(w) + (u64)h0 * lo32(nq);
+  const u32 hi = hi32(lo) + a0 * hi32(w) + a1 * lo32(w) + h0 * hi32(nq) + h1 * lo32(nq);
+  return ((u64)hi << 32) | lo32(lo);
+}
+
+// x mod q lazily, in [0, 4q) for any x < 2^64 (Shoup multiplication by 1).
+__device__ __forceinline__ u64 reduce_lazy4(u64 x, u64 one_sh, u64 nq) {
+  const u64 h = mulhi64_lazy(x, one_sh);
+  const u32 h0 = lo32(h), h1 = hi32(h);
+  const u64 lo = (u64)lo32(x) + (u64)h0 * lo32(nq);
+  const u32 hi = hi32(lo) + hi32(x) + h0 * hi32(nq) + h1 * lo32(nq);
+  return ((u64)hi << 32) | lo32(lo);
+}
+
 __device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
 
 __device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 wp, u64 q) { return csub(mul_shoup_lazy(a, w, wp, q), q); }

@@ -12,10 +12,9 @@
 //    last 8 stages on contiguous 256-point chunks.  Each pass reads and
 //    writes the limb once (2 x 1 MiB of HBM traffic per limb and transform).
 //  * 256 threads per workgroup, 16 residues per thread in registers: four
-//    stages run in registers, one LDS transpose (padded by one word per 16,
-//    and with an odd slice length per sub-transform, so that both access
-//    patterns are free of bank conflicts) switches the ownership, the
-//    remaining stages run in registers again.
+//    stages run in registers, one LDS transpose (in two 32-bit halves, padded
+//    against bank conflicts) switches the ownership, the remaining stages run
+//    in registers again.
 //  * Loads and stores are arranged so that the 16 threads of a sub-transform
 //    (contiguous pass) or 16 neighbouring columns (strided pass) touch 128
 //    contiguous bytes.
@@ -37,17 +36,18 @@ constexpr int NTT_R = 16;
 
 __device__ __forceinline__ int pad_idx(int v) { return v + (v >> 4); }
 
-__device__ __forceinline__ void fwd_bfly(u64& x, u64& y, ulonglong2 w, u64 q, u64 q4) {
-  u64 t = mul_shoup_lazy4(y, w.x, w.y, q);
+__device__ __forceinline__ void fwd_bfly(u64& x, u64& y, ulonglong2 w, u64 nq, u64 q4) {
+  const u64 t = mul_shoup_lazy4n(y, w.x, w.y, nq);
   y = x + q4 - t;
   x = x + t;
 }
 
-__device__ __forceinline__ void inv_bfly(u64& x, u64& y, ulonglong2 w, u64 q, u64 q4) {
-  u64 s = x + y;
-  s = s >= q4 ? s - q4 : s;
-  u64 d = x + q4 - y;
-  y = mul_shoup_lazy4(d, w.x, w.y, q);
+// Gentleman-Sande butterfly without reduction of the sum: with both inputs below b, x + b - y is
+// positive, the sum stays below 2b and the product below 4q.
+__device__ __forceinline__ void inv_bfly(u64& x, u64& y, ulonglong2 w, u64 nq, u64 b) {
+  const u64 s = x + y;
+  const u64 d = x + b - y;
+  y = mul_shoup_lazy4n(d, w.x, w.y, nq);
   x = s;
 }
 
@@ -65,23 +65,55 @@ struct PassArgs {
   int wg_per_poly;
 };
 
+// Transpose through LDS: x[u] is stored at word widx(u) of the workgroup's buffer, then x[u] is
+// loaded from word ridx(u).  The 64-bit residues travel as two 32-bit halves through a 32-bit
+// buffer, which halves the LDS a workgroup holds.  LEAD_SYNC: the buffer was read before.
+template <bool LEAD_SYNC, class W, class R>
+__device__ __forceinline__ void lds_exchange(u64 (&x)[NTT_R], u32* __restrict__ ls, W widx, R ridx) {
+  if (LEAD_SYNC) __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = lo32(x[u]);
+  __syncthreads();
+  u32 lo[NTT_R];
+#pragma unroll
+  for (int u = 0; u < NTT_R; ++u) lo[u] = ls[ridx(u)];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = hi32(x[u]);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NTT_R; ++u) x[u] = ((u64)ls[ridx(u)] << 32) | lo[u];
+}
+
+// One pass of 2^L-point sub-transforms.  Two shapes occur:
+//  * strided (pass A, CONTIG false): the 256 columns of the limb seen as a 2^L x 256 matrix, stages
+//    0 .. L-1 (s0 == 0); element v of column c sits at c + 256 v;
+//  * contiguous (pass B, CONTIG true): the 2^(log_n - 8) chunks of 256, stages log_n - 8 .. log_n - 1
+//    (L == 8); element v of chunk c sits at 256 c + v.
+// Forward passes run A then B, inverse passes B then A; the second pass of either is the final one
+// (full reduction; for the inverse also the N^-1 scaling).
+//
+// Each thread holds 16 elements of one sub-transform: in stages 0..3 of the pass element
+// v = j + T u ("spread"), in stages 4..L-1 element v = 16 j + u ("block").  The twiddle of stage l
+// for element v is psi_rev[2^(s0 + l) + (c 2^l) + (v >> (L - l))] (c = 0 in the strided pass, where
+// in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
 template <int L, bool INV, bool CONTIG>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const ulonglong2* __restrict__ tw,
                                                               const ModInfo* __restrict__ mods,
-                                                              const PrimeConsts* __restrict__ pc, int log_n, int s0,
-                                                              int final_pass) {
+                                                              const PrimeConsts* __restrict__ pc, int log_n, int s0) {
   constexpr int SUB = 1 << L;
   constexpr int T = SUB / NTT_R;        // threads per sub-transform
   constexpr int S = NTT_THREADS / T;    // sub-transforms per workgroup
-  // one word of padding per 16 keeps strided reads of a sub-transform on distinct banks; the odd
-  // slice length spreads neighbouring sub-transforms (read in lockstep by the strided pass) as well
-  constexpr int PAD = SUB + SUB / 16 + 1;
-  __shared__ u64 lds[S * PAD];
+  constexpr bool FINAL = INV != CONTIG;
+  static_assert(!CONTIG || L == 8, "the contiguous pass covers the last 8 stages");
+  // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
+  // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
+  // neighbouring slices in lockstep fall on distinct banks.
+  constexpr int PAD = SUB + SUB / 16 + (CONTIG ? 0 : 2);
+  __shared__ u32 lds[S * PAD];
 
   const int n = 1 << log_n;
-  const int log_stride = log_n - s0 - L;
-  const int stride = 1 << log_stride;
   const int wg = blockIdx.x;
   const int per_block = 8 * pa.batch;
   const int item = (wg % per_block) >> 3;
@@ -95,138 +127,128 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       pa.src ? pa.src + (size_t)item * pa.src_batch_stride + (size_t)(rj.x * pa.src_row_mul + pa.src_row_add) * n : a;
   const u64 q = mods[rj.y].q;
   const u64 q4 = 4 * q;
+  const u64 nq = 0 - q;
   const ulonglong2* __restrict__ w = tw + (size_t)rj.y * n;
 
   const int tid = threadIdx.x;
-  constexpr bool contiguous = CONTIG;  // stride == 1
-  const int sl = contiguous ? tid / T : tid % S;
-  const int j = contiguous ? tid % T : tid / S;
+  const int sl = CONTIG ? tid / T : tid % S;
+  const int j = CONTIG ? tid % T : tid / S;
   const int sub = chunk * S + sl;
-  const int hi = sub >> log_stride;
-  const int lo = sub & (stride - 1);
-  u64* __restrict__ p = a + ((size_t)hi << (log_stride + L)) + lo;
-  const u64* __restrict__ pin = ain + ((size_t)hi << (log_stride + L)) + lo;
-  u64* __restrict__ ls = lds + sl * PAD;
+  // limb offsets of this thread's elements: spread u at sp_off + sp_step u, block u at bl_off + bl_step u
+  const u32 sp_off = CONTIG ? (u32)(sub * SUB + j) : (u32)(sub + (j << 8));
+  const u32 bl_off = CONTIG ? (u32)(sub * SUB + 16 * j) : (u32)(sub + (j << 12));
+  constexpr u32 sp_step = CONTIG ? T : T * 256;
+  constexpr u32 bl_step = CONTIG ? 1 : 256;
+  u32* __restrict__ ls = lds + sl * PAD;
+  auto spread = [&](int u) { return pad_idx(j + T * u); };
+  auto block = [&](int u) { return pad_idx(16 * j + u); };
+  auto tw_spread = [&](int l, int u) {
+    return CONTIG ? w[(1 << (s0 + l)) + (sub << l) + (u >> (4 - l))] : w[(1 << l) + (u >> (4 - l))];
+  };
+  auto tw_block = [&](int l, int u) {
+    // contiguous pass: entry (16 j + u) >> (8 - l) = j 2^(l-4) + i of the chunk's block, stored at 16 i + j
+    return CONTIG ? w[(1 << (s0 + l)) + (sub << l) + (((u >> (8 - l)) << 4) | j)]
+                  : w[(1 << l) + ((16 * j + u) >> (L - l))];
+  };
   u64 x[NTT_R];
 
   if (!INV) {
 #pragma unroll
-    for (int u = 0; u < NTT_R; ++u) x[u] = pin[(size_t)(j + T * u) << log_stride];
-    // stages 0..3: element v = j + T u is held in x[u]
+    for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int hu = 8 >> l;
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) {
-        if (u & hu) continue;
-        const int v = j + T * u;
-        const int blk = (hi << l) | (v >> (L - l));
-        fwd_bfly(x[u], x[u + hu], w[(1 << (s0 + l)) + blk], q, q4);
-      }
+      for (int u = 0; u < NTT_R; ++u)
+        if (!(u & hu)) fwd_bfly(x[u], x[u + hu], tw_spread(l, u), nq, q4);
     }
     if (L > 4) {
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) ls[pad_idx(j + T * u)] = x[u];
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = ls[pad_idx(16 * j + u)];
-      // stages 4..L-1: element v = 16 j + u is held in x[u]
+      lds_exchange<false>(x, ls, spread, block);
 #pragma unroll
       for (int l = 4; l < L; ++l) {
         const int half = 1 << (L - 1 - l);
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) {
-          if (u & half) continue;
-          const int v = 16 * j + u;
-          const int blk = (hi << l) | (v >> (L - l));
-          fwd_bfly(x[u], x[u + half], w[(1 << (s0 + l)) + blk], q, q4);
-        }
+        for (int u = 0; u < NTT_R; ++u)
+          if (!(u & half)) fwd_bfly(x[u], x[u + half], tw_block(l, u), nq, q4);
       }
     }
-    if (final_pass) {
+    if (FINAL) {
       const ModInfo m = mods[rj.y];
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = reduce64(x[u], m);
     }
-    if (L > 4) {
-      if (contiguous) {
-        __syncthreads();
+    if (CONTIG) {
+      lds_exchange<true>(x, ls, block, spread);
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) ls[pad_idx(16 * j + u)] = x[u];
-        __syncthreads();
+      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
+    } else if (L > 4) {
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) p[(size_t)(j + T * u) << log_stride] = ls[pad_idx(j + T * u)];
-      } else {
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u) p[(size_t)(16 * j + u) << log_stride] = x[u];
-      }
+      for (int u = 0; u < NTT_R; ++u) (a + bl_step * u)[bl_off] = x[u];
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) p[(size_t)(j + T * u) << log_stride] = x[u];
+      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
     }
   } else {
-    // ownership v = 16 j + u for stages L-1 .. 4
-    if (L > 4 && contiguous) {
+    // Inputs are below 4q; after k executed stages all values are below 4q 2^k.
+    if (CONTIG) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) ls[pad_idx(j + T * u)] = pin[(size_t)(j + T * u) << log_stride];
-      __syncthreads();
+      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
+      lds_exchange<false>(x, ls, spread, block);
+    } else if (L > 4) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = ls[pad_idx(16 * j + u)];
+      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + bl_step * u)[bl_off];
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = pin[(size_t)(16 * j + u) << log_stride];
+      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
     }
     if (L > 4) {
 #pragma unroll
       for (int l = L - 1; l >= 4; --l) {
         const int half = 1 << (L - 1 - l);
+        const u64 b = q4 << (L - 1 - l);
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) {
-          if (u & half) continue;
-          const int v = 16 * j + u;
-          const int blk = (hi << l) | (v >> (L - l));
-          inv_bfly(x[u], x[u + half], w[(1 << (s0 + l)) + blk], q, q4);
-        }
+        for (int u = 0; u < NTT_R; ++u)
+          if (!(u & half)) inv_bfly(x[u], x[u + half], tw_block(l, u), nq, b);
       }
-      if (contiguous) __syncthreads();
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) ls[pad_idx(16 * j + u)] = x[u];
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = ls[pad_idx(j + T * u)];
+      if (CONTIG)
+        lds_exchange<true>(x, ls, block, spread);
+      else
+        lds_exchange<false>(x, ls, block, spread);
     }
-    // stages 3..0: element v = j + T u is held in x[u]
-    const bool merge_ninv = final_pass && s0 == 0;
 #pragma unroll
     for (int l = 3; l >= 0; --l) {
       const int hu = 8 >> l;
+      const u64 b = q4 << (L - 1 - l);
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         if (u & hu) continue;
-        const int v = j + T * u;
-        const int blk = (hi << l) | (v >> (L - l));
-        if (l == 0 && merge_ninv) {
+        if (l == 0 && FINAL) {
+          // last stage of the transform, N^-1 merged into both outputs
           const PrimeConsts k = pc[rj.y];
-          u64 s = x[u] + x[u + hu];
-          u64 d = x[u] + q4 - x[u + hu];
-          x[u] = mul_shoup_lazy4(s, k.ninv, k.ninv_sh, q);
-          x[u + hu] = mul_shoup_lazy4(d, k.w1ninv, k.w1ninv_sh, q);
+          const u64 s = x[u] + x[u + hu];
+          const u64 d = x[u] + b - x[u + hu];
+          x[u] = mul_shoup_lazy4n(s, k.ninv, k.ninv_sh, nq);
+          x[u + hu] = mul_shoup_lazy4n(d, k.w1ninv, k.w1ninv_sh, nq);
         } else {
-          inv_bfly(x[u], x[u + hu], w[(1 << (s0 + l)) + blk], q, q4);
+          inv_bfly(x[u], x[u + hu], tw_spread(l, u), nq, b);
         }
       }
     }
-    if (final_pass) {
+    if (FINAL) {
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = csub(csub(x[u], 2 * q), q);
+    } else {
+      const u64 one_sh = mods[rj.y].one_sh;
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) x[u] = reduce_lazy4(x[u], one_sh, nq);
     }
 #pragma unroll
-    for (int u = 0; u < NTT_R; ++u) p[(size_t)(j + T * u) << log_stride] = x[u];
+    for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
   }
 }
 
 template <bool INV>
-void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0, int final_pass,
+void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0,
                  const NttSrc& src) {
   const int sub = 1 << L;
   const int per_wg = NTT_THREADS * NTT_R / sub;  // sub-transforms per workgroup
@@ -244,13 +266,15 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   const int padded = (pa.groups + 7) / 8 * 8;
   dim3 grid((unsigned)(padded * batch)), block(NTT_THREADS);
   const ulonglong2* tw = INV ? c.d_tw_inv : c.d_tw_fwd;
-  c.begin_launch();
+  // the strided pass is the 2^L x 256 column view (s0 == 0), the contiguous one the last 8 stages
   const bool contiguous = s0 + L == c.log_n;
+  if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
+  c.begin_launch();
   switch (L * 2 + (contiguous ? 1 : 0)) {
 #define HETAL_NTT_CASE(LL, CC)                                                                           \
   case LL * 2 + CC:                                                                                    \
     hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, \
-                       c.d_pc, c.log_n, s0, final_pass);                                               \
+                       c.d_pc, c.log_n, s0);                                                           \
     break;
     HETAL_NTT_CASE(4, 0)
     HETAL_NTT_CASE(5, 0)
@@ -270,16 +294,16 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
-  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, 0, src);
-  launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, 1, NttSrc{});
+  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src);
+  launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, NttSrc{});
   c.counters[6] += (int64_t)rows.count * batch;
 }
 
 void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
-  launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, 0, src);
-  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, 1, NttSrc{});
+  launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, src);
+  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{});
   c.counters[6] += (int64_t)rows.count * batch;
 }
 
