@@ -19,6 +19,7 @@ Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -79,6 +80,161 @@ def encrypt_inputs(ctx, sk, X, W, PY):
     return gx, gw, gpy
 
 
+# ---------------------------------------------------------------- profile summaries
+# rocprofv3 kernel names -> the library's timing classes (N = 2^16: every NTT pass has 256-point sub-transforms)
+PROFILE_CLASSES = [
+    ("ntt_pass_kernel<8, false, false>", "ntt_fwd_strided"),
+    ("ntt_pass_kernel<8, false, true>", "ntt_fwd_contig"),
+    ("ntt_pass_kernel<8, true, true>", "ntt_inv_contig"),
+    ("ntt_pass_kernel<8, true, false>", "ntt_inv_strided"),
+    ("modup_kernel", "modup"),
+    ("inner_product", "inner_product"),
+    ("moddown_conv_kernel", "moddown_conv"),
+    ("moddown_combine_kernel", "moddown_combine"),
+    ("rescale_", "rescale"),
+]
+PROFILE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "kernels_n16l12_matmul_step.md")
+
+
+def kernel_sources_digest():
+    """sha256 over the HIP sources: a recorded counter profile is only valid for the sources it was taken on."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2403_14111_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_class(name):
+    for key, cls in PROFILE_CLASSES:
+        if key in name:
+            return cls
+    return None
+
+
+def timed_window(names, steps):
+    """Indices of the last `steps` repetitions of the step's kernel sequence (the timed region)."""
+    # The largest period whose `steps` copies end the trace: shorter accidental periods (a step ending in two
+    # equal kernels) are passed over, and multiples of the true period would need more identical steps than ran.
+    n = len(names)
+    for p in range(n // steps, 0, -1):
+        lo = n - steps * p
+        if all(names[i] == names[i + p] for i in range(n - p - 1, lo - 1, -1)):
+            return lo, n, p
+    raise SystemExit("no %d-fold repeated step found in the trace" % steps)
+
+
+def read_dispatches(path, counter=None):
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    if counter is None:
+        out = [(int(r["Start_Timestamp"]), r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]), 0.0) for r in rows]
+    else:
+        per = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            d = per.setdefault(r["Dispatch_Id"], [int(r["Start_Timestamp"]), r["Kernel_Name"],
+                                                  int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                                                  int(r["Grid_Size"]), 0.0])
+            d[4] += float(r["Counter_Value"])
+        out = [tuple(v) for v in per.values()]
+    out.sort()
+    # the calibration copy closes a profile run: split it off
+    assert "copyBuffer" in out[-1][1], "profile run does not end with the calibration copy"
+    return out[:-1], out[-1]
+
+
+def trace_summary(directory, steps, pmc_steps, bench=None):
+    """Markdown summary of rocprofv3 output under `directory` (from bench.py --profile runs)."""
+    import glob
+    copy_kib = 256 * 1024
+    trace = glob.glob(os.path.join(directory, "trace", "*kernel_trace.csv"))[0]
+    disp, _ = read_dispatches(trace)
+    lo, hi, per_step = timed_window([d[1] for d in disp], steps)
+    agg = {}
+    for t, name, dur, grid, _ in disp[lo:hi]:
+        cls = profile_class(name) or (re.findall(r"(\w+)(?:<[^>]*>)?\(", name) or [name])[0][:40]
+        a = agg.setdefault(cls, [0, 0.0, 0.0])
+        a[0] += 1
+        a[1] += dur
+        if cls.startswith("ntt_"):
+            a[2] += grid * 16 * 16.0  # 16 residues per thread, each read and written once
+    lines = ["# Kernel profile: DiagABT + DiagATB step, N=2^16, level 11 (bench workload)", "",
+             "Commands (repository root; DIR is any output folder):", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d DIR/trace -o trace -- "
+             "python bench.py --profile --steps %d --warmup 2" % steps,
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/FETCH_SIZE -o pmc -- "
+             "python bench.py --profile --steps %d --warmup 1" % pmc_steps,
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/WRITE_SIZE -o pmc -- "
+             "python bench.py --profile --steps %d --warmup 1" % pmc_steps,
+             ] + (["    python bench.py --steps %d --warmup 2 --no-cpu-baseline > BENCH.json" % steps] if bench else []) + [
+             "    python bench.py --trace-summary DIR --steps %d --pmc-steps %d%s" % (
+                 steps, pmc_steps, " --bench-json BENCH.json" if bench else ""), "",
+             "Timed region: the last %d steps of the trace (%d kernels per step).  HBM MB/launch: FETCH_SIZE and "
+             "WRITE_SIZE (KiB per dispatch) scaled by what they read for the closing plain copy, averaged over the "
+             "class's launches in the counter runs' timed steps." % (steps, per_step), "",
+             "| kernel | launches/step | avg us | ms/step | algorithmic GB/s | HBM MB/launch (counters) |",
+             "|---|---|---|---|---|---|"]
+    traffic = {}
+    scales = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        f = glob.glob(os.path.join(directory, counter, "*counter_collection.csv"))
+        if not f:
+            continue
+        d, cal = read_dispatches(f[0], counter)
+        scales[counter] = copy_kib / cal[4] if cal[4] > 0 else None
+        plo, phi, _ = timed_window([x[1] for x in d], pmc_steps)
+        for t, name, dur, grid, v in d[plo:phi]:
+            cls = profile_class(name)
+            if cls:
+                e = traffic.setdefault(cls, {}).setdefault(counter, [0, 0.0])
+                e[0] += 1
+                e[1] += v * 1024.0 * scales[counter]
+    per_launch = {}
+    for cls, e in traffic.items():
+        if "FETCH_SIZE" in e and "WRITE_SIZE" in e:
+            per_launch[cls] = e["FETCH_SIZE"][1] / e["FETCH_SIZE"][0] + e["WRITE_SIZE"][1] / e["WRITE_SIZE"][0]
+    for cls, (n, dur, byts) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:16]:
+        gbs = "%.0f" % (byts / dur) if byts else ""
+        tr = "%.1f" % (per_launch[cls] / 1e6) if cls in per_launch else ""
+        lines.append("| %s | %d | %.1f | %.3f | %s | %s |" % (cls, n // steps, dur / n / 1e3, dur / steps / 1e6, gbs, tr))
+    if bench:
+        b = json.load(open(bench))
+        r = b["roofline"]
+        k = r["kernel"]
+        lines += ["", "bench.py (HIP events on the library stream, %d steps): %.3f matmuls/s, %.3f ms/step; dominant "
+                  "kernel %s: %.2f us per launch (trace above: %.2f us), %.0f algorithmic MB per launch." % (
+                      b["steps"], b["value"], b["ms_per_step"], k, r["avg_launch_us"],
+                      agg[k][1] / agg[k][0] / 1e3 if k in agg else float("nan"), r["avg_bytes_per_launch"] / 1e6)]
+    lines += ["", "Counter scale factors from the closing plain copy of 256 MiB each way: " +
+              ", ".join("%s x%.3f" % (k, v) for k, v in scales.items() if v), "",
+              "traffic_json: " + json.dumps({"bytes_per_launch": {k: round(v) for k, v in per_launch.items()},
+                                             "avg_us": {k: round(a[1] / a[0] / 1e3, 2) for k, a in agg.items()
+                                                        if k in dict(PROFILE_CLASSES).values()},
+                                             "sources_sha256": kernel_sources_digest()})]
+    return "\n".join(lines)
+
+
+def recorded_traffic(cls):
+    """HBM bytes per launch of class `cls` from the committed counter profile, if taken on these sources."""
+    try:
+        with open(PROFILE_FILE) as fh:
+            for line in fh:
+                if line.startswith("traffic_json: "):
+                    rec = json.loads(line[len("traffic_json: "):])
+                    if rec.get("sources_sha256") == kernel_sources_digest():
+                        return rec["bytes_per_launch"].get(cls)
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(X, W, gpu_abt_coeffs):
     """The oracle (never tuned) on one full DiagABT of the same workload."""
     from oracle import ckks
@@ -114,7 +270,7 @@ def cpu_baseline(X, W, gpu_abt_coeffs):
     same = gpu_abt_coeffs is not None and np.array_equal(gpu_abt_coeffs, out[0].c)
     return dict(value=1.0 / dt, unit="matmuls/s", cores=threads, kind="oracle",
                 sample="one full DiagABT of the forward product (128x768x16, N=2^16, level 11): %.1f s on %d "
-                       "OpenMP threads (%s)" % (dt, threads, os.uname().nodename),
+                       "OpenMP threads" % (dt, threads),
                 seconds=dt), same
 
 
@@ -128,7 +284,16 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler run: warmup + timed steps + one plain copy of 256 MiB (counter calibration); "
                          "no event-timing pass, HRot loop or oracle leg")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="no GPU: summarise rocprofv3 output of --profile runs under DIR (trace/, FETCH_SIZE/, "
+                         "WRITE_SIZE/) as markdown; --steps is the trace run's step count, --pmc-steps the counter "
+                         "runs' one")
+    ap.add_argument("--pmc-steps", type=int, default=2)
+    ap.add_argument("--bench-json", metavar="FILE", help="with --trace-summary: a bench.py output line to compare")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.steps, args.pmc_steps, args.bench_json))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
@@ -215,8 +380,9 @@ def main():
     avg_ms = d["ms"] / max(d["launches"], 1)
     avg_bytes = d["bytes"] / max(d["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = recorded_traffic(dom)
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     avg_launch_us=round(avg_ms * 1e3, 2), avg_bytes_per_launch=avg_bytes,
                     launches_per_step=d["launches"] // args.steps)
     kernel_share = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3), launches_per_step=v["launches"] // args.steps,

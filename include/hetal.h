@@ -225,15 +225,19 @@ int hetal_counters_get(const hetal_ctx* ctx, int64_t* out8);
 int hetal_counters_reset(hetal_ctx* ctx);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch (adds two event records per launch while enabled).  Classes:
- * [0] NTT / inverse NTT passes, [1] ModUp basis conversion, [2] key inner
- * product, [3] ModDown basis conversion, [4] ModDown combine, [5] rescale,
- * [6] elementwise, [7] encode / decode.  enable(on) clears what was
- * collected; get synchronises and returns, per class, the summed kernel
- * time in ms, the launch count and the summed algorithmic HBM bytes (each
- * operand read once and each result written once). */
+ * every launch (adds two event records per launch while enabled).  There are
+ * hetal_timing_classes() classes: [0] forward NTT, strided first pass,
+ * [1] forward NTT, contiguous final pass, [2] inverse NTT, contiguous first
+ * pass, [3] inverse NTT, strided final pass, [4] ModUp basis conversion,
+ * [5] key inner product, [6] ModDown basis conversion, [7] ModDown combine,
+ * [8] rescale, [9] elementwise, [10] encode / decode.  enable(on) clears what
+ * was collected; get synchronises and fills, per class, the summed kernel time
+ * in ms, the launch count and the summed algorithmic HBM bytes (each operand
+ * read once and each result written once) into caller arrays of
+ * hetal_timing_classes() entries. */
+int hetal_timing_classes(void);
 int hetal_timing_enable(hetal_ctx* ctx, int on);
-int hetal_timing_get(hetal_ctx* ctx, double* ms8, int64_t* launches8, double* bytes8);
+int hetal_timing_get(hetal_ctx* ctx, double* ms, int64_t* launches, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -657,22 +657,24 @@ int hetal_timing_enable(hetal_ctx* ctx, int on) {
   });
 }
 
-int hetal_timing_get(hetal_ctx* ctx, double* ms8, int64_t* launches8, double* bytes8) {
+int hetal_timing_classes(void) { return NUM_KC; }
+
+int hetal_timing_get(hetal_ctx* ctx, double* ms, int64_t* launches, double* bytes) {
   return guarded([&] {
-    need(ctx && ms8 && launches8 && bytes8, HETAL_E_INVALID_ARG, "null argument");
+    need(ctx && ms && launches && bytes, HETAL_E_INVALID_ARG, "null argument");
     Context& c = ctx->c;
     HCHECK(hipStreamSynchronize(c.stream));
     for (int k = 0; k < NUM_KC; ++k) {
-      ms8[k] = 0.0;
-      launches8[k] = 0;
-      bytes8[k] = 0.0;
+      ms[k] = 0.0;
+      launches[k] = 0;
+      bytes[k] = 0.0;
     }
     for (auto& t : c.timed) {
-      float ms = 0.f;
-      HCHECK(hipEventElapsedTime(&ms, t.start, t.stop));
-      ms8[t.cls] += ms;
-      launches8[t.cls] += 1;
-      bytes8[t.cls] += t.bytes;
+      float e = 0.f;
+      HCHECK(hipEventElapsedTime(&e, t.start, t.stop));
+      ms[t.cls] += e;
+      launches[t.cls] += 1;
+      bytes[t.cls] += t.bytes;
     }
   });
 }

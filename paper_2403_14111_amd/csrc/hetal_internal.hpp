@@ -116,7 +116,22 @@ struct Tmp {
 };
 
 // Kernel classes for the optional per-launch HIP-event timing.
-enum KernelClass { KC_NTT = 0, KC_MODUP, KC_INNER, KC_MODDOWN, KC_COMBINE, KC_RESCALE, KC_ELEMWISE, KC_ENCODE, NUM_KC };
+// NTT passes: forward strided (first), forward contiguous (final), inverse contiguous (first), inverse
+// strided (final).
+enum KernelClass {
+  KC_NTT_FWD_STRIDED = 0,
+  KC_NTT_FWD_CONTIG,
+  KC_NTT_INV_CONTIG,
+  KC_NTT_INV_STRIDED,
+  KC_MODUP,
+  KC_INNER,
+  KC_MODDOWN,
+  KC_COMBINE,
+  KC_RESCALE,
+  KC_ELEMWISE,
+  KC_ENCODE,
+  NUM_KC
+};
 
 struct TimedLaunch {
   hipEvent_t start, stop;

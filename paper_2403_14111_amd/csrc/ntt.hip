@@ -286,7 +286,9 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
     default:
       fail(HETAL_E_PARAMS, "unsupported NTT pass size");
   }
-  c.end_launch(KC_NTT, 16.0 * c.n * rows.count * batch);  // every residue read and written once
+  const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
+                      : (contiguous ? KC_NTT_FWD_CONTIG : KC_NTT_FWD_STRIDED);
+  c.end_launch(cls, 16.0 * c.n * rows.count * batch);  // every residue read and written once
 }
 
 }  // namespace

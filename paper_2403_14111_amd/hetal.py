@@ -99,11 +99,12 @@ _SIGS = {
     "hetal_counters_get": (ctypes.c_int, [_vp, _i64p]),
     "hetal_counters_reset": (ctypes.c_int, [_vp]),
     "hetal_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "hetal_timing_classes": (ctypes.c_int, []),
     "hetal_timing_get": (ctypes.c_int, [_vp, _dblp, _i64p, _dblp]),
 }
 
-KERNEL_CLASSES = ["ntt", "modup", "inner_product", "moddown_conv", "moddown_combine", "rescale", "elementwise",
-                  "encode"]
+KERNEL_CLASSES = ["ntt_fwd_strided", "ntt_fwd_contig", "ntt_inv_contig", "ntt_inv_strided", "modup", "inner_product",
+                  "moddown_conv", "moddown_combine", "rescale", "elementwise", "encode"]
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -236,9 +237,12 @@ class Context:
         _check(_lib.hetal_timing_enable(self._h, 1 if on else 0))
 
     def timing_get(self):
-        ms = np.zeros(8)
-        n = np.zeros(8, dtype=np.int64)
-        b = np.zeros(8)
+        k = _lib.hetal_timing_classes()
+        if k != len(KERNEL_CLASSES):
+            raise HetalError(-1, "library reports %d timing classes, binding knows %d" % (k, len(KERNEL_CLASSES)))
+        ms = np.zeros(k)
+        n = np.zeros(k, dtype=np.int64)
+        b = np.zeros(k)
         _check(_lib.hetal_timing_get(self._h, ms.ctypes.data_as(_dblp), n.ctypes.data_as(_i64p),
                                      b.ctypes.data_as(_dblp)))
         return {k: dict(ms=float(ms[i]), launches=int(n[i]), bytes=float(b[i])) for i, k in enumerate(KERNEL_CLASSES)}
