@@ -83,14 +83,14 @@ def encrypt_inputs(ctx, sk, X, W, PY):
 # ---------------------------------------------------------------- profile summaries
 # rocprofv3 kernel names -> the library's timing classes (N = 2^16: every NTT pass has 256-point sub-transforms)
 PROFILE_CLASSES = [
-    ("ntt_pass_kernel<8, false, false>", "ntt_fwd_strided"),
-    ("ntt_pass_kernel<8, false, true>", "ntt_fwd_contig"),
-    ("ntt_pass_kernel<8, true, true>", "ntt_inv_contig"),
-    ("ntt_pass_kernel<8, true, false>", "ntt_inv_strided"),
+    ("ntt_pass_kernel<8, false, false, false>", "ntt_fwd_strided"),
+    ("ntt_pass_kernel<8, false, true, false>", "ntt_fwd_contig"),
+    ("ntt_pass_kernel<8, false, true, true>", "ntt_fwd_epilogue"),
+    ("ntt_pass_kernel<8, true, true, false>", "ntt_inv_contig"),
+    ("ntt_pass_kernel<8, true, false, false>", "ntt_inv_strided"),
     ("modup_kernel", "modup"),
     ("inner_product", "inner_product"),
     ("moddown_conv_kernel", "moddown_conv"),
-    ("moddown_combine_kernel", "moddown_combine"),
     ("rescale_", "rescale"),
 ]
 PROFILE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "kernels_n16l12_matmul_step.md")

@@ -116,17 +116,17 @@ struct Tmp {
 };
 
 // Kernel classes for the optional per-launch HIP-event timing.
-// NTT passes: forward strided (first), forward contiguous (final), inverse contiguous (first), inverse
-// strided (final).
+// NTT passes: forward strided (first), forward contiguous (final; plain, or with the combine epilogue),
+// inverse contiguous (first), inverse strided (final).
 enum KernelClass {
   KC_NTT_FWD_STRIDED = 0,
   KC_NTT_FWD_CONTIG,
+  KC_NTT_FWD_EPILOGUE,
   KC_NTT_INV_CONTIG,
   KC_NTT_INV_STRIDED,
   KC_MODUP,
   KC_INNER,
   KC_MODDOWN,
-  KC_COMBINE,
   KC_RESCALE,
   KC_ELEMWISE,
   KC_ENCODE,
@@ -223,7 +223,32 @@ struct NttSrc {
 
 // NTT over `rows` (row index inside a batch item, prime index) of `batch`
 // items spaced batch_stride words apart.  Input and output reduced to [0, q).
-void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{});
+// Optional epilogue of a forward NTT over ciphertext rows (row table ROWS_CT, row r = p l + i): the
+// transform x of row (p, i) is not stored; the last pass stores instead
+//   out[p][i] = (a[p][i] - x) cst[i] + add0[i](gathered through tau_g, p = 0) + add1[i](p = 1) + addx[p][i]
+// mod q_i, every addend optional.  ModDown ends this way (a = the Q part of the key inner product,
+// cst = P^-1 mod q_i) and so does the rescale (a = the input, cst = q_l^-1 mod q_i).
+struct NttEpilogue {
+  const u64* a = nullptr;
+  size_t a_stride = 0;       // words between items
+  int a_poly_rows = 0;       // rows between a[0][i] and a[1][i]
+  int l = 0;                 // limbs per output polynomial
+  const u64* cst = nullptr;  // device arrays indexed by prime
+  const u64* cst_sh = nullptr;
+  u64* out = nullptr;
+  size_t out_stride = 0;
+  const u64* add0 = nullptr;  // [l][N] per item
+  size_t add0_stride = 0;
+  int gather = 0;            // add0 read at the Galois source of each position
+  const u64* add1 = nullptr;  // [l][N] per item
+  size_t add1_stride = 0;
+  const u64* addx = nullptr;  // [2][l][N] per item
+  size_t addx_stride = 0;
+  u32 g[MAX_BATCH];
+};
+
+void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
+                 const NttEpilogue* epi = nullptr);
 void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{});
 
 struct KsItem {

@@ -97,16 +97,19 @@ __device__ __forceinline__ void lds_exchange(u64 (&x)[NTT_R], u32* __restrict__ 
 // v = j + T u ("spread"), in stages 4..L-1 element v = 16 j + u ("block").  The twiddle of stage l
 // for element v is psi_rev[2^(s0 + l) + (c 2^l) + (v >> (L - l))] (c = 0 in the strided pass, where
 // in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
-template <int L, bool INV, bool CONTIG>
+// EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.
+template <int L, bool INV, bool CONTIG, bool EPI>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const ulonglong2* __restrict__ tw,
                                                               const ModInfo* __restrict__ mods,
-                                                              const PrimeConsts* __restrict__ pc, int log_n, int s0) {
+                                                              const PrimeConsts* __restrict__ pc, int log_n, int s0,
+                                                              NttEpilogue epi) {
   constexpr int SUB = 1 << L;
   constexpr int T = SUB / NTT_R;        // threads per sub-transform
   constexpr int S = NTT_THREADS / T;    // sub-transforms per workgroup
   constexpr bool FINAL = INV != CONTIG;
   static_assert(!CONTIG || L == 8, "the contiguous pass covers the last 8 stages");
+  static_assert(!EPI || (CONTIG && !INV), "the epilogue belongs to the last forward pass");
   // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
   // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
   // neighbouring slices in lockstep fall on distinct banks.
@@ -177,7 +180,27 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = reduce64(x[u], m);
     }
-    if (CONTIG) {
+    if (CONTIG && EPI) {
+      lds_exchange<true>(x, ls, block, spread);
+      const int p = rj.x >= epi.l ? 1 : 0;
+      const int i = rj.y;
+      const u64 cst = epi.cst[i], cst_sh = epi.cst_sh[i];
+      const u64* __restrict__ ea = epi.a + item * epi.a_stride + ((size_t)p * epi.a_poly_rows + i) * n;
+      u64* __restrict__ eo = epi.out + item * epi.out_stride + (size_t)rj.x * n;
+      const u64* __restrict__ own = p == 0 ? (epi.add0 ? epi.add0 + item * epi.add0_stride + (size_t)i * n : nullptr)
+                                           : (epi.add1 ? epi.add1 + item * epi.add1_stride + (size_t)i * n : nullptr);
+      const u64* __restrict__ both = epi.addx ? epi.addx + item * epi.addx_stride + (size_t)rj.x * n : nullptr;
+      const u32 g = epi.g[item];
+      const bool gather = p == 0 && epi.gather && g != 1;
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) {
+        const u32 k = sp_off + sp_step * u;
+        u64 v = mul_shoup(sub_mod(ea[k], x[u], q), cst, cst_sh, q);
+        if (own) v = add_mod(v, own[gather ? galois_source(k, g, log_n) : k], q);
+        if (both) v = add_mod(v, both[k], q);
+        eo[k] = v;
+      }
+    } else if (CONTIG) {
       lds_exchange<true>(x, ls, block, spread);
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
@@ -249,7 +272,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 
 template <bool INV>
 void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0,
-                 const NttSrc& src) {
+                 const NttSrc& src, const NttEpilogue* epi = nullptr) {
   const int sub = 1 << L;
   const int per_wg = NTT_THREADS * NTT_R / sub;  // sub-transforms per workgroup
   const int nsub = c.n / sub;
@@ -269,35 +292,50 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   // the strided pass is the 2^L x 256 column view (s0 == 0), the contiguous one the last 8 stages
   const bool contiguous = s0 + L == c.log_n;
   if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
+  if (epi && (INV || !contiguous)) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
+  if (epi && batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "NTT epilogue batch");
+  const NttEpilogue none{};
   c.begin_launch();
-  switch (L * 2 + (contiguous ? 1 : 0)) {
-#define HETAL_NTT_CASE(LL, CC)                                                                           \
-  case LL * 2 + CC:                                                                                    \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, \
-                       c.d_pc, c.log_n, s0);                                                           \
+  if (epi) {
+    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod,
+                       c.d_pc, c.log_n, s0, *epi);
+  } else {
+    switch (L * 2 + (contiguous ? 1 : 0)) {
+#define HETAL_NTT_CASE(LL, CC)                                                                                \
+  case LL * 2 + CC:                                                                                         \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC, false>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, \
+                       c.d_pc, c.log_n, s0, none);                                                          \
     break;
-    HETAL_NTT_CASE(4, 0)
-    HETAL_NTT_CASE(5, 0)
-    HETAL_NTT_CASE(6, 0)
-    HETAL_NTT_CASE(7, 0)
-    HETAL_NTT_CASE(8, 0)
-    HETAL_NTT_CASE(8, 1)
+      HETAL_NTT_CASE(4, 0)
+      HETAL_NTT_CASE(5, 0)
+      HETAL_NTT_CASE(6, 0)
+      HETAL_NTT_CASE(7, 0)
+      HETAL_NTT_CASE(8, 0)
+      HETAL_NTT_CASE(8, 1)
 #undef HETAL_NTT_CASE
-    default:
-      fail(HETAL_E_PARAMS, "unsupported NTT pass size");
+      default:
+        fail(HETAL_E_PARAMS, "unsupported NTT pass size");
+    }
   }
-  const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
-                      : (contiguous ? KC_NTT_FWD_CONTIG : KC_NTT_FWD_STRIDED);
-  c.end_launch(cls, 16.0 * c.n * rows.count * batch);  // every residue read and written once
+  if (epi) {
+    // per word: the pass input and a read, out written; addx on every row, add0 / add1 on half of them
+    const double per_word = 24.0 + (epi->addx ? 8.0 : 0.0) + (epi->add0 ? 4.0 : 0.0) + (epi->add1 ? 4.0 : 0.0);
+    c.end_launch(KC_NTT_FWD_EPILOGUE, per_word * c.n * rows.count * batch);
+  } else {
+    const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
+                        : (contiguous ? KC_NTT_FWD_CONTIG : KC_NTT_FWD_STRIDED);
+    c.end_launch(cls, 16.0 * c.n * rows.count * batch);  // every residue read and written once
+  }
 }
 
 }  // namespace
 
-void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
+void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
+                 const NttEpilogue* epi) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
   launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src);
-  launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, NttSrc{});
+  launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, NttSrc{}, epi);
   c.counters[6] += (int64_t)rows.count * batch;
 }
 

@@ -13,6 +13,12 @@ constexpr int TPB = 256;
 
 inline dim3 grid_for(const Context& c, int y, int z) { return dim3((unsigned)(c.n / TPB), (unsigned)y, (unsigned)z); }
 
+// Device address of a field of a device-resident table (address arithmetic only, nothing is read).
+template <class T, class S>
+const T* device_field(const S* table, size_t offset) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(table) + offset);
+}
+
 // ---------------------------------------------------------------- ModUp
 // For digit j (blockIdx.y): every row of the extended basis outside the digit q_0..q_l, p_0..p_{K-1} receives the fast
 // basis conversion of the digit's coefficient-form residues
@@ -175,52 +181,6 @@ __global__ void __launch_bounds__(TPB) moddown_conv_kernel(const u64* __restrict
   }
 }
 
-// out_p[i] = (acc_p[i] - conv_p[i]) P^-1 + add_p[i]  (add_0 gathered by the Galois map when asked).
-struct CombineArgs {
-  const u64* add0;
-  size_t add0_stride;
-  const u64* add1;
-  size_t add1_stride;
-  const u64* addx;  // optional ciphertext [2][l][N] added to both outputs (x + Lrot(x) in one pass)
-  size_t addx_stride;
-  u32 g[MAX_BATCH];
-  int gather;
-};
-
-__global__ void __launch_bounds__(TPB) moddown_combine_kernel(const u64* __restrict__ acc, size_t acc_stride,
-                                                              const u64* __restrict__ conv, size_t conv_stride,
-                                                              u64* __restrict__ out, size_t out_stride,
-                                                              CombineArgs ca, const ModDownTab* __restrict__ tab,
-                                                              const ModInfo* __restrict__ mods, int log_n, int level,
-                                                              int num_p) {
-  const int n = 1 << log_n;
-  const int l = level + 1;
-  const int ext = l + num_p;
-  const int k = blockIdx.x * TPB + threadIdx.x;
-  const int i = blockIdx.y;
-  const int item = blockIdx.z;
-  const u64 q = mods[i].q;
-  const u64 pinv = tab->pinv[i], pinv_sh = tab->pinv_sh[i];
-  const u64* __restrict__ a = acc + item * acc_stride;
-  const u64* __restrict__ cv = conv + item * conv_stride;
-  u64* __restrict__ o = out + item * out_stride;
-  u64 v0 = mul_shoup(sub_mod(a[(size_t)i * n + k], cv[(size_t)i * n + k], q), pinv, pinv_sh, q);
-  u64 v1 = mul_shoup(sub_mod(a[(size_t)(ext + i) * n + k], cv[(size_t)(l + i) * n + k], q), pinv, pinv_sh, q);
-  if (ca.add0) {
-    const u32 g = ca.g[item];
-    const u32 src = (ca.gather && g != 1) ? galois_source((u32)k, g, log_n) : (u32)k;
-    v0 = add_mod(v0, ca.add0[item * ca.add0_stride + (size_t)i * n + src], q);
-  }
-  if (ca.add1) v1 = add_mod(v1, ca.add1[item * ca.add1_stride + (size_t)i * n + k], q);
-  if (ca.addx) {
-    const u64* x = ca.addx + item * ca.addx_stride;
-    v0 = add_mod(v0, x[(size_t)i * n + k], q);
-    v1 = add_mod(v1, x[(size_t)(l + i) * n + k], q);
-  }
-  o[(size_t)i * n + k] = v0;
-  o[(size_t)(l + i) * n + k] = v1;
-}
-
 // ---------------------------------------------------------------- rescale
 // top[p][k] = coefficient-form limb `level` of poly p; spread[p][i][k] = [top]_centred mod q_i.
 __global__ void __launch_bounds__(TPB) rescale_spread_kernel(const u64* __restrict__ top, size_t top_stride,
@@ -239,23 +199,6 @@ __global__ void __launch_bounds__(TPB) rescale_spread_kernel(const u64* __restri
     const u64 r = reduce64(mag, m);
     o[(size_t)i * n + k] = negative ? neg_mod(r, m.q) : r;
   }
-}
-
-// out[p][i] = (in[p][i] - spread[p][i]) * q_level^-1 mod q_i, i < level.
-__global__ void __launch_bounds__(TPB) rescale_combine_kernel(const u64* __restrict__ in, size_t in_stride,
-                                                              const u64* __restrict__ spread, size_t spread_stride,
-                                                              u64* __restrict__ out, size_t out_stride,
-                                                              const RescaleTab* __restrict__ tab,
-                                                              const ModInfo* __restrict__ mods, int log_n, int level) {
-  const int n = 1 << log_n;
-  const int k = blockIdx.x * TPB + threadIdx.x;
-  const int i = blockIdx.y % level;
-  const int poly = blockIdx.y / level;
-  const u64 q = mods[i].q;
-  const u64* __restrict__ a = in + blockIdx.z * in_stride + ((size_t)poly * (level + 1) + i) * n;
-  const u64* __restrict__ s = spread + blockIdx.z * spread_stride + ((size_t)poly * level + i) * n;
-  u64* __restrict__ o = out + blockIdx.z * out_stride + ((size_t)poly * level + i) * n;
-  o[k] = mul_shoup(sub_mod(a[k], s[k], q), tab->inv[i], tab->inv_sh[i], q);
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -454,21 +397,25 @@ void key_switch(Context& c, const KsJob& job) {
   hipLaunchKernelGGL(moddown_conv_kernel, grid_for(c, 2, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
                      conv_words, c.d_moddown, c.d_mod, c.log_n, level, c.num_q, c.num_p);
   c.end_launch(KC_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
-  ntt_forward(c, conv, conv_words, m, ct_rows);
-  CombineArgs ca;
-  ca.add0 = job.add0;
-  ca.add0_stride = job.add0_stride;
-  ca.add1 = job.add1;
-  ca.add1_stride = job.add1_stride;
-  ca.addx = job.addx;
-  ca.addx_stride = job.addx_stride;
-  ca.gather = job.add0_galois ? 1 : 0;
-  for (int i = 0; i < MAX_BATCH; ++i) ca.g[i] = i < m ? job.item[i].g : 1;
-  c.begin_launch();
-  hipLaunchKernelGGL(moddown_combine_kernel, grid_for(c, l, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
-                     conv_words, job.out, job.out_stride, ca, c.d_moddown, c.d_mod, c.log_n, level, c.num_p);
-  c.end_launch(KC_COMBINE,
-               8.0 * n * m * (4.0 * l + (job.add0 ? l : 0) + (job.add1 ? l : 0) + (job.addx ? 2.0 * l : 0) + 2.0 * l));
+  // ... and the combine (acc_Q - conv) P^-1 + addends as the epilogue of the NTT's last pass
+  NttEpilogue epi;
+  epi.a = acc.p;
+  epi.a_stride = acc_words;
+  epi.a_poly_rows = ext;
+  epi.l = l;
+  epi.cst = device_field<u64>(c.d_moddown, offsetof(ModDownTab, pinv));
+  epi.cst_sh = device_field<u64>(c.d_moddown, offsetof(ModDownTab, pinv_sh));
+  epi.out = job.out;
+  epi.out_stride = job.out_stride;
+  epi.add0 = job.add0;
+  epi.add0_stride = job.add0_stride;
+  epi.gather = job.add0_galois ? 1 : 0;
+  epi.add1 = job.add1;
+  epi.add1_stride = job.add1_stride;
+  epi.addx = job.addx;
+  epi.addx_stride = job.addx_stride;
+  for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = i < m ? job.item[i].g : 1;
+  ntt_forward(c, conv, conv_words, m, ct_rows, NttSrc{}, &epi);
   c.counters[5] += m;
 }
 
@@ -526,11 +473,19 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
   hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, batch), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
                      2 * (size_t)level * n, c.d_mod, c.log_n, level);
   c.end_launch(KC_RESCALE, 8.0 * n * batch * (2.0 + 2.0 * level));
-  ntt_forward(c, spread, 2 * (size_t)level * n, batch, c.rows(ROWS_CT, level - 1));
-  c.begin_launch();
-  hipLaunchKernelGGL(rescale_combine_kernel, grid_for(c, 2 * level, batch), dim3(TPB), 0, c.stream, in, in_stride,
-                     spread.p, 2 * (size_t)level * n, out, out_stride, c.d_rescale + level, c.d_mod, c.log_n, level);
-  c.end_launch(KC_RESCALE, 8.0 * n * batch * 6.0 * level);
+  // out = (in - spread) q_level^-1, as the epilogue of the spread rows' NTT
+  if (batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "rescale batch");
+  NttEpilogue epi;
+  epi.a = in;
+  epi.a_stride = in_stride;
+  epi.a_poly_rows = level + 1;
+  epi.l = level;
+  epi.cst = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv));
+  epi.cst_sh = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv_sh));
+  epi.out = out;
+  epi.out_stride = out_stride;
+  for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = 1;
+  ntt_forward(c, spread, 2 * (size_t)level * n, batch, c.rows(ROWS_CT, level - 1), NttSrc{}, &epi);
   c.counters[4] += batch;
 }
 
