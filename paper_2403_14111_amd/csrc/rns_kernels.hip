@@ -23,8 +23,9 @@ const T* device_field(const S* table, size_t offset) {
 // For digit j (blockIdx.y): every row of the extended basis outside the digit q_0..q_l, p_0..p_{K-1} receives the fast
 // basis conversion of the digit's coefficient-form residues
 //   sum_i [x_i (D/d_i)^-1]_{d_i} (D/d_i) mod t    (128-bit lazy sum, one Barrett).
+// ALPHA is the digit length; a shorter last digit takes zero terms.
+template <int ALPHA>
 __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef, size_t coef_stride,
-                                                    const u64* __restrict__ ntt_in, size_t in_stride,
                                                     u64* __restrict__ dt, size_t dt_stride,
                                                     const ModUpTab* __restrict__ tabs, const ModInfo* __restrict__ mods,
                                                     int log_n, int level, int num_q, int num_p) {
@@ -36,21 +37,19 @@ __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef
   const ModUpTab& tb = tabs[jd];
   const u64* __restrict__ cf = coef + blockIdx.z * coef_stride;
   u64* __restrict__ out = dt + blockIdx.z * dt_stride + (size_t)jd * ext * n;
-  u64 y[MAX_ALPHA];
+  u64 y[ALPHA];
 #pragma unroll
-  for (int i = 0; i < MAX_ALPHA; ++i) {
-    if (i < tb.nsrc) {
-      const int s = tb.first + i;
-      y[i] = mul_shoup(cf[(size_t)s * n + k], tb.dinv[i], tb.dinv_sh[i], mods[s].q);
-    }
+  for (int i = 0; i < ALPHA; ++i) {
+    const int s = tb.first + (i < tb.nsrc ? i : 0);
+    const u64 v = mul_shoup(cf[(size_t)s * n + k], tb.dinv[i], tb.dinv_sh[i], mods[s].q);
+    y[i] = i < tb.nsrc ? v : 0;
   }
   for (int r = 0; r < ext; ++r) {
     if (r >= tb.first && r < tb.first + tb.nsrc) continue;  // the digit's own rows are read from the input
     const int t = r < l ? r : num_q + (r - l);
-    U128 acc = {0, 0};
+    U128 acc = mul_wide(y[0], tb.dhat[0][t]);
 #pragma unroll
-    for (int i = 0; i < MAX_ALPHA; ++i)
-      if (i < tb.nsrc) acc_wide(acc, mul_wide(y[i], tb.dhat[i][t]));
+    for (int i = 1; i < ALPHA; ++i) acc_wide(acc, mul_wide(y[i], tb.dhat[i][t]));
     out[(size_t)r * n + k] = reduce128(acc, mods[t]);
   }
 }
@@ -58,17 +57,18 @@ __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef
 // ---------------------------------------------------------------- key inner product
 // acc_b[r][k] = sum_j dt_j[r][src(k)] * b_j[t][k], acc_a likewise, where src is
 // the Galois gather of the automorphism (identity for g = 1) and t the global
-// prime of extended row r.  The key streams through once; dt is re-read per item.
+// prime of extended row r.  BETA is the number of digits at the level.
 struct IpArgs {
   const u64* key[MAX_BATCH];
   u32 g[MAX_BATCH];
 };
 
+template <int BETA>
 __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restrict__ dt, size_t dt_stride,
                                                             const u64* __restrict__ in, size_t in_stride,
                                                             u64* __restrict__ acc, size_t acc_stride, IpArgs args,
                                                             const ModInfo* __restrict__ mods, int log_n, int level,
-                                                            int num_q, int num_p, int nprimes, int beta, int alpha) {
+                                                            int num_q, int num_p, int nprimes, int alpha) {
   const int n = 1 << log_n;
   const int l = level + 1;
   const int ext = l + num_p;
@@ -82,13 +82,14 @@ __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restric
   const u64* __restrict__ own = in + item * in_stride + (size_t)r * n;
   const int rd = r < l ? r / alpha : -1;  // the digit that row r belongs to
   const u32 src = g == 1 ? (u32)k : galois_source((u32)k, g, log_n);
+  u64 x[BETA];
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) x[j] = j == rd ? own[src] : d[(size_t)j * ext * n + src];
   U128 sb = {0, 0}, sa = {0, 0};
-  for (int j = 0; j < beta; ++j) {
-    const u64 x = j == rd ? own[src] : d[(size_t)j * ext * n + src];
-    const u64 kb = key[((size_t)(2 * j) * nprimes + t) * n + k];
-    const u64 ka = key[((size_t)(2 * j + 1) * nprimes + t) * n + k];
-    acc_wide(sb, mul_wide(x, kb));
-    acc_wide(sa, mul_wide(x, ka));
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) {
+    acc_wide(sb, mul_wide(x[j], key[((size_t)(2 * j) * nprimes + t) * n + k]));
+    acc_wide(sa, mul_wide(x[j], key[((size_t)(2 * j + 1) * nprimes + t) * n + k]));
   }
   const ModInfo m = mods[t];
   u64* __restrict__ o = acc + item * acc_stride;
@@ -97,15 +98,16 @@ __global__ void __launch_bounds__(TPB) inner_product_kernel(const u64* __restric
 }
 
 // Same, for `count` items that share one key and Galois element: the key
-// words are loaded once per coefficient and reused for every item.
+// words are loaded once per coefficient and reused for every item; two items
+// are in flight at a time.
+template <int BETA>
 __global__ void __launch_bounds__(TPB) inner_product_shared_kernel(const u64* __restrict__ dt, size_t dt_stride,
                                                                    const u64* __restrict__ in, size_t in_stride,
                                                                    u64* __restrict__ acc, size_t acc_stride,
                                                                    const u64* __restrict__ key, u32 g, int count,
                                                                    const ModInfo* __restrict__ mods, int log_n,
                                                                    int level, int num_q, int num_p, int nprimes,
-                                                                   int beta, int alpha) {
-  constexpr int MAXB = 8;  // digits held in registers (dnum <= 8 for this kernel)
+                                                                   int alpha) {
   const int n = 1 << log_n;
   const int l = level + 1;
   const int ext = l + num_p;
@@ -113,69 +115,78 @@ __global__ void __launch_bounds__(TPB) inner_product_shared_kernel(const u64* __
   const int r = blockIdx.y;
   const int t = r < l ? r : num_q + (r - l);
   const u32 src = g == 1 ? (u32)k : galois_source((u32)k, g, log_n);
-  u64 kb[MAXB], ka[MAXB];
+  u64 kb[BETA], ka[BETA];
 #pragma unroll
-  for (int j = 0; j < MAXB; ++j) {
-    if (j < beta) {
-      kb[j] = key[((size_t)(2 * j) * nprimes + t) * n + k];
-      ka[j] = key[((size_t)(2 * j + 1) * nprimes + t) * n + k];
-    }
+  for (int j = 0; j < BETA; ++j) {
+    kb[j] = key[((size_t)(2 * j) * nprimes + t) * n + k];
+    ka[j] = key[((size_t)(2 * j + 1) * nprimes + t) * n + k];
   }
   const ModInfo m = mods[t];
   const int rd = r < l ? r / alpha : -1;  // the digit that row r belongs to
-  for (int item = 0; item < count; ++item) {
+  auto load = [&](int item, u64 (&x)[BETA]) {
     const u64* __restrict__ d = dt + item * dt_stride + (size_t)r * n;
     const u64* __restrict__ own = in + item * in_stride + (size_t)r * n;
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) x[j] = j == rd ? own[src] : d[(size_t)j * ext * n + src];
+  };
+  auto finish = [&](int item, const u64 (&x)[BETA]) {
     U128 sb = {0, 0}, sa = {0, 0};
 #pragma unroll
-    for (int j = 0; j < MAXB; ++j) {
-      if (j < beta) {
-        const u64 x = j == rd ? own[src] : d[(size_t)j * ext * n + src];
-        acc_wide(sb, mul_wide(x, kb[j]));
-        acc_wide(sa, mul_wide(x, ka[j]));
-      }
+    for (int j = 0; j < BETA; ++j) {
+      acc_wide(sb, mul_wide(x[j], kb[j]));
+      acc_wide(sa, mul_wide(x[j], ka[j]));
     }
     u64* __restrict__ o = acc + item * acc_stride;
     o[(size_t)r * n + k] = reduce128(sb, m);
     o[(size_t)(ext + r) * n + k] = reduce128(sa, m);
+  };
+  int item = 0;
+  for (; item + 1 < count; item += 2) {
+    u64 x0[BETA], x1[BETA];
+    load(item, x0);
+    load(item + 1, x1);
+    finish(item, x0);
+    finish(item + 1, x1);
+  }
+  if (item < count) {
+    u64 x0[BETA];
+    load(item, x0);
+    finish(item, x0);
   }
 }
 
 // ---------------------------------------------------------------- ModDown
 // Centred conversion of the special-prime part (coefficient form) to each q_i:
-// y_k = [x_k (P/p_k)^-1]_{p_k} taken in (-p_k/2, p_k/2]; conv_i = sum_k y_k (P/p_k) mod q_i.
+// y_k = [x_k (P/p_k)^-1]_{p_k} taken in (-p_k/2, p_k/2]; conv_i = sum_k y_k (P/p_k) mod q_i.  K special primes.
+template <int K>
 __global__ void __launch_bounds__(TPB) moddown_conv_kernel(const u64* __restrict__ acc, size_t acc_stride,
                                                            u64* __restrict__ conv, size_t conv_stride,
                                                            const ModDownTab* __restrict__ tab,
                                                            const ModInfo* __restrict__ mods, int log_n, int level,
-                                                           int num_q, int num_p) {
+                                                           int num_q) {
   const int n = 1 << log_n;
   const int l = level + 1;
-  const int ext = l + num_p;
+  const int ext = l + K;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int poly = blockIdx.y;
   const u64* __restrict__ a = acc + blockIdx.z * acc_stride + (size_t)poly * ext * n;
   u64* __restrict__ o = conv + blockIdx.z * conv_stride + (size_t)poly * l * n;
-  u64 y[MAX_K];
-  bool neg[MAX_K];
+  u64 y[K];
+  bool neg[K];
 #pragma unroll
-  for (int kk = 0; kk < MAX_K; ++kk) {
-    if (kk < num_p) {
-      const u64 pk = mods[num_q + kk].q;
-      u64 v = mul_shoup(a[(size_t)(l + kk) * n + k], tab->pkinv[kk], tab->pkinv_sh[kk], pk);
-      neg[kk] = v > (pk >> 1);
-      y[kk] = neg[kk] ? pk - v : v;
-    }
+  for (int kk = 0; kk < K; ++kk) {
+    const u64 pk = mods[num_q + kk].q;
+    const u64 v = mul_shoup(a[(size_t)(l + kk) * n + k], tab->pkinv[kk], tab->pkinv_sh[kk], pk);
+    neg[kk] = v > (pk >> 1);
+    y[kk] = neg[kk] ? pk - v : v;
   }
   for (int i = 0; i < l; ++i) {
     const ModInfo m = mods[i];
     U128 s = {0, 0};
 #pragma unroll
-    for (int kk = 0; kk < MAX_K; ++kk) {
-      if (kk < num_p) {
-        const u64 h = tab->phat[kk][i];
-        acc_wide(s, mul_wide(y[kk], neg[kk] ? m.q - h : h));
-      }
+    for (int kk = 0; kk < K; ++kk) {
+      const u64 h = tab->phat[kk][i];
+      acc_wide(s, mul_wide(y[kk], neg[kk] ? m.q - h : h));
     }
     o[(size_t)i * n + k] = reduce128(s, m);
   }
@@ -358,22 +369,39 @@ void key_switch(Context& c, const KsJob& job) {
   // 2. ModUp of every digit, then the NTT of the converted rows
   Tmp dt(c.pool, m_in * dt_words);
   c.begin_launch();
-  hipLaunchKernelGGL(modup_kernel, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, poly, job.in,
-                     job.in_stride, dt.p, dt_words, c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level,
-                     c.num_q, c.num_p);
+  switch (c.alpha) {
+#define HETAL_MODUP(A)                                                                                          \
+  case A:                                                                                                     \
+    hipLaunchKernelGGL(modup_kernel<A>, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, poly, dt.p, dt_words, \
+                       c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level, c.num_q, c.num_p);        \
+    break;
+    HETAL_MODUP(1) HETAL_MODUP(2) HETAL_MODUP(3) HETAL_MODUP(4) HETAL_MODUP(5) HETAL_MODUP(6) HETAL_MODUP(7)
+    HETAL_MODUP(8)
+#undef HETAL_MODUP
+    default:
+      fail(HETAL_E_PARAMS, "digit length above 8");
+  }
   // reads: each digit's coefficient-form limbs (l rows in all); writes the beta * ext - l rows outside the digits
   c.end_launch(KC_MODUP, 8.0 * n * m_in * ((double)beta * ext));
   ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level));
 
   // 3. inner product with the keys, automorphism applied on the loads
   Tmp acc(c.pool, m * acc_words);
-  bool shared = !hoisted && beta <= 8;
+  bool shared = !hoisted;
   for (int i = 1; i < m && shared; ++i) shared = job.item[i].key == job.item[0].key && job.item[i].g == job.item[0].g;
+  if (beta < 1 || beta > 8) fail(HETAL_E_PARAMS, "more than 8 digits");
   if (shared) {
     c.begin_launch();
-    hipLaunchKernelGGL(inner_product_shared_kernel, grid_for(c, ext, 1), dim3(TPB), 0, c.stream, dt.p, dt_words,
-                       job.in, job.in_stride, acc.p, acc_words, job.item[0].key, job.item[0].g, m, c.d_mod, c.log_n,
-                       level, c.num_q, c.num_p, c.nprimes, beta, c.alpha);
+    switch (beta) {
+#define HETAL_IPS(B)                                                                                              \
+  case B:                                                                                                       \
+    hipLaunchKernelGGL(inner_product_shared_kernel<B>, grid_for(c, ext, 1), dim3(TPB), 0, c.stream, dt.p, dt_words, \
+                       job.in, job.in_stride, acc.p, acc_words, job.item[0].key, job.item[0].g, m, c.d_mod,     \
+                       c.log_n, level, c.num_q, c.num_p, c.nprimes, c.alpha);                                   \
+    break;
+      HETAL_IPS(1) HETAL_IPS(2) HETAL_IPS(3) HETAL_IPS(4) HETAL_IPS(5) HETAL_IPS(6) HETAL_IPS(7) HETAL_IPS(8)
+#undef HETAL_IPS
+    }
     // reads: the extended digits of every item and 2 beta ext key rows once; writes 2 ext rows per item
     c.end_launch(KC_INNER, 8.0 * n * ((double)m * beta * ext + 2.0 * beta * ext + (double)m * 2.0 * ext));
   } else {
@@ -382,10 +410,17 @@ void key_switch(Context& c, const KsJob& job) {
       ip.key[i] = i < m ? job.item[i].key : nullptr;
       ip.g[i] = i < m ? job.item[i].g : 1;
     }
+    const size_t dts = hoisted ? (size_t)0 : dt_words, ins = hoisted ? (size_t)0 : job.in_stride;
     c.begin_launch();
-    hipLaunchKernelGGL(inner_product_kernel, grid_for(c, ext, m), dim3(TPB), 0, c.stream, dt.p,
-                       hoisted ? (size_t)0 : dt_words, job.in, hoisted ? (size_t)0 : job.in_stride, acc.p, acc_words,
-                       ip, c.d_mod, c.log_n, level, c.num_q, c.num_p, c.nprimes, beta, c.alpha);
+    switch (beta) {
+#define HETAL_IP(B)                                                                                             \
+  case B:                                                                                                     \
+    hipLaunchKernelGGL(inner_product_kernel<B>, grid_for(c, ext, m), dim3(TPB), 0, c.stream, dt.p, dts, job.in, ins, \
+                       acc.p, acc_words, ip, c.d_mod, c.log_n, level, c.num_q, c.num_p, c.nprimes, c.alpha);   \
+    break;
+      HETAL_IP(1) HETAL_IP(2) HETAL_IP(3) HETAL_IP(4) HETAL_IP(5) HETAL_IP(6) HETAL_IP(7) HETAL_IP(8)
+#undef HETAL_IP
+    }
     // reads: the extended digits (once per input) and 2 beta ext key rows per item; writes 2 ext rows per item
     c.end_launch(KC_INNER, 8.0 * n * ((double)m_in * beta * ext + (double)m * (2.0 * beta * ext + 2.0 * ext)));
   }
@@ -394,8 +429,17 @@ void key_switch(Context& c, const KsJob& job) {
   ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level));
   Tmp conv(c.pool, m * conv_words);
   c.begin_launch();
-  hipLaunchKernelGGL(moddown_conv_kernel, grid_for(c, 2, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p,
-                     conv_words, c.d_moddown, c.d_mod, c.log_n, level, c.num_q, c.num_p);
+  switch (c.num_p) {
+#define HETAL_CONV(K)                                                                                          \
+  case K:                                                                                                    \
+    hipLaunchKernelGGL(moddown_conv_kernel<K>, grid_for(c, 2, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p, \
+                       conv_words, c.d_moddown, c.d_mod, c.log_n, level, c.num_q);                           \
+    break;
+    HETAL_CONV(1) HETAL_CONV(2) HETAL_CONV(3) HETAL_CONV(4) HETAL_CONV(5) HETAL_CONV(6) HETAL_CONV(7) HETAL_CONV(8)
+#undef HETAL_CONV
+    default:
+      fail(HETAL_E_PARAMS, "more than 8 special primes");
+  }
   c.end_launch(KC_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
   // ... and the combine (acc_Q - conv) P^-1 + addends as the epilogue of the NTT's last pass
   NttEpilogue epi;
