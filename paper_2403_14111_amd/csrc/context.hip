@@ -233,6 +233,7 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
           for (int k = 0; k < tb.nsrc; ++k)
             if (k != i) h = mulm(h, c.primes[tb.first + k] % qt, qt);
           tb.dhat[i][t] = h;
+          tb.dhat_sh[i][t] = shoup(h, qt);
         }
       }
     }
@@ -253,6 +254,7 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
       for (int t = 0; t < c.num_p; ++t)
         if (t != k) h = mulm(h, c.primes[c.num_q + t] % qi, qi);
       c.h_moddown.phat[k][i] = h;
+      c.h_moddown.phat_sh[k][i] = shoup(h, qi);
     }
   }
   for (int i = 0; i < c.num_q; ++i) {

@@ -39,6 +39,7 @@ struct ModUpTab {
   u64 dinv[MAX_ALPHA];            // (D / d_i)^-1 mod d_i
   u64 dinv_sh[MAX_ALPHA];         // its Shoup companion
   u64 dhat[MAX_ALPHA][MAX_PRIMES];  // (D / d_i) mod t, t = global prime index
+  u64 dhat_sh[MAX_ALPHA][MAX_PRIMES];  // Shoup companions w.r.t. t
 };
 
 // Centred conversion from the special primes to q_i, and P^-1 mod q_i (ModDown).
@@ -48,6 +49,7 @@ struct ModDownTab {
   u64 pkinv[MAX_K];               // (P / p_k)^-1 mod p_k
   u64 pkinv_sh[MAX_K];
   u64 phat[MAX_K][MAX_PRIMES];    // (P / p_k) mod q_i
+  u64 phat_sh[MAX_K][MAX_PRIMES];  // Shoup companions w.r.t. q_i
   u64 pinv[MAX_PRIMES];           // P^-1 mod q_i
   u64 pinv_sh[MAX_PRIMES];
 };

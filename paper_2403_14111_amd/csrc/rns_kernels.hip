@@ -22,8 +22,9 @@ const T* device_field(const S* table, size_t offset) {
 // ---------------------------------------------------------------- ModUp
 // For digit j (blockIdx.y): every row of the extended basis outside the digit q_0..q_l, p_0..p_{K-1} receives the fast
 // basis conversion of the digit's coefficient-form residues
-//   sum_i [x_i (D/d_i)^-1]_{d_i} (D/d_i) mod t    (128-bit lazy sum, one Barrett).
-// ALPHA is the digit length; a shorter last digit takes zero terms.
+//   sum_i [x_i (D/d_i)^-1]_{d_i} (D/d_i) mod t
+// as a sum of lazy Shoup products by the constants (D/d_i) mod t (each below 4t, the sum below 4 ALPHA t < 2^55),
+// reduced once.  ALPHA is the digit length; a shorter last digit takes zero terms.
 template <int ALPHA>
 __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef, size_t coef_stride,
                                                     u64* __restrict__ dt, size_t dt_stride,
@@ -47,10 +48,11 @@ __global__ void __launch_bounds__(TPB) modup_kernel(const u64* __restrict__ coef
   for (int r = 0; r < ext; ++r) {
     if (r >= tb.first && r < tb.first + tb.nsrc) continue;  // the digit's own rows are read from the input
     const int t = r < l ? r : num_q + (r - l);
-    U128 acc = mul_wide(y[0], tb.dhat[0][t]);
+    const u64 q = mods[t].q, nq = 0 - q;
+    u64 s = mul_shoup_lazy4n(y[0], tb.dhat[0][t], tb.dhat_sh[0][t], nq);
 #pragma unroll
-    for (int i = 1; i < ALPHA; ++i) acc_wide(acc, mul_wide(y[i], tb.dhat[i][t]));
-    out[(size_t)r * n + k] = reduce128(acc, mods[t]);
+    for (int i = 1; i < ALPHA; ++i) s += mul_shoup_lazy4n(y[i], tb.dhat[i][t], tb.dhat_sh[i][t], nq);
+    out[(size_t)r * n + k] = csub(csub(reduce_lazy4(s, mods[t].one_sh, nq), 2 * q), q);
   }
 }
 
@@ -158,6 +160,7 @@ __global__ void __launch_bounds__(TPB) inner_product_shared_kernel(const u64* __
 // ---------------------------------------------------------------- ModDown
 // Centred conversion of the special-prime part (coefficient form) to each q_i:
 // y_k = [x_k (P/p_k)^-1]_{p_k} taken in (-p_k/2, p_k/2]; conv_i = sum_k y_k (P/p_k) mod q_i.  K special primes.
+// Each term is a lazy Shoup product |y_k| (P/p_k) in [0, 4 q_i), negated as 4 q_i - it; one reduction ends the sum.
 template <int K>
 __global__ void __launch_bounds__(TPB) moddown_conv_kernel(const u64* __restrict__ acc, size_t acc_stride,
                                                            u64* __restrict__ conv, size_t conv_stride,
@@ -181,14 +184,14 @@ __global__ void __launch_bounds__(TPB) moddown_conv_kernel(const u64* __restrict
     y[kk] = neg[kk] ? pk - v : v;
   }
   for (int i = 0; i < l; ++i) {
-    const ModInfo m = mods[i];
-    U128 s = {0, 0};
+    const u64 q = mods[i].q, nq = 0 - q, q4 = 4 * q;
+    u64 s = 0;
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
-      const u64 h = tab->phat[kk][i];
-      acc_wide(s, mul_wide(y[kk], neg[kk] ? m.q - h : h));
+      const u64 t = mul_shoup_lazy4n(y[kk], tab->phat[kk][i], tab->phat_sh[kk][i], nq);
+      s += neg[kk] ? q4 - t : t;
     }
-    o[(size_t)i * n + k] = reduce128(s, m);
+    o[(size_t)i * n + k] = csub(csub(reduce_lazy4(s, mods[i].one_sh, nq), 2 * q), q);
   }
 }
 
