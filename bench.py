@@ -83,11 +83,13 @@ def encrypt_inputs(ctx, sk, X, W, PY):
 # ---------------------------------------------------------------- profile summaries
 # rocprofv3 kernel names -> the library's timing classes (N = 2^16: every NTT pass has 256-point sub-transforms)
 PROFILE_CLASSES = [
-    ("ntt_pass_kernel<8, false, false, false>", "ntt_fwd_strided"),
-    ("ntt_pass_kernel<8, false, true, false>", "ntt_fwd_contig"),
-    ("ntt_pass_kernel<8, false, true, true>", "ntt_fwd_epilogue"),
-    ("ntt_pass_kernel<8, true, true, false>", "ntt_inv_contig"),
-    ("ntt_pass_kernel<8, true, false, false>", "ntt_inv_strided"),
+    ("ntt_pass_kernel<8, false, false, false, 0,", "ntt_fwd_strided"),
+    ("ntt_pass_kernel<8, false, false, false, 1,", "ntt_fwd_modup"),
+    ("ntt_pass_kernel<8, false, false, false, 2,", "ntt_fwd_moddown"),
+    ("ntt_pass_kernel<8, false, true, false,", "ntt_fwd_contig"),
+    ("ntt_pass_kernel<8, false, true, true,", "ntt_fwd_epilogue"),
+    ("ntt_pass_kernel<8, true, true, false,", "ntt_inv_contig"),
+    ("ntt_pass_kernel<8, true, false, false,", "ntt_inv_strided"),
     ("modup_kernel", "modup"),
     ("inner_product", "inner_product"),
     ("moddown_conv_kernel", "moddown_conv"),

@@ -227,12 +227,15 @@ int hetal_counters_reset(hetal_ctx* ctx);
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds two event records per launch while enabled).  There are
  * hetal_timing_classes() classes: [0] forward NTT, strided first pass,
- * [1] forward NTT, contiguous final pass, [2] the same pass ending a key
+ * [1] the same pass computing its input as the ModUp basis conversion,
+ * [2] the same pass computing its input as the ModDown basis conversion,
+ * [3] forward NTT, contiguous final pass, [4] the same pass ending a key
  * switch or rescale (it also subtracts, scales and adds: the ModDown / rescale
- * combine), [3] inverse NTT, contiguous first pass, [4] inverse NTT, strided
- * final pass, [5] ModUp basis conversion, [6] key inner product, [7] ModDown
- * basis conversion, [8] rescale (the top limb's centred spread), [9]
- * elementwise, [10] encode / decode.  enable(on) clears what
+ * combine), [5] inverse NTT, contiguous first pass, [6] inverse NTT, strided
+ * final pass, [7] ModUp basis conversion as a kernel of its own, [8] key
+ * inner product, [9] ModDown basis conversion as a kernel of its own,
+ * [10] rescale (the top limb's centred spread), [11] elementwise,
+ * [12] encode / decode.  enable(on) clears what
  * was collected; get synchronises and fills, per class, the summed kernel time
  * in ms, the launch count and the summed algorithmic HBM bytes (each operand
  * read once and each result written once) into caller arrays of

@@ -262,6 +262,25 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
     c.h_moddown.pinv[i] = invm(c.h_pc[i].pmod, qi);
     c.h_moddown.pinv_sh[i] = shoup(c.h_moddown.pinv[i], qi);
   }
+  // Final inverse-NTT scalings that leave the (D_j/d_i)^-1 or (P/p_k)^-1 factors of the conversions applied
+  auto scaled = [&](int prime, u64 f) {
+    const u64 q = c.primes[prime];
+    NttScale s;
+    s.s0 = mulm(c.h_pc[prime].ninv, f, q);
+    s.s0_sh = shoup(s.s0, q);
+    s.s1 = mulm(c.h_pc[prime].w1ninv, f, q);
+    s.s1_sh = shoup(s.s1, q);
+    return s;
+  };
+  std::vector<NttScale> up_scale((size_t)c.num_q * MAX_PRIMES, NttScale{0, 0, 0, 0});
+  for (int lv = 0; lv < c.num_q; ++lv)
+    for (int i = 0; i <= lv; ++i) {
+      const ModUpTab& tb = c.h_modup[(size_t)lv * c.dnum + i / c.alpha];
+      up_scale[(size_t)lv * MAX_PRIMES + i] = scaled(i, tb.dinv[i % c.alpha]);
+    }
+  std::vector<NttScale> down_scale(2 * (size_t)c.num_p);
+  for (int pp = 0; pp < 2; ++pp)
+    for (int k = 0; k < c.num_p; ++k) down_scale[(size_t)pp * c.num_p + k] = scaled(c.num_q + k, c.h_moddown.pkinv[k]);
   // Rescale tables
   std::vector<RescaleTab> resc(c.num_q);
   for (int lv = 0; lv < c.num_q; ++lv) {
@@ -328,6 +347,8 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
   c.d_modup = upload(c.h_modup.data(), c.h_modup.size(), stream);
   c.d_moddown = upload(&c.h_moddown, 1, stream);
   c.d_rescale = upload(resc.data(), resc.size(), stream);
+  c.d_modup_scale = upload(up_scale.data(), up_scale.size(), stream);
+  c.d_moddown_scale = upload(down_scale.data(), down_scale.size(), stream);
   c.d_pow5 = upload(pow5.data(), pow5.size(), stream);
   c.d_rows = upload(rows.data(), rows.size(), stream);
   if (hipMalloc(&c.d_roots, (size_t)m * 4 * sizeof(double)) != hipSuccess) fail(HETAL_E_OOM, "roots table");
@@ -338,8 +359,8 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
 void context_free(Context& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   else (void)hipDeviceSynchronize();
-  void* ptrs[] = {c.d_mod, c.d_tw_fwd, c.d_tw_inv, c.d_pc, c.d_modup, c.d_moddown, c.d_rescale, c.d_roots, c.d_pow5,
-                  c.d_rows};
+  void* ptrs[] = {c.d_mod,     c.d_tw_fwd, c.d_tw_inv, c.d_pc,   c.d_modup,         c.d_moddown,
+                  c.d_rescale, c.d_roots,  c.d_pow5,   c.d_rows, c.d_modup_scale, c.d_moddown_scale};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -54,6 +54,13 @@ struct ModDownTab {
   u64 pinv_sh[MAX_PRIMES];
 };
 
+// Per-row replacement of the inverse transform's final N^-1 scaling: row r of the row list gets
+// s0 on the sums and s1 = psi^-(N/2) s0 on the differences of the last butterfly (each with its Shoup
+// companion), i.e. the inverse transform times s0 / N^-1.
+struct NttScale {
+  u64 s0, s0_sh, s1, s1_sh;
+};
+
 // q_l^-1 mod q_i (i < l) for the rescale at level l.
 struct RescaleTab {
   u64 inv[MAX_PRIMES];
@@ -118,10 +125,13 @@ struct Tmp {
 };
 
 // Kernel classes for the optional per-launch HIP-event timing.
-// NTT passes: forward strided (first), forward contiguous (final; plain, or with the combine epilogue),
-// inverse contiguous (first), inverse strided (final).
+// NTT passes: forward strided (first; plain, or computing its input by a ModUp / ModDown basis
+// conversion), forward contiguous (final; plain, or with the combine epilogue), inverse contiguous (first),
+// inverse strided (final).
 enum KernelClass {
   KC_NTT_FWD_STRIDED = 0,
+  KC_NTT_FWD_MODUP,
+  KC_NTT_FWD_MODDOWN,
   KC_NTT_FWD_CONTIG,
   KC_NTT_FWD_EPILOGUE,
   KC_NTT_INV_CONTIG,
@@ -160,6 +170,8 @@ struct Context {
   PrimeConsts* d_pc = nullptr;       // [nprimes]
   ModUpTab* d_modup = nullptr;       // [num_q levels][dnum]
   ModDownTab* d_moddown = nullptr;   // one table (rows q_0..q_{num_q-1})
+  NttScale* d_modup_scale = nullptr;    // [num_q levels][MAX_PRIMES]: N^-1 (D_j/d_i)^-1 for limb i of the level
+  NttScale* d_moddown_scale = nullptr;  // [2 num_p] (rows of ROWS_SPECIAL): N^-1 (P/p_k)^-1
   RescaleTab* d_rescale = nullptr;   // [num_q]
   double* d_roots = nullptr;         // [2N][4]: exp(2 pi i j / 2N) in double-double (re hi, re lo, im hi, im lo)
   u32* d_pow5 = nullptr;             // [N/2]: 5^k mod 2N
@@ -249,9 +261,35 @@ struct NttEpilogue {
   u32 g[MAX_BATCH];
 };
 
+// Optional basis-conversion input of a forward NTT: the first pass computes its input words instead of
+// reading them (the fast basis conversions of hybrid key switching, never stored):
+//  * CONV_MODUP, rows of ROWS_MODUP: row (digit j, extended row r, prime t) takes
+//      sum_i y_i (D_j / d_i) mod t
+//    over the digit's rows y_i = [x_i (D_j/d_i)^-1]_{d_i} of `y` (coefficient form, rows indexed like the
+//    ciphertext's limbs, `ext` rows per digit in the row table's row index);
+//  * CONV_MODDOWN, rows of ROWS_CT: row (polynomial p, limb i) takes
+//      sum_k y_k (P / p_k) mod q_i
+//    over the special rows y_k = [x_k (P/p_k)^-1]_{p_k} of polynomial p of `y` (at row p ext + l + k), each
+//    taken in the centred range (-p_k/2, p_k/2].
+// The words are left lazy (below 4 count q); the transform tolerates that.
+enum NttConvKind { CONV_NONE = 0, CONV_MODUP = 1, CONV_MODDOWN = 2 };
+struct NttConv {
+  int kind = CONV_NONE;
+  int count = 0;          // digit length alpha, or the number K of special primes
+  const u64* y = nullptr;
+  size_t y_stride = 0;    // words between items
+  int ext = 0;
+  int l = 0;              // CONV_MODDOWN: limbs per output polynomial
+  int num_q = 0;
+  const ModUpTab* modup = nullptr;  // the level's digit tables
+  const ModDownTab* moddown = nullptr;
+};
+constexpr int MAX_FUSED_CONV = 4;  // conversions of more terms run as separate kernels
+
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
-                 const NttEpilogue* epi = nullptr);
-void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{});
+                 const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr);
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
+                 const NttScale* row_scale = nullptr);
 
 struct KsItem {
   const u64* key;  // [dnum][2][nprimes][N]

@@ -98,18 +98,23 @@ __device__ __forceinline__ void lds_exchange(u64 (&x)[NTT_R], u32* __restrict__ 
 // for element v is psi_rev[2^(s0 + l) + (c 2^l) + (v >> (L - l))] (c = 0 in the strided pass, where
 // in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
 // EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.
-template <int L, bool INV, bool CONTIG, bool EPI>
+// CONVK / CNT (forward strided pass only): the input words are the basis conversion of NttConv over CNT
+// source rows.  row_scale (inverse strided pass only, may be null): per-row final scaling.
+template <int L, bool INV, bool CONTIG, bool EPI, int CONVK, int CNT>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const ulonglong2* __restrict__ tw,
                                                               const ModInfo* __restrict__ mods,
                                                               const PrimeConsts* __restrict__ pc, int log_n, int s0,
-                                                              NttEpilogue epi) {
+                                                              NttEpilogue epi, NttConv cv,
+                                                              const NttScale* __restrict__ row_scale) {
   constexpr int SUB = 1 << L;
   constexpr int T = SUB / NTT_R;        // threads per sub-transform
   constexpr int S = NTT_THREADS / T;    // sub-transforms per workgroup
   constexpr bool FINAL = INV != CONTIG;
   static_assert(!CONTIG || L == 8, "the contiguous pass covers the last 8 stages");
   static_assert(!EPI || (CONTIG && !INV), "the epilogue belongs to the last forward pass");
+  static_assert(CONVK == CONV_NONE || (!CONTIG && !INV && CNT >= 1 && CNT <= MAX_FUSED_CONV),
+                "the conversion input belongs to the first forward pass");
   // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
   // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
   // neighbouring slices in lockstep fall on distinct banks.
@@ -156,8 +161,55 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   u64 x[NTT_R];
 
   if (!INV) {
+    if (CONVK == CONV_MODUP) {
+      // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t, lazily
+      const ModUpTab& tb = cv.modup[rj.x / cv.ext];
+      const u64* yb[CNT];
+      u64 cc[CNT], cs[CNT];
 #pragma unroll
-    for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
+      for (int i = 0; i < CNT; ++i) {
+        // a short last digit has zero constants beyond its length (its row pointer stays in range)
+        yb[i] = cv.y + item * cv.y_stride + (size_t)(tb.first + (i < tb.nsrc ? i : 0)) * n;
+        cc[i] = tb.dhat[i][rj.y];
+        cs[i] = tb.dhat_sh[i][rj.y];
+      }
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) {
+        const u32 pos = sp_off + sp_step * u;
+        u64 s = mul_shoup_lazy4n(yb[0][pos], cc[0], cs[0], nq);
+#pragma unroll
+        for (int i = 1; i < CNT; ++i) s += mul_shoup_lazy4n(yb[i][pos], cc[i], cs[i], nq);
+        x[u] = s;
+      }
+    } else if (CONVK == CONV_MODDOWN) {
+      // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i, y_k centred, lazily
+      const int p = rj.x >= cv.l ? 1 : 0;
+      const u64* yb[CNT];
+      u64 pk[CNT], cc[CNT], cs[CNT];
+#pragma unroll
+      for (int k = 0; k < CNT; ++k) {
+        yb[k] = cv.y + item * cv.y_stride + (size_t)(p * cv.ext + cv.l + k) * n;
+        pk[k] = mods[cv.num_q + k].q;
+        cc[k] = cv.moddown->phat[k][rj.y];
+        cs[k] = cv.moddown->phat_sh[k][rj.y];
+      }
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) {
+        const u32 pos = sp_off + sp_step * u;
+        u64 s = 0;
+#pragma unroll
+        for (int k = 0; k < CNT; ++k) {
+          const u64 v = yb[k][pos];
+          const bool neg = v > (pk[k] >> 1);
+          const u64 t = mul_shoup_lazy4n(neg ? pk[k] - v : v, cc[k], cs[k], nq);
+          s += neg ? q4 - t : t;
+        }
+        x[u] = s;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
+    }
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int hu = 8 >> l;
@@ -246,12 +298,18 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       for (int u = 0; u < NTT_R; ++u) {
         if (u & hu) continue;
         if (l == 0 && FINAL) {
-          // last stage of the transform, N^-1 merged into both outputs
-          const PrimeConsts k = pc[rj.y];
+          // last stage of the transform, N^-1 (or the row's replacement) merged into both outputs
+          NttScale k;
+          if (row_scale) {
+            k = row_scale[rowi];
+          } else {
+            const PrimeConsts& pcr = pc[rj.y];
+            k = NttScale{pcr.ninv, pcr.ninv_sh, pcr.w1ninv, pcr.w1ninv_sh};
+          }
           const u64 s = x[u] + x[u + hu];
           const u64 d = x[u] + b - x[u + hu];
-          x[u] = mul_shoup_lazy4n(s, k.ninv, k.ninv_sh, nq);
-          x[u + hu] = mul_shoup_lazy4n(d, k.w1ninv, k.w1ninv_sh, nq);
+          x[u] = mul_shoup_lazy4n(s, k.s0, k.s0_sh, nq);
+          x[u + hu] = mul_shoup_lazy4n(d, k.s1, k.s1_sh, nq);
         } else {
           inv_bfly(x[u], x[u + hu], tw_spread(l, u), nq, b);
         }
@@ -272,7 +330,8 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 
 template <bool INV>
 void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0,
-                 const NttSrc& src, const NttEpilogue* epi = nullptr) {
+                 const NttSrc& src, const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr,
+                 const NttScale* row_scale = nullptr) {
   const int sub = 1 << L;
   const int per_wg = NTT_THREADS * NTT_R / sub;  // sub-transforms per workgroup
   const int nsub = c.n / sub;
@@ -294,17 +353,40 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
   if (epi && (INV || !contiguous)) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
   if (epi && batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "NTT epilogue batch");
-  const NttEpilogue none{};
+  const bool cv = conv && conv->kind != CONV_NONE;
+  if (cv && (INV || contiguous || (L != 4 && L != 8) || conv->count < 1 || conv->count > MAX_FUSED_CONV))
+    fail(HETAL_E_PARAMS, "NTT conversion input outside the first forward pass");
+  if (row_scale && !(INV && !contiguous)) fail(HETAL_E_PARAMS, "NTT row scaling outside the last inverse pass");
+  const NttEpilogue no_epi{};
+  const NttConv no_conv{};
   c.begin_launch();
   if (epi) {
-    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod,
-                       c.d_pc, c.log_n, s0, *epi);
+    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, CONV_NONE, 1>), grid, block, 0, c.stream, pa, rows.d, tw,
+                       c.d_mod, c.d_pc, c.log_n, s0, *epi, no_conv, nullptr);
+  } else if (cv) {
+    const int key = (L == 8 ? 100 : 0) + conv->kind * 10 + conv->count;
+    switch (key) {
+#define HETAL_NTT_CONV(LL, K, C)                                                                               \
+  case (LL == 8 ? 100 : 0) + K * 10 + C:                                                                     \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, false, false, false, K, C>), grid, block, 0, c.stream, pa, rows.d, tw, \
+                       c.d_mod, c.d_pc, c.log_n, s0, no_epi, *conv, nullptr);                                \
+    break;
+#define HETAL_NTT_CONV_L(LL) \
+  HETAL_NTT_CONV(LL, 1, 1) HETAL_NTT_CONV(LL, 1, 2) HETAL_NTT_CONV(LL, 1, 3) HETAL_NTT_CONV(LL, 1, 4) \
+  HETAL_NTT_CONV(LL, 2, 1) HETAL_NTT_CONV(LL, 2, 2) HETAL_NTT_CONV(LL, 2, 3) HETAL_NTT_CONV(LL, 2, 4)
+      HETAL_NTT_CONV_L(4)
+      HETAL_NTT_CONV_L(8)
+#undef HETAL_NTT_CONV_L
+#undef HETAL_NTT_CONV
+      default:
+        fail(HETAL_E_PARAMS, "unsupported NTT conversion input");
+    }
   } else {
     switch (L * 2 + (contiguous ? 1 : 0)) {
-#define HETAL_NTT_CASE(LL, CC)                                                                                \
-  case LL * 2 + CC:                                                                                         \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC, false>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_mod, \
-                       c.d_pc, c.log_n, s0, none);                                                          \
+#define HETAL_NTT_CASE(LL, CC)                                                                                 \
+  case LL * 2 + CC:                                                                                          \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC, false, CONV_NONE, 1>), grid, block, 0, c.stream, pa, rows.d, \
+                       tw, c.d_mod, c.d_pc, c.log_n, s0, no_epi, no_conv, row_scale);                        \
     break;
       HETAL_NTT_CASE(4, 0)
       HETAL_NTT_CASE(5, 0)
@@ -317,33 +399,40 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
         fail(HETAL_E_PARAMS, "unsupported NTT pass size");
     }
   }
+  const double words = (double)c.n * rows.count * batch;
   if (epi) {
     // per word: the pass input and a read, out written; addx on every row, add0 / add1 on half of them
     const double per_word = 24.0 + (epi->addx ? 8.0 : 0.0) + (epi->add0 ? 4.0 : 0.0) + (epi->add1 ? 4.0 : 0.0);
-    c.end_launch(KC_NTT_FWD_EPILOGUE, per_word * c.n * rows.count * batch);
+    c.end_launch(KC_NTT_FWD_EPILOGUE, per_word * words);
+  } else if (cv) {
+    // the source rows once per item (l limbs for ModUp, 2K special rows for ModDown), every output word written
+    const double src_rows = conv->kind == CONV_MODUP ? (double)(conv->ext - c.num_p) : 2.0 * conv->count;
+    c.end_launch(conv->kind == CONV_MODUP ? KC_NTT_FWD_MODUP : KC_NTT_FWD_MODDOWN,
+                 8.0 * words + 8.0 * (double)c.n * src_rows * batch);
   } else {
     const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
                         : (contiguous ? KC_NTT_FWD_CONTIG : KC_NTT_FWD_STRIDED);
-    c.end_launch(cls, 16.0 * c.n * rows.count * batch);  // every residue read and written once
+    c.end_launch(cls, 16.0 * words);  // every residue read and written once
   }
 }
 
 }  // namespace
 
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
-                 const NttEpilogue* epi) {
+                 const NttEpilogue* epi, const NttConv* conv) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
-  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src);
+  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src, nullptr, conv);
   launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, NttSrc{}, epi);
   c.counters[6] += (int64_t)rows.count * batch;
 }
 
-void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
+                 const NttScale* row_scale) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
   launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, src);
-  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{});
+  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{}, nullptr, nullptr, row_scale);
   c.counters[6] += (int64_t)rows.count * batch;
 }
 

@@ -361,32 +361,50 @@ void key_switch(Context& c, const KsJob& job) {
   const size_t acc_words = 2 * (size_t)ext * n;
   const size_t conv_words = 2 * poly;
 
+  // The basis conversions run fused into the first pass of the NTT that follows them when the pass shape and
+  // term count allow (the inverse NTT before each then applies the conversion's first factor).
+  const bool fuse_up = c.alpha <= MAX_FUSED_CONV && (c.log_n == 12 || c.log_n == 16);
+  const bool fuse_down = c.num_p <= MAX_FUSED_CONV && (c.log_n == 12 || c.log_n == 16);
+
   // 1. coefficient form of the input(s): the inverse NTT reads the input in place of a copy
   Tmp coef(c.pool, m_in * poly);
   RowsRef ct_rows = c.rows(ROWS_CT, level);
   NttSrc src;
   src.p = job.in;
   src.batch_stride = hoisted ? 0 : job.in_stride;
-  ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l}, src);
+  ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l}, src,
+              fuse_up ? c.d_modup_scale + (size_t)level * MAX_PRIMES : nullptr);
 
   // 2. ModUp of every digit, then the NTT of the converted rows
   Tmp dt(c.pool, m_in * dt_words);
-  c.begin_launch();
-  switch (c.alpha) {
+  if (fuse_up) {
+    NttConv cv;
+    cv.kind = CONV_MODUP;
+    cv.count = c.alpha;
+    cv.y = coef.p;
+    cv.y_stride = poly;
+    cv.ext = ext;
+    cv.num_q = c.num_q;
+    cv.modup = c.d_modup + (size_t)level * c.dnum;
+    ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level), NttSrc{}, nullptr, &cv);
+  } else {
+    c.begin_launch();
+    switch (c.alpha) {
 #define HETAL_MODUP(A)                                                                                          \
   case A:                                                                                                     \
     hipLaunchKernelGGL(modup_kernel<A>, grid_for(c, beta, m_in), dim3(TPB), 0, c.stream, coef.p, poly, dt.p, dt_words, \
                        c.d_modup + (size_t)level * c.dnum, c.d_mod, c.log_n, level, c.num_q, c.num_p);        \
     break;
-    HETAL_MODUP(1) HETAL_MODUP(2) HETAL_MODUP(3) HETAL_MODUP(4) HETAL_MODUP(5) HETAL_MODUP(6) HETAL_MODUP(7)
-    HETAL_MODUP(8)
+      HETAL_MODUP(1) HETAL_MODUP(2) HETAL_MODUP(3) HETAL_MODUP(4) HETAL_MODUP(5) HETAL_MODUP(6) HETAL_MODUP(7)
+      HETAL_MODUP(8)
 #undef HETAL_MODUP
-    default:
-      fail(HETAL_E_PARAMS, "digit length above 8");
+      default:
+        fail(HETAL_E_PARAMS, "digit length above 8");
+    }
+    // reads: each digit's coefficient-form limbs (l rows in all); writes the beta * ext - l rows outside the digits
+    c.end_launch(KC_MODUP, 8.0 * n * m_in * ((double)beta * ext));
+    ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level));
   }
-  // reads: each digit's coefficient-form limbs (l rows in all); writes the beta * ext - l rows outside the digits
-  c.end_launch(KC_MODUP, 8.0 * n * m_in * ((double)beta * ext));
-  ntt_forward(c, dt, dt_words, m_in, c.rows(ROWS_MODUP, level));
 
   // 3. inner product with the keys, automorphism applied on the loads
   Tmp acc(c.pool, m * acc_words);
@@ -429,21 +447,33 @@ void key_switch(Context& c, const KsJob& job) {
   }
 
   // 4. ModDown: special rows to coefficient form, centred conversion, NTT, combine
-  ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level));
+  ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level), NttSrc{}, fuse_down ? c.d_moddown_scale : nullptr);
   Tmp conv(c.pool, m * conv_words);
-  c.begin_launch();
-  switch (c.num_p) {
+  NttConv cv;
+  if (fuse_down) {
+    cv.kind = CONV_MODDOWN;
+    cv.count = c.num_p;
+    cv.y = acc.p;
+    cv.y_stride = acc_words;
+    cv.ext = ext;
+    cv.l = l;
+    cv.num_q = c.num_q;
+    cv.moddown = c.d_moddown;
+  } else {
+    c.begin_launch();
+    switch (c.num_p) {
 #define HETAL_CONV(K)                                                                                          \
   case K:                                                                                                    \
     hipLaunchKernelGGL(moddown_conv_kernel<K>, grid_for(c, 2, m), dim3(TPB), 0, c.stream, acc.p, acc_words, conv.p, \
                        conv_words, c.d_moddown, c.d_mod, c.log_n, level, c.num_q);                           \
     break;
-    HETAL_CONV(1) HETAL_CONV(2) HETAL_CONV(3) HETAL_CONV(4) HETAL_CONV(5) HETAL_CONV(6) HETAL_CONV(7) HETAL_CONV(8)
+      HETAL_CONV(1) HETAL_CONV(2) HETAL_CONV(3) HETAL_CONV(4) HETAL_CONV(5) HETAL_CONV(6) HETAL_CONV(7) HETAL_CONV(8)
 #undef HETAL_CONV
-    default:
-      fail(HETAL_E_PARAMS, "more than 8 special primes");
+      default:
+        fail(HETAL_E_PARAMS, "more than 8 special primes");
+    }
+    c.end_launch(KC_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
   }
-  c.end_launch(KC_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
   // ... and the combine (acc_Q - conv) P^-1 + addends as the epilogue of the NTT's last pass
   NttEpilogue epi;
   epi.a = acc.p;
@@ -462,7 +492,7 @@ void key_switch(Context& c, const KsJob& job) {
   epi.addx = job.addx;
   epi.addx_stride = job.addx_stride;
   for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = i < m ? job.item[i].g : 1;
-  ntt_forward(c, conv, conv_words, m, ct_rows, NttSrc{}, &epi);
+  ntt_forward(c, conv, conv_words, m, ct_rows, NttSrc{}, &epi, fuse_down ? &cv : nullptr);
   c.counters[5] += m;
 }
 
