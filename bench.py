@@ -29,6 +29,7 @@ METRIC = "encrypted 128x768x10 matmuls/s at N=2^16; HRot/s; p99 latency batched"
 HBM_PEAK_GBS = 8000.0
 SEEDS = dict(data=1002, keys=2000, enc=3000)
 A_ROWS, FEAT, CLASSES, C_PAD, S0, LEVEL = 128, 768, 10, 16, 128, 11
+HROT_BATCH, BATCH_REPS = 64, 5
 
 
 def log(msg):
@@ -237,6 +238,89 @@ def recorded_traffic(cls):
     return None
 
 
+# The paper's Table 4 shapes (a, b, c) with s0 = a, its A40 seconds per call (DiagABT, DiagATB on the level(A) >=
+# level(B) branch), and its corrected operation counts (Table matnum_fixed).
+PAPER_SHAPES = [
+    ((128, 128, 4), 0.0601, 0.0415),
+    ((256, 256, 8), 0.1211, 0.1239),
+    ((512, 769, 4), 0.1223, 0.3343),
+    ((1024, 769, 8), 0.3710, 1.2558),
+    ((2048, 769, 16), 1.2376, 4.9970),
+]
+
+
+def paper_shapes(reps):
+    """DiagABT and both DiagATB branches at the paper's Table 4 shapes; one JSON line per shape."""
+    import torch
+    from paper_2403_14111_amd import hetal, inputs
+    counts = {(r["a"], r["b"], r["c"]): r for r in json.load(open(os.path.join(
+        os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "matnum_fixed.json")))["rows"]}
+    ctx = hetal.Context("n16l12")
+    sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
+    for (a, b, c), paper_abt, paper_atb in PAPER_SHAPES:
+        s0 = a
+        s1 = ctx.slots // s0
+        log("shape %dx%dx%d: keys" % (a, b, c))
+        steps = sorted(set(ctx.required_rot_steps(0, c, s0)) | set(ctx.required_rot_steps(1, c, s0)) |
+                       set(ctx.required_rot_steps(2, c, s0)))
+        keys = ctx.keys_create()
+        ra, re_ = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
+        keys.gen_relin(sk, ra, re_)
+        for g in sorted(set(ctx.galois_rot(r) for r in steps) | {ctx.galois_conj()}):
+            ra, re_ = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(1, g), ctx.dnum, ctx.primes, ctx.n)
+            keys.gen_galois(sk, g, ra, re_)
+        A = inputs.toy_matrix(SEEDS["data"] + a, a, b, 0)
+        B = inputs.toy_matrix(SEEDS["data"] + a, c, b, 1)
+        P = inputs.toy_matrix(SEEDS["data"] + a + 1, a, c, 0)
+
+        def enc(mat, tiling, level, first):
+            nb = int(np.prod(ctx.mat_blocks(mat.shape[0], mat.shape[1], s0, tiling, c)))
+            ea, ee = enc_randomness(ctx, nb, level, first)
+            return ctx.mat_encrypt(sk, mat, s0, level, 2.0 ** 40, ea, ee, tiling=tiling, c=c)
+
+        ga = enc(A, 0, LEVEL, 0)
+        gb = enc(B, 1, LEVEL, 1000)
+        gp = enc(P, 2, LEVEL, 2000)
+        gp_low = enc(P, 2, LEVEL - 1, 3000)
+        runs = {"abt": lambda: ctx.enc_matmul_abt(keys, ga, gb, c, 1.0),
+                "atb_rl": lambda: ctx.enc_matmul_atb(keys, gp, ga, c, 1.0),
+                "atb_pru": lambda: ctx.enc_matmul_atb(keys, gp_low, ga, c, 1.0)}
+        line = {"shape": {"a": a, "b": b, "c": c}, "s0": s0, "s1": s1, "unit": "s per call", "reps": reps}
+        ops, err = {}, {}
+        for name, f in runs.items():
+            out = f()  # warm-up: masks are encoded once and cached
+            torch.cuda.synchronize()
+            ctx.reset_counters()
+            f()
+            torch.cuda.synchronize()
+            ops[name] = ctx.counters()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                f()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            line[name + "_s"] = round(float(np.median(ts)), 5)
+            res = ctx.mat_decrypt(sk, out)
+            if name == "abt":
+                ref = np.tile(A @ B.T, (1, s1 // c))
+                err[name] = float(np.max(np.abs(res[:a, :s1] - ref)))
+            else:
+                ref = np.tile(P.T @ A, (s0 // c, 1))
+                err[name] = float(np.max(np.abs(res[:s0, :b] - ref)))
+        row = counts[(a, b, c)]
+        line["ops_match_table"] = (
+            {k: ops["abt"][k] for k in ("cmult", "mult", "rot")} == row["abt"]
+            and {k: ops["atb_rl"][k] for k in ("cmult", "mult", "rot")} == row["atb_rl"]
+            and {k: ops["atb_pru"][k] for k in ("cmult", "rot")} == row["atb_pru"])
+        line["ops"] = {k: {kk: v[kk] for kk in ("rot", "conj", "mult", "cmult", "keyswitch")} for k, v in ops.items()}
+        line["max_abs_err"] = err
+        line["paper_a40_s"] = {"abt": paper_abt, "atb": paper_atb, "note": "A40 + HEaaN, Table 4; context only"}
+        print(json.dumps(line), flush=True)
+        del keys, ga, gb, gp, gp_low
+        torch.cuda.empty_cache()
+
+
 def cpu_baseline(X, W, gpu_abt_coeffs):
     """The oracle (never tuned) on one full DiagABT of the same workload."""
     from oracle import ckks
@@ -279,7 +363,7 @@ def cpu_baseline(X, W, gpu_abt_coeffs):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--hrot-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (e.g. under a profiler)")
@@ -291,6 +375,9 @@ def main():
                          "WRITE_SIZE/) as markdown; --steps is the trace run's step count, --pmc-steps the counter "
                          "runs' one")
     ap.add_argument("--pmc-steps", type=int, default=2)
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="instead of the benchmark: DiagABT / DiagATB (both branches) at the paper's Table 4 shapes, "
+                         "one JSON line per shape (median of --steps calls)")
     ap.add_argument("--bench-json", metavar="FILE", help="with --trace-summary: a bench.py output line to compare")
     args = ap.parse_args()
     if args.trace_summary:
@@ -305,6 +392,9 @@ def main():
     from paper_2403_14111_amd import hetal, inputs
 
     torch.cuda.set_device(0)
+    if args.paper_shapes:
+        paper_shapes(args.steps)
+        return
     log("context + keys")
     ctx = hetal.Context("n16l12")
     sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
@@ -401,6 +491,25 @@ def main():
         ctx.hrot(keys, ct, 1)
     torch.cuda.synchronize()
     hrot_s = args.hrot_reps / (time.perf_counter() - t0)
+    # 64 independent ciphertexts in one batched call: all by one step (one key), and each by its own step
+    batch = ctx.new_ct_batch(HROT_BATCH, LEVEL)
+    for b in batch:
+        b.buf.copy_(ct.buf)
+        b.scale = ct.scale
+    out = ctx.new_ct_batch(HROT_BATCH, LEVEL)
+    avail = key_steps(ctx)
+    distinct = [avail[i % len(avail)] for i in range(HROT_BATCH)]
+    hrot_batched = {}
+    for name, steps in (("same_key", 1), ("distinct_keys", distinct)):
+        ctx.hrot_batch(keys, batch, steps, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(BATCH_REPS):
+            ctx.hrot_batch(keys, batch, steps, out=out)
+        torch.cuda.synchronize()
+        hrot_batched[name] = round(HROT_BATCH * BATCH_REPS / (time.perf_counter() - t0), 1)
+    hrot_batched["distinct_key_count"] = len(set(distinct))
+    del batch, out
 
     # ---- CPU baseline (the oracle) on one DiagABT of the same workload
     cpu = None
@@ -433,6 +542,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": {k: v for k, v in (cpu or {}).items() if k != "seconds"} if cpu else None,
         "hrot_per_s": round(hrot_s, 1),
+        "hrot_batched_per_s": dict(hrot_batched, batch=HROT_BATCH, level=LEVEL),
         "step_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
         "step_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
         "max_abs_err": {"abt": err_y, "atb": err_g, "bound": 2.0 ** -18},

@@ -170,6 +170,14 @@ int hetal_hmult(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* a, const
  * digits, inner product with the key, ModDown with a centred basis
  * conversion; plus tau_g(c0).  E_NO_KEY without the Galois key. */
 int hetal_hrot(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, int r, hetal_ct* out);
+/* HRot of `count` ciphertexts at one level: out[i] = Lrot(in[i], steps[i]) (Sec. 2.2), as one batched key
+ * switch per group of up to 32 rotations; rotations that share a step share the key's loads.  A step that
+ * is 0 mod N/2 copies.  Inputs evenly spaced in one allocation, and outputs likewise, are used in place;
+ * other layouts go through a packed device copy.  Outputs must not overlap the inputs or each other
+ * (E_INVALID_ARG).  All inputs at one level (E_LEVEL); each output keeps its input's scale.  E_NO_KEY
+ * without a step's Galois key. */
+int hetal_hrot_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* in, const int* steps, int count,
+                     hetal_ct* out);
 /* Slot-wise complex conjugation (Galois element 2N-1). */
 int hetal_conj(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, hetal_ct* out);
 /* Rescale: c_i <- (c_i - [c_l]_centred) q_l^-1 mod q_i, level - 1, scale / q_l.

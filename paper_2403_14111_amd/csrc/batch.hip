@@ -175,8 +175,9 @@ Batch b_rescale(Context& c, BView a) {
 
 static void run_rotations(Context& c, const KeySet& k, const u64* in0, size_t in_stride, int count, bool hoisted,
                           const std::vector<u32>& gal, int level, u64* out, const u64* addx = nullptr,
-                          size_t addx_stride = 0) {
-  const size_t poly = c.poly_words(level), w = c.ct_words(level);
+                          size_t addx_stride = 0, size_t out_stride = 0) {
+  const size_t poly = c.poly_words(level);
+  const size_t w = out_stride ? out_stride : c.ct_words(level);
   for (int first = 0; first < count; first += MAX_BATCH) {
     const int m = std::min(MAX_BATCH, count - first);
     KsJob job;
@@ -214,6 +215,15 @@ Batch b_rotate(Context& c, const KeySet& k, BView a, const std::vector<int>& ste
   o.scale = a.scale;
   c.counters[0] += a.count;
   return o;
+}
+
+void b_rotate_into(Context& c, const KeySet& k, BView a, const std::vector<u32>& gal, u64* out, size_t out_stride) {
+  if ((int)gal.size() != a.count) fail(HETAL_E_INVALID_ARG, "one Galois element per item");
+  for (u32 g : gal)
+    if (g == 1) fail(HETAL_E_INVALID_ARG, "identity rotation inside a batch");
+  if (out_stride < c.ct_words(a.level)) fail(HETAL_E_INVALID_ARG, "output stride below one ciphertext");
+  run_rotations(c, k, a.d, a.stride, a.count, false, gal, a.level, out, nullptr, 0, out_stride);
+  c.counters[0] += a.count;
 }
 
 Batch b_rotate_add(Context& c, const KeySet& k, BView a, int step, const BView* addend) {

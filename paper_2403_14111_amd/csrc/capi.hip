@@ -1,5 +1,6 @@
 // extern "C" entry points: argument validation, error translation, and the
 // host <-> device transfers of the client-side calls.
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -387,6 +388,74 @@ int hetal_hrot(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, int r
     ctx->c.counters[0] += 1;
     out->level = lv;
     out->scale = s;
+  });
+}
+
+int hetal_hrot_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* in, const int* steps, int count,
+                     hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && keys && in && steps && out && count >= 0, HETAL_E_INVALID_ARG, "null argument");
+    if (count == 0) return;
+    Context& c = ctx->c;
+    const int lv = in[0].level;
+    const size_t w = c.ct_words(lv);
+    std::vector<std::pair<uintptr_t, int>> spans;  // (start, +1 input / -1 output), for the overlap check
+    for (int i = 0; i < count; ++i) {
+      check_ct(c, &in[i], "ciphertext");
+      need(in[i].level == lv, HETAL_E_LEVEL, "batch items at different levels");
+      check_out(c, &out[i], lv);
+      spans.push_back({(uintptr_t)in[i].data, 1});
+      spans.push_back({(uintptr_t)out[i].data, -1});
+    }
+    // outputs overlap no input and no other output (each span is w words)
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i) {
+      const bool overlap = spans[i].first < spans[i - 1].first + w * 8;
+      need(!overlap || (spans[i].second > 0 && spans[i - 1].second > 0), HETAL_E_INVALID_ARG,
+           "outputs overlap the inputs or each other");
+    }
+    std::vector<int> rot, idn;
+    std::vector<u32> gal;
+    for (int i = 0; i < count; ++i) {
+      const u32 g = galois_rot(c, steps[i]);
+      if (g == 1) {
+        idn.push_back(i);
+      } else {
+        rot.push_back(i);
+        gal.push_back(g);
+      }
+    }
+    for (int i : idn) HCHECK(hipMemcpyAsync(out[i].data, in[i].data, w * 8, hipMemcpyDeviceToDevice, c.stream));
+    if (!rot.empty()) {
+      const int m = (int)rot.size();
+      // evenly spaced handles are used in place; anything else goes through a packed copy
+      auto even = [&](auto ptr) {
+        if (m == 1) return (size_t)w;
+        const intptr_t d = (intptr_t)ptr(1) - (intptr_t)ptr(0);
+        if (d < (intptr_t)(w * 8) || d % 8) return (size_t)0;
+        for (int t = 2; t < m; ++t)
+          if ((intptr_t)ptr(t) - (intptr_t)ptr(t - 1) != d) return (size_t)0;
+        return (size_t)(d / 8);
+      };
+      const size_t sin = even([&](int t) { return in[rot[t]].data; });
+      const size_t sout = even([&](int t) { return out[rot[t]].data; });
+      if (sin && sout) {
+        b_rotate_into(c, keys->set, BView{in[rot[0]].data, lv, m, in[rot[0]].scale, sin}, gal, out[rot[0]].data,
+                      sout);
+      } else {
+        std::vector<CtView> items;
+        for (int i : rot) items.push_back(view_of(&in[i]));
+        Batch packed = b_pack(c, items);
+        Batch res(c, lv, m);
+        b_rotate_into(c, keys->set, packed.v(), gal, res.d, w);
+        for (int t = 0; t < m; ++t)
+          HCHECK(hipMemcpyAsync(out[rot[t]].data, res.d + (size_t)t * w, w * 8, hipMemcpyDeviceToDevice, c.stream));
+      }
+    }
+    for (int i = 0; i < count; ++i) {
+      out[i].level = lv;
+      out[i].scale = in[i].scale;
+    }
   });
 }
 

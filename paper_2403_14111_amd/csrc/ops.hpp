@@ -157,6 +157,8 @@ Batch b_mod_drop(Context& c, BView a, int level);
 Batch b_rescale(Context& c, BView a);
 // Item i rotated left by steps[i] (steps.size() == 1: the same step for all).
 Batch b_rotate(Context& c, const KeySet& k, BView a, const std::vector<int>& steps);
+// tau_{gal[i]}(a[i]) written to out + i out_stride (no identity elements; out must not overlap a).
+void b_rotate_into(Context& c, const KeySet& k, BView a, const std::vector<u32>& gal, u64* out, size_t out_stride);
 // addend[i] + Lrot(a[i], step) for every item (addend defaults to a itself),
 // the addition fused into the key switch's last kernel.
 Batch b_rotate_add(Context& c, const KeySet& k, BView a, int step, const BView* addend = nullptr);

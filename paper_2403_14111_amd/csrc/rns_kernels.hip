@@ -538,31 +538,36 @@ void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int lev
 
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
   const size_t n = c.n;
-  Tmp top(c.pool, (size_t)batch * 2 * n);
-  NttSrc src;
-  src.p = in;
-  src.batch_stride = in_stride;
-  src.row_mul = level + 1;  // top row of poly p: p (level + 1) + level
-  src.row_add = level;
-  ntt_inverse(c, top, 2 * n, batch, c.rows(ROWS_TOP, level), src);
-  Tmp spread(c.pool, (size_t)batch * 2 * level * n);
-  c.begin_launch();
-  hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, batch), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
-                     2 * (size_t)level * n, c.d_mod, c.log_n, level);
-  c.end_launch(KC_RESCALE, 8.0 * n * batch * (2.0 + 2.0 * level));
-  // out = (in - spread) q_level^-1, as the epilogue of the spread rows' NTT
-  if (batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "rescale batch");
-  NttEpilogue epi;
-  epi.a = in;
-  epi.a_stride = in_stride;
-  epi.a_poly_rows = level + 1;
-  epi.l = level;
-  epi.cst = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv));
-  epi.cst_sh = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv_sh));
-  epi.out = out;
-  epi.out_stride = out_stride;
-  for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = 1;
-  ntt_forward(c, spread, 2 * (size_t)level * n, batch, c.rows(ROWS_CT, level - 1), NttSrc{}, &epi);
+  // groups of at most MAX_BATCH items (the NTT epilogue's per-launch limit)
+  for (int first = 0; first < batch; first += MAX_BATCH) {
+    const int m = std::min(MAX_BATCH, batch - first);
+    const u64* in_m = in + (size_t)first * in_stride;
+    u64* out_m = out + (size_t)first * out_stride;
+    Tmp top(c.pool, (size_t)m * 2 * n);
+    NttSrc src;
+    src.p = in_m;
+    src.batch_stride = in_stride;
+    src.row_mul = level + 1;  // top row of poly p: p (level + 1) + level
+    src.row_add = level;
+    ntt_inverse(c, top, 2 * n, m, c.rows(ROWS_TOP, level), src);
+    Tmp spread(c.pool, (size_t)m * 2 * level * n);
+    c.begin_launch();
+    hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, m), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
+                       2 * (size_t)level * n, c.d_mod, c.log_n, level);
+    c.end_launch(KC_RESCALE, 8.0 * n * m * (2.0 + 2.0 * level));
+    // out = (in - spread) q_level^-1, as the epilogue of the spread rows' NTT
+    NttEpilogue epi;
+    epi.a = in_m;
+    epi.a_stride = in_stride;
+    epi.a_poly_rows = level + 1;
+    epi.l = level;
+    epi.cst = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv));
+    epi.cst_sh = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv_sh));
+    epi.out = out_m;
+    epi.out_stride = out_stride;
+    for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = 1;
+    ntt_forward(c, spread, 2 * (size_t)level * n, m, c.rows(ROWS_CT, level - 1), NttSrc{}, &epi);
+  }
   c.counters[4] += batch;
 }
 

@@ -84,6 +84,7 @@ _SIGS = {
     "hetal_cmult": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
     "hetal_hmult": (ctypes.c_int, [_vp, _vp, _ctp, _ctp, _ctp]),
     "hetal_hrot": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_int, _ctp]),
+    "hetal_hrot_batch": (ctypes.c_int, [_vp, _vp, _ctp, _intp, ctypes.c_int, _ctp]),
     "hetal_conj": (ctypes.c_int, [_vp, _vp, _ctp, _ctp]),
     "hetal_rescale": (ctypes.c_int, [_vp, _ctp, _ctp]),
     "hetal_mod_drop": (ctypes.c_int, [_vp, _ctp, ctypes.c_int, _ctp]),
@@ -145,11 +146,12 @@ PRESETS = {
 
 
 class Ciphertext:
-    """Device buffer ([2][level+1][N] words) + level + scale.  Also used for plaintexts ([level+1][N])."""
+    """Device buffer ([2][level+1][N] words) + level + scale.  Also used for plaintexts ([level+1][N]).
+    `buf` may be a view into a larger tensor (see Context.new_ct_batch)."""
 
-    def __init__(self, ctx, level, words, scale=0.0):
+    def __init__(self, ctx, level, words, scale=0.0, buf=None):
         self.ctx = ctx
-        self.buf = torch.empty(words, dtype=torch.int64, device=ctx.device)
+        self.buf = torch.empty(words, dtype=torch.int64, device=ctx.device) if buf is None else buf
         self.level = level
         self.scale = scale
 
@@ -212,6 +214,12 @@ class Context:
 
     def new_ct(self, level):
         return Ciphertext(self, level, self.ct_words(level))
+
+    def new_ct_batch(self, count, level):
+        """`count` ciphertexts at `level` laid out back to back in one device buffer."""
+        w = self.ct_words(level)
+        big = torch.empty(max(count, 1) * w, dtype=torch.int64, device=self.device)
+        return [Ciphertext(self, level, w, buf=big[i * w:(i + 1) * w]) for i in range(count)]
 
     def new_pt(self, level):
         return Ciphertext(self, level, (level + 1) * self.n)
@@ -326,6 +334,23 @@ class Context:
         s = out._struct()
         _check(_lib.hetal_hrot(self._h, keys._h, ctypes.byref(a._struct()), int(r), ctypes.byref(s)))
         out.level, out.scale = s.level, s.scale
+        return out
+
+    def hrot_batch(self, keys, cts, steps, out=None):
+        """[Lrot(cts[i], steps[i])] as one batched key switch (steps: one int for all, or one per item)."""
+        n = len(cts)
+        steps = [int(steps)] * n if np.ndim(steps) == 0 else [int(s) for s in steps]
+        if len(steps) != n:
+            raise ValueError("one step per ciphertext")
+        if n == 0:
+            return []
+        out = self.new_ct_batch(n, cts[0].level) if out is None else out
+        ins = (_Ct * n)(*[c._struct() for c in cts])
+        outs = (_Ct * n)(*[o._struct() for o in out])
+        st = (ctypes.c_int * n)(*steps)
+        _check(_lib.hetal_hrot_batch(self._h, keys._h, ins, st, n, outs))
+        for o, s in zip(out, outs):
+            o.level, o.scale = s.level, s.scale
         return out
 
     def conj(self, keys, a):

@@ -123,6 +123,34 @@ def test_hrot_identity_and_missing_key(toy):
     assert ei.value.name == "E_NO_KEY"
 
 
+@pytest.mark.parametrize("layout", ["packed_buffer", "separate"])
+def test_hrot_batch_bit_exact(toy, layout):
+    """One batched call: mixed steps (shared and distinct keys, and the identity), against single oracle rotations."""
+    from paper_2403_14111_amd import hetal
+    ctx, sk, keys, ev = toy
+    level = 3
+    steps = [1, 1, 2, -5, 0, 2047, 1, 256]
+    note("hrot_batch %s" % layout)
+    zs = [inputs.slot_values(100 + i, ctx.slots) for i in range(len(steps))]
+    refs = [encrypt_slots(ev, z, level, index=40 + i) for i, z in enumerate(zs)]
+    if layout == "packed_buffer":
+        cts = ctx.new_ct_batch(len(steps), level)
+        for i, z in enumerate(zs):
+            one = encrypt_slots_gpu(ctx, sk, z, level, index=40 + i)
+            cts[i].buf.copy_(one.buf)
+            cts[i].scale = one.scale
+    else:
+        cts = [encrypt_slots_gpu(ctx, sk, z, level, index=40 + i) for i, z in enumerate(zs)]
+    outs = ctx.hrot_batch(keys, cts, steps)
+    for out, ref, r in zip(outs, refs, steps):
+        same(ctx.ct_to_coeff(out), ev.rot(ref, r) if r else ref)
+        assert out.level == level
+    # outputs may not overlap the inputs
+    with pytest.raises(hetal.HetalError) as ei:
+        ctx.hrot_batch(keys, cts, steps, out=cts)
+    assert ei.value.name == "E_INVALID_ARG"
+
+
 @pytest.mark.parametrize("level", [1, 4])
 def test_conj_bit_exact(toy, level):
     ctx, sk, keys, ev = toy
@@ -245,7 +273,8 @@ def compare_blocks(ctx, gmat, oblocks):
 
 
 @pytest.mark.parametrize("shape", [(16, 32, 8, 16), (13, 45, 4, 16), (40, 300, 8, 16), (16, 32, 2, 16),
-                                   (16, 200, 8, 8)], ids=["base", "ragged", "multiblock", "c2", "s0_8"])
+                                   (16, 200, 8, 8), (16, 1152, 8, 16)],
+                         ids=["base", "ragged", "multiblock", "c2", "s0_8", "wide_36_products"])
 def test_diag_abt_bit_exact(toy_mm, shape):
     ctx, sk, keys, ev = toy_mm
     a_rows, b_cols, c, s0 = shape
@@ -266,7 +295,8 @@ def test_diag_abt_bit_exact(toy_mm, shape):
 
 
 @pytest.mark.parametrize("pru", [False, True])
-@pytest.mark.parametrize("shape", [(16, 32, 8), (30, 150, 4), (16, 32, 2)], ids=["base", "multiblock", "c2"])
+@pytest.mark.parametrize("shape", [(16, 32, 8), (30, 150, 4), (16, 32, 2), (16, 1152, 8)],
+                         ids=["base", "multiblock", "c2", "wide_36_products"])
 def test_diag_atb_bit_exact(toy_mm, pru, shape):
     ctx, sk, keys, ev = toy_mm
     a_rows, b_cols, c = shape
