@@ -27,6 +27,7 @@ import numpy as np
 
 METRIC = "encrypted 128x768x10 matmuls/s at N=2^16; HRot/s; p99 latency batched"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 SEEDS = dict(data=1002, keys=2000, enc=3000)
 A_ROWS, FEAT, CLASSES, C_PAD, S0, LEVEL = 128, 768, 10, 16, 128, 11
 HROT_BATCH, BATCH_REPS = 64, 5
@@ -166,8 +167,8 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
         a = agg.setdefault(cls, [0, 0.0, 0.0])
         a[0] += 1
         a[1] += dur
-        if cls.startswith("ntt_"):
-            a[2] += grid * 16 * 16.0  # 16 residues per thread, each read and written once
+        if cls in ("ntt_fwd_strided", "ntt_fwd_contig", "ntt_inv_contig", "ntt_inv_strided"):
+            a[2] += grid * 16 * 16.0  # plain passes: 16 residues per thread, each read and written once
     lines = ["# Kernel profile: DiagABT + DiagATB step, N=2^16, level 11 (bench workload)", "",
              "Commands (repository root; DIR is any output folder):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d DIR/trace -o trace -- "
@@ -176,14 +177,20 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
              "python bench.py --profile --steps %d --warmup 1" % pmc_steps,
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/WRITE_SIZE -o pmc -- "
              "python bench.py --profile --steps %d --warmup 1" % pmc_steps,
+             "    rocprofv3 --pmc SQ_INSTS_VALU --output-format csv -d DIR/SQ_INSTS_VALU -o pmc -- "
+             "python bench.py --profile --steps %d --warmup 1" % pmc_steps,
              ] + (["    python bench.py --steps %d --warmup 2 --no-cpu-baseline > BENCH.json" % steps] if bench else []) + [
              "    python bench.py --trace-summary DIR --steps %d --pmc-steps %d%s" % (
                  steps, pmc_steps, " --bench-json BENCH.json" if bench else ""), "",
              "Timed region: the last %d steps of the trace (%d kernels per step).  HBM MB/launch: FETCH_SIZE and "
              "WRITE_SIZE (KiB per dispatch) scaled by what they read for the closing plain copy, averaged over the "
-             "class's launches in the counter runs' timed steps." % (steps, per_step), "",
-             "| kernel | launches/step | avg us | ms/step | algorithmic GB/s | HBM MB/launch (counters) |",
-             "|---|---|---|---|---|---|"]
+             "class's launches in the counter runs' timed steps.  HBM frac: those bytes per launch over the average "
+             "launch time, against 8 TB/s.  VALU frac: SQ_INSTS_VALU (wave instructions) x 64 lanes per launch over the "
+             "average launch time, against 39.3 T lane-ops/s (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz)." % (
+                 steps, per_step), "",
+             "| kernel | launches/step | avg us | ms/step | algorithmic GB/s | HBM MB/launch (counters) | HBM frac "
+             "| VALU frac |",
+             "|---|---|---|---|---|---|---|---|"]
     traffic = {}
     scales = {}
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
@@ -199,14 +206,29 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
                 e = traffic.setdefault(cls, {}).setdefault(counter, [0, 0.0])
                 e[0] += 1
                 e[1] += v * 1024.0 * scales[counter]
+    valu = {}
+    f = glob.glob(os.path.join(directory, "SQ_INSTS_VALU", "*counter_collection.csv"))
+    if f:
+        d, _ = read_dispatches(f[0], "SQ_INSTS_VALU")
+        plo, phi, _ = timed_window([x[1] for x in d], pmc_steps)
+        for t, name, dur, grid, v in d[plo:phi]:
+            cls = profile_class(name)
+            if cls:
+                e = valu.setdefault(cls, [0, 0.0])
+                e[0] += 1
+                e[1] += v
     per_launch = {}
     for cls, e in traffic.items():
         if "FETCH_SIZE" in e and "WRITE_SIZE" in e:
             per_launch[cls] = e["FETCH_SIZE"][1] / e["FETCH_SIZE"][0] + e["WRITE_SIZE"][1] / e["WRITE_SIZE"][0]
     for cls, (n, dur, byts) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:16]:
         gbs = "%.0f" % (byts / dur) if byts else ""
+        avg_s = dur / n * 1e-9
         tr = "%.1f" % (per_launch[cls] / 1e6) if cls in per_launch else ""
-        lines.append("| %s | %d | %.1f | %.3f | %s | %s |" % (cls, n // steps, dur / n / 1e3, dur / steps / 1e6, gbs, tr))
+        hf = "%.2f" % (per_launch[cls] / avg_s / (HBM_PEAK_GBS * 1e9)) if cls in per_launch else ""
+        vf = "%.2f" % (valu[cls][1] / valu[cls][0] * 64 / VALU_PEAK_LANE_OPS / avg_s) if cls in valu else ""
+        lines.append("| %s | %d | %.1f | %.3f | %s | %s | %s | %s |" % (
+            cls, n // steps, avg_s * 1e6, dur / steps / 1e6, gbs, tr, hf, vf))
     if bench:
         b = json.load(open(bench))
         r = b["roofline"]
