@@ -221,6 +221,27 @@ int hetal_enc_matmul_abt(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
  * min(lA - 1, lB - 1) - 2), else the RotLeft branch (min(lA - 2, lB) - 2). */
 int hetal_enc_matmul_atb(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* abar, const hetal_mat* b, int c,
                          double t, hetal_mat* out);
+/* One request of a batched call: op 0 = DiagABT (a = <A>, b = <Bbar>), op 1 =
+ * DiagATB (a = <Abar>, b = <B>), with c and t as in the single calls. */
+typedef struct {
+  int op;
+  const hetal_mat* a;
+  const hetal_mat* b;
+  int c;
+  double t;
+} hetal_matmul_req;
+
+/* Many products, of any mix of shapes, in one call: outs[i] receives exactly
+ * what hetal_enc_matmul_abt / _atb would return for reqs[i] (bit-identical
+ * ciphertexts, same levels and scales).  Requests that share (op, c, s0,
+ * input levels, input scales) run in lockstep, so every step of their
+ * algorithm -- each rotation step, relinearisation, rescale, mask product --
+ * is one batched launch sequence over all of their ciphertexts, with the
+ * key read once per step; groups run one after the other.  Errors as in the
+ * single calls; on an error no output is written (checked before any work). */
+int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                           hetal_mat* outs);
+
 /* Rotation steps (signed, left positive) the algorithms need, for key
  * generation: op 0 = DiagABT, 1 = DiagATB (RotLeft branch), 2 = DiagATB
  * (PRotUp branch).  *n: in, capacity of out; out, count written. */

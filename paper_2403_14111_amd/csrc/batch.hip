@@ -54,19 +54,27 @@ __global__ void __launch_bounds__(TPB) cmult_batch_kernel(const u64* __restrict_
       mul_mod(a[item * a_stride + (size_t)row * n + k], p.a[item][(size_t)i * n + k], m);
 }
 
-// out[g][row] = sum_t a[g * per + t][row].
-__global__ void __launch_bounds__(TPB) sum_groups_kernel(const u64* __restrict__ a, size_t a_stride, int per,
-                                                         u64* __restrict__ out, const ModInfo* __restrict__ mods,
-                                                         int log_n, int level) {
+// Segment g of a launch is items [start[g], start[g+1]) of the input (start[0] = 0 relative to the launch's
+// first item).
+constexpr int MAX_SEGMENTS = 64;
+struct SegArgs {
+  int start[MAX_SEGMENTS + 1];
+};
+
+// out[g][row] = sum over the items t of segment g of a[t][row].
+__global__ void __launch_bounds__(TPB) sum_segments_kernel(const u64* __restrict__ a, size_t a_stride, SegArgs sg,
+                                                           u64* __restrict__ out, const ModInfo* __restrict__ mods,
+                                                           int log_n, int level) {
   const int n = 1 << log_n;
   const int l = level + 1;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const int row = blockIdx.y;
   const int g = blockIdx.z;
   const u64 q = mods[row % l].q;
-  const u64* __restrict__ src = a + (size_t)g * per * a_stride + (size_t)row * n + k;
+  const int t0 = sg.start[g], t1 = sg.start[g + 1];
+  const u64* __restrict__ src = a + (size_t)t0 * a_stride + (size_t)row * n + k;
   u64 s = 0;
-  for (int t = 0; t < per; ++t) s = add_mod(s, src[(size_t)t * a_stride], q);
+  for (int t = 0; t < t1 - t0; ++t) s = add_mod(s, src[(size_t)t * a_stride], q);
   out[(size_t)g * 2 * l * n + (size_t)row * n + k] = s;
 }
 
@@ -336,16 +344,35 @@ Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSp
   return o;
 }
 
-Batch b_sum_groups(Context& c, BView a, int groups) {
-  if (groups < 1 || a.count % groups) fail(HETAL_E_INVALID_ARG, "group count must divide the batch");
-  const int per = a.count / groups, l = a.level + 1;
+Batch b_sum_segments(Context& c, BView a, const std::vector<int>& sizes) {
+  int total = 0;
+  for (int z : sizes) {
+    if (z < 1) fail(HETAL_E_INVALID_ARG, "empty segment");
+    total += z;
+  }
+  if (sizes.empty() || total != a.count) fail(HETAL_E_INVALID_ARG, "segments must cover the batch");
+  const int l = a.level + 1;
+  const int groups = (int)sizes.size();
   Batch o(c, a.level, groups);
-  c.begin_launch();
-  hipLaunchKernelGGL(sum_groups_kernel, grid3(c, 2 * l, groups), dim3(TPB), 0, c.stream, a.d, a.stride, per, o.d,
-                     c.d_mod, c.log_n, a.level);
-  c.end_launch(KC_ELEMWISE, 8.0 * c.n * 2.0 * l * (a.count + groups));
+  int item = 0;
+  for (int first = 0; first < groups; first += MAX_SEGMENTS) {
+    const int m = std::min(MAX_SEGMENTS, groups - first);
+    SegArgs sg;
+    sg.start[0] = 0;
+    for (int g = 0; g < m; ++g) sg.start[g + 1] = sg.start[g] + sizes[first + g];
+    c.begin_launch();
+    hipLaunchKernelGGL(sum_segments_kernel, grid3(c, 2 * l, m), dim3(TPB), 0, c.stream, a.d + (size_t)item * a.stride,
+                       a.stride, sg, o.d + (size_t)first * c.ct_words(a.level), c.d_mod, c.log_n, a.level);
+    c.end_launch(KC_ELEMWISE, 8.0 * c.n * 2.0 * l * (sg.start[m] + m));
+    item += sg.start[m];
+  }
   o.scale = a.scale;
   return o;
+}
+
+Batch b_sum_groups(Context& c, BView a, int groups) {
+  if (groups < 1 || a.count % groups) fail(HETAL_E_INVALID_ARG, "group count must divide the batch");
+  return b_sum_segments(c, a, std::vector<int>(groups, a.count / groups));
 }
 
 }  // namespace hetal

@@ -683,6 +683,91 @@ int hetal_enc_matmul_atb(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
   });
 }
 
+int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                           hetal_mat* outs) {
+  return guarded([&] {
+    need(ctx && keys && reqs && outs && count >= 0, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    // validate everything first; then group by what makes the algorithm's step sequence identical
+    std::map<std::tuple<int, int, int, int, int, double, double>, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+      const hetal_matmul_req& r = reqs[i];
+      need(r.op == 0 || r.op == 1, HETAL_E_INVALID_ARG, "request op must be 0 (DiagABT) or 1 (DiagATB)");
+      check_mat(c, r.a, r.op == 0 ? "A" : "Abar");
+      check_mat(c, r.b, r.op == 0 ? "Bbar" : "B");
+      need(r.a->s0 == r.b->s0, HETAL_E_SHAPE, "request block shapes differ");
+      need(r.c >= 2 && (r.c & (r.c - 1)) == 0 && r.a->s1 % r.c == 0 && r.c <= (r.op == 0 ? r.a->s0 : r.a->s1),
+           HETAL_E_SHAPE, "need c a power of two above 1 dividing s1 (and at most s0 for DiagABT)");
+      need(outs[i].data != nullptr, HETAL_E_INVALID_ARG, "output matrix");
+      int lv_a, lv_b;
+      if (r.op == 0) {
+        need(r.b->n_rb == 1 && r.b->n_cb == r.a->n_cb, HETAL_E_SHAPE, "Bbar must be one block row matching A's columns");
+        need(std::min(r.a->level, r.b->level) >= 3, HETAL_E_LEVEL, "DiagABT needs three levels");
+        need(outs[i].capacity >= (size_t)r.a->n_rb * c.ct_words(std::min(r.a->level, r.b->level) - 3),
+             HETAL_E_INVALID_ARG, "output capacity too small");
+        lv_a = lv_b = std::min(r.a->level, r.b->level);
+      } else {
+        need(r.a->n_cb == 1 && r.a->n_rb == r.b->n_rb, HETAL_E_SHAPE, "Abar must be one block column matching B's rows");
+        const int ls = r.a->level < r.b->level ? std::min(r.a->level - 1, r.b->level - 1)
+                                               : std::min(r.a->level - 2, r.b->level);
+        need(ls >= 2, HETAL_E_LEVEL, "DiagATB needs more levels");
+        need(outs[i].capacity >= (size_t)r.b->n_cb * c.ct_words(ls - 2), HETAL_E_INVALID_ARG,
+             "output capacity too small");
+        lv_a = r.a->level;
+        lv_b = r.b->level;
+      }
+      groups[std::make_tuple(r.op, r.c, r.a->s0, lv_a, lv_b, r.a->scale, r.b->scale)].push_back(i);
+    }
+    for (auto& kv : groups) {
+      const int op = std::get<0>(kv.first), cc = std::get<1>(kv.first), s0 = std::get<2>(kv.first);
+      const int s1 = c.slots / s0;
+      const std::vector<int>& idx = kv.second;
+      Batch res;
+      if (op == 0) {
+        std::vector<AbtRequest> rq;
+        for (int i : idx) {
+          const hetal_matmul_req& r = reqs[i];
+          std::vector<CtView> av = block_views(c, r.a);
+          AbtRequest q;
+          for (int b = 0; b < r.a->n_rb; ++b) q.A.emplace_back(av.begin() + b * r.a->n_cb, av.begin() + (b + 1) * r.a->n_cb);
+          q.Bbar = block_views(c, r.b);
+          q.t = r.t;
+          rq.push_back(std::move(q));
+        }
+        res = diag_abt_multi(c, keys->set, ctx->masks, rq, cc, s0, s1);
+      } else {
+        std::vector<AtbRequest> rq;
+        for (int i : idx) {
+          const hetal_matmul_req& r = reqs[i];
+          std::vector<CtView> bv = block_views(c, r.b);
+          AtbRequest q;
+          q.Abar = block_views(c, r.a);
+          for (int b = 0; b < r.b->n_rb; ++b) q.B.emplace_back(bv.begin() + b * r.b->n_cb, bv.begin() + (b + 1) * r.b->n_cb);
+          q.t = r.t;
+          rq.push_back(std::move(q));
+        }
+        res = diag_atb_multi(c, keys->set, ctx->masks, rq, cc, s0, s1);
+      }
+      // request i's blocks follow the earlier requests' in the result
+      int first = 0;
+      const size_t w = c.ct_words(res.level);
+      for (int i : idx) {
+        const hetal_matmul_req& r = reqs[i];
+        const int nb = op == 0 ? r.a->n_rb : r.b->n_cb;
+        hetal_mat* o = &outs[i];
+        HCHECK(hipMemcpyAsync(o->data, res.d + (size_t)first * w, (size_t)nb * w * 8, hipMemcpyDeviceToDevice, c.stream));
+        o->n_rb = op == 0 ? nb : 1;
+        o->n_cb = op == 0 ? 1 : nb;
+        o->s0 = s0;
+        o->s1 = s1;
+        o->level = res.level;
+        o->scale = res.scale;
+        first += nb;
+      }
+    }
+  });
+}
+
 int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int cc, int s0, int32_t* out, int* n) {
   return guarded([&] {
     need(ctx && n, HETAL_E_INVALID_ARG, "null argument");

@@ -135,26 +135,49 @@ std::vector<Cipher> to_ciphers(Context& c, const Batch& b) {
   return out;
 }
 
-Batch diag_abt_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,
-                     const std::vector<CtView>& Bbar, int cc, int s0, int s1, double t) {
+namespace {
+
+int common_level(std::initializer_list<const std::vector<CtView>*> parts) {
+  int lv = 1 << 30;
+  for (auto* v : parts)
+    for (auto& x : *v) lv = std::min(lv, x.level);
+  return lv;
+}
+
+}  // namespace
+
+Batch diag_abt_multi(Context& c, const KeySet& k, MaskCache& mc, const std::vector<AbtRequest>& reqs, int cc, int s0,
+                     int s1) {
   check_block_shape(c, s0, s1);
   if (cc < 2 || cc > s0 || s1 % cc || (cc & (cc - 1))) fail(HETAL_E_SHAPE, "need 1 < c <= s0, c a power of two dividing s1");
-  const int n_a = (int)A.size(), n_b = (int)Bbar.size();
-  if (n_a < 1 || n_b < 1) fail(HETAL_E_SHAPE, "empty block matrix");
-  int lv = 1 << 30;
-  for (auto& row : A) {
-    if ((int)row.size() != n_b) fail(HETAL_E_SHAPE, "A and Bbar block columns differ");
-    for (auto& x : row) lv = std::min(lv, x.level);
+  if (reqs.empty()) fail(HETAL_E_INVALID_ARG, "no requests");
+  int lv = -1;
+  for (const AbtRequest& r : reqs) {
+    const int n_a = (int)r.A.size(), n_b = (int)r.Bbar.size();
+    if (n_a < 1 || n_b < 1) fail(HETAL_E_SHAPE, "empty block matrix");
+    int l = common_level({&r.Bbar});
+    for (auto& row : r.A) {
+      if ((int)row.size() != n_b) fail(HETAL_E_SHAPE, "A and Bbar block columns differ");
+      l = std::min(l, common_level({&row}));
+    }
+    if (lv >= 0 && l != lv) fail(HETAL_E_LEVEL, "requests in one lockstep group at different levels");
+    lv = l;
   }
-  for (auto& x : Bbar) lv = std::min(lv, x.level);
   if (lv < 3) fail(HETAL_E_LEVEL, "DiagABT needs three levels");
   const int half = cc / 2;
   std::vector<Batch> hold;
-  std::vector<std::vector<CtView>> a(n_a);
-  for (int i = 0; i < n_a; ++i)
-    for (int j = 0; j < n_b; ++j) a[i].push_back(at_level(c, A[i][j], lv, hold));
+  // every request's blocks at the common level; the Bbar blocks of all requests in one batch
+  std::vector<std::vector<std::vector<CtView>>> a(reqs.size());
   std::vector<CtView> bv;
-  for (int j = 0; j < n_b; ++j) bv.push_back(at_level(c, Bbar[j], lv, hold));
+  std::vector<int> boff;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    for (auto& row : reqs[r].A) {
+      a[r].emplace_back();
+      for (auto& x : row) a[r].back().push_back(at_level(c, x, lv, hold));
+    }
+    boff.push_back((int)bv.size());
+    for (auto& x : reqs[r].Bbar) bv.push_back(at_level(c, x, lv, hold));
+  }
   Batch bp = b_pack(c, bv);
 
   // B_cplx = Bbar + i RU(Bbar, c/2)
@@ -163,65 +186,86 @@ Batch diag_abt_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vect
   Batch bc = b_add(c, bp.v(), rbi.v());
 
   // RU(B_cplx, k) for k = 1 .. c/2 - 1, hoisted per block
-  std::vector<Batch> bk(n_b);
+  std::vector<Batch> bk(bv.size());
   if (half > 1) {
     std::vector<int> steps;
     for (int kk = 1; kk < half; ++kk) steps.push_back(kk * s1);
-    for (int j = 0; j < n_b; ++j) bk[j] = b_rotate_hoisted(c, k, bc.item(j), steps);
+    for (size_t g = 0; g < bv.size(); ++g) bk[g] = b_rotate_hoisted(c, k, bc.item((int)g), steps);
   }
 
-  // products A_ij * B_kj in the order (i, k, j): sums over j are contiguous groups
+  // products A_ij * B_kj in the order (request, i, k, j): each sum over j is a contiguous run
   std::vector<CtView> pa, pb;
-  for (int i = 0; i < n_a; ++i)
-    for (int kk = 0; kk < half; ++kk)
-      for (int j = 0; j < n_b; ++j) {
-        pa.push_back(a[i][j]);
-        pb.push_back(kk == 0 ? bc.item(j) : bk[j].item(kk - 1));
-      }
-  Batch prod = b_hmult(c, k, pa, pb);
-  Batch r = b_sum_groups(c, prod.v(), n_a * half);
-  prod = Batch();
-  r = b_rescale(c, r.v());
-
-  r = col_sum(c, k, mc, std::move(r), s0, s1);
-
+  std::vector<int> runs_j, runs_k;
   std::vector<MaskSpec> masks;
-  for (int i = 0; i < n_a; ++i)
-    for (int kk = 0; kk < half; ++kk) masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, kk, cc, s0, s1, t});
-  Batch rm = b_cmult_masks(c, mc, r.v(), masks);
-  r = b_rescale(c, rm.v());
-  Batch x = b_sum_groups(c, r.v(), n_a);
-  return b_conj_add(c, k, x.v());
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const int n_b = (int)reqs[r].Bbar.size();
+    for (auto& row : a[r]) {
+      for (int kk = 0; kk < half; ++kk) {
+        for (int j = 0; j < n_b; ++j) {
+          pa.push_back(row[j]);
+          pb.push_back(kk == 0 ? bc.item(boff[r] + j) : bk[boff[r] + j].item(kk - 1));
+        }
+        runs_j.push_back(n_b);
+        masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, kk, cc, s0, s1, reqs[r].t});
+      }
+      runs_k.push_back(half);
+    }
+  }
+  Batch prod = b_hmult(c, k, pa, pb);
+  Batch x = b_sum_segments(c, prod.v(), runs_j);
+  prod = Batch();
+  x = b_rescale(c, x.v());
+
+  x = col_sum(c, k, mc, std::move(x), s0, s1);
+
+  Batch xm = b_cmult_masks(c, mc, x.v(), masks);
+  x = b_rescale(c, xm.v());
+  Batch y = b_sum_segments(c, x.v(), runs_k);
+  return b_conj_add(c, k, y.v());
 }
 
-Batch diag_atb_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<CtView>& Abar,
-                     const std::vector<std::vector<CtView>>& B, int cc, int s0, int s1, double t) {
+Batch diag_abt_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,
+                     const std::vector<CtView>& Bbar, int cc, int s0, int s1, double t) {
+  return diag_abt_multi(c, k, mc, {AbtRequest{A, Bbar, t}}, cc, s0, s1);
+}
+
+Batch diag_atb_multi(Context& c, const KeySet& k, MaskCache& mc, const std::vector<AtbRequest>& reqs, int cc, int s0,
+                     int s1) {
   check_block_shape(c, s0, s1);
   if (cc < 2 || cc > s1 || s1 % cc || (cc & (cc - 1))) fail(HETAL_E_SHAPE, "need 1 < c, c a power of two dividing s1");
-  const int n_a = (int)Abar.size();
-  if (n_a < 1 || (int)B.size() != n_a || B[0].empty()) fail(HETAL_E_SHAPE, "Abar and B block rows differ");
-  const int n_b = (int)B[0].size();
-  int lA = 1 << 30, lB = 1 << 30;
-  for (auto& x : Abar) lA = std::min(lA, x.level);
-  for (auto& row : B) {
-    if ((int)row.size() != n_b) fail(HETAL_E_SHAPE, "ragged B");
-    for (auto& x : row) lB = std::min(lB, x.level);
+  if (reqs.empty()) fail(HETAL_E_INVALID_ARG, "no requests");
+  int lA = -1, lB = -1;
+  for (const AtbRequest& r : reqs) {
+    const int n_a = (int)r.Abar.size();
+    if (n_a < 1 || (int)r.B.size() != n_a || r.B[0].empty()) fail(HETAL_E_SHAPE, "Abar and B block rows differ");
+    const int n_b = (int)r.B[0].size();
+    const int la = common_level({&r.Abar});
+    int lb = 1 << 30;
+    for (auto& row : r.B) {
+      if ((int)row.size() != n_b) fail(HETAL_E_SHAPE, "ragged B");
+      lb = std::min(lb, common_level({&row}));
+    }
+    if (lA >= 0 && (la != lA || lb != lB)) fail(HETAL_E_LEVEL, "requests in one lockstep group at different levels");
+    lA = la;
+    lB = lb;
   }
   const bool use_pru = lA < lB;
   const int lstar = use_pru ? std::min(lA - 1, lB - 1) : std::min(lA - 2, lB);
   if (lstar < 2) fail(HETAL_E_LEVEL, "DiagATB needs more levels");
   const int half = cc / 2;
   std::vector<Batch> hold;
+  // the Abar blocks of all requests in one batch
   std::vector<CtView> av;
-  for (int i = 0; i < n_a; ++i) av.push_back(at_level(c, Abar[i], lA, hold));
+  std::vector<int> aoff;
+  for (const AtbRequest& r : reqs) {
+    aoff.push_back((int)av.size());
+    for (auto& x : r.Abar) av.push_back(at_level(c, x, lA, hold));
+  }
   Batch ap = b_pack(c, av);
-  std::vector<std::vector<CtView>> bview(n_a);
-  for (int i = 0; i < n_a; ++i)
-    for (int j = 0; j < n_b; ++j) bview[i].push_back(at_level(c, B[i][j], lB, hold));
 
   // A_cplx = Abar + i RL(Abar, c/2)
   Batch a1 = b_rotate(c, k, ap.v(), {half});
-  Batch rl = rot_left_finish(c, k, mc, a1, std::vector<int>(n_a, half), s0, s1);
+  Batch rl = rot_left_finish(c, k, mc, a1, std::vector<int>(av.size(), half), s0, s1);
   Batch apd = b_mod_drop(c, ap.v(), rl.level);
   Batch rli = b_mul_i(c, rl.v());
   Batch ac = b_add(c, apd.v(), rli.v());
@@ -232,55 +276,74 @@ Batch diag_atb_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vect
     ks.push_back(kk);
     steps.push_back(kk);
   }
-  // A_k[i][kk] and B_k[i][j][kk] at lstar
-  std::vector<std::vector<CtView>> ak(n_a, std::vector<CtView>(half));
-  std::vector<std::vector<std::vector<CtView>>> bk(n_a, std::vector<std::vector<CtView>>(n_b, std::vector<CtView>(half)));
-  for (int i = 0; i < n_a; ++i) {
-    ak[i][0] = at_level(c, ac.item(i), lstar, hold);
-    if (half > 1) {
-      Batch rk = b_rotate_hoisted(c, k, ac.item(i), steps);
-      if (!use_pru) rk = rot_left_finish(c, k, mc, rk, ks, s0, s1);
-      hold.push_back(rk.level == lstar ? std::move(rk) : b_mod_drop(c, rk.v(), lstar));
-      for (int kk = 1; kk < half; ++kk) ak[i][kk] = hold.back().item(kk - 1);
-    }
-    for (int j = 0; j < n_b; ++j) {
-      CtView bd = at_level(c, bview[i][j], lstar, hold);
-      bk[i][j][0] = bd;
+  // per request: A_k[i][kk] and B_k[i][j][kk] at lstar
+  std::vector<std::vector<std::vector<CtView>>> ak(reqs.size());
+  std::vector<std::vector<std::vector<std::vector<CtView>>>> bk(reqs.size());
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const int n_a = (int)reqs[r].Abar.size(), n_b = (int)reqs[r].B[0].size();
+    ak[r].assign(n_a, std::vector<CtView>(half));
+    bk[r].assign(n_a, std::vector<std::vector<CtView>>(n_b, std::vector<CtView>(half)));
+    for (int i = 0; i < n_a; ++i) {
+      const CtView aci = ac.item(aoff[r] + i);
+      ak[r][i][0] = at_level(c, aci, lstar, hold);
       if (half > 1) {
-        if (use_pru) {
-          Batch pr = partial_rot_up(c, k, mc, bview[i][j], ks, s0, s1);
-          hold.push_back(pr.level == lstar ? std::move(pr) : b_mod_drop(c, pr.v(), lstar));
-          for (int kk = 1; kk < half; ++kk) bk[i][j][kk] = hold.back().item(kk - 1);
-        } else {
-          for (int kk = 1; kk < half; ++kk) bk[i][j][kk] = bd;
+        Batch rk = b_rotate_hoisted(c, k, aci, steps);
+        if (!use_pru) rk = rot_left_finish(c, k, mc, rk, ks, s0, s1);
+        hold.push_back(rk.level == lstar ? std::move(rk) : b_mod_drop(c, rk.v(), lstar));
+        for (int kk = 1; kk < half; ++kk) ak[r][i][kk] = hold.back().item(kk - 1);
+      }
+      for (int j = 0; j < n_b; ++j) {
+        const CtView bij = at_level(c, reqs[r].B[i][j], lB, hold);
+        const CtView bd = at_level(c, bij, lstar, hold);
+        bk[r][i][j][0] = bd;
+        if (half > 1) {
+          if (use_pru) {
+            Batch pr = partial_rot_up(c, k, mc, bij, ks, s0, s1);
+            hold.push_back(pr.level == lstar ? std::move(pr) : b_mod_drop(c, pr.v(), lstar));
+            for (int kk = 1; kk < half; ++kk) bk[r][i][j][kk] = hold.back().item(kk - 1);
+          } else {
+            for (int kk = 1; kk < half; ++kk) bk[r][i][j][kk] = bd;
+          }
         }
       }
     }
   }
 
-  // products in the order (j, k, i): sums over i are contiguous groups
+  // products in the order (request, j, k, i): each sum over i is a contiguous run
   std::vector<CtView> pa, pb;
-  for (int j = 0; j < n_b; ++j)
-    for (int kk = 0; kk < half; ++kk)
-      for (int i = 0; i < n_a; ++i) {
-        pa.push_back(ak[i][kk]);
-        pb.push_back(bk[i][j][kk]);
+  std::vector<int> runs_i, runs_k;
+  std::vector<MaskSpec> masks;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const int n_a = (int)reqs[r].Abar.size(), n_b = (int)reqs[r].B[0].size();
+    for (int j = 0; j < n_b; ++j) {
+      for (int kk = 0; kk < half; ++kk) {
+        for (int i = 0; i < n_a; ++i) {
+          pa.push_back(ak[r][i][kk]);
+          pb.push_back(bk[r][i][j][kk]);
+        }
+        runs_i.push_back(n_a);
+        masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, -kk, cc, s0, s1, reqs[r].t});
       }
+      runs_k.push_back(half);
+    }
+  }
   Batch prod = b_hmult(c, k, pa, pb);
-  Batch r = b_sum_groups(c, prod.v(), n_b * half);
+  Batch x = b_sum_segments(c, prod.v(), runs_i);
   prod = Batch();
   hold.clear();
-  r = b_rescale(c, r.v());
+  x = b_rescale(c, x.v());
 
-  r = row_sum(c, k, std::move(r), s0, s1);
+  x = row_sum(c, k, std::move(x), s0, s1);
 
-  std::vector<MaskSpec> masks;
-  for (int j = 0; j < n_b; ++j)
-    for (int kk = 0; kk < half; ++kk) masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, -kk, cc, s0, s1, t});
-  Batch rm = b_cmult_masks(c, mc, r.v(), masks);
-  r = b_rescale(c, rm.v());
-  Batch x = b_sum_groups(c, r.v(), n_b);
-  return b_conj_add(c, k, x.v());
+  Batch xm = b_cmult_masks(c, mc, x.v(), masks);
+  x = b_rescale(c, xm.v());
+  Batch y = b_sum_segments(c, x.v(), runs_k);
+  return b_conj_add(c, k, y.v());
+}
+
+Batch diag_atb_batch(Context& c, const KeySet& k, MaskCache& mc, const std::vector<CtView>& Abar,
+                     const std::vector<std::vector<CtView>>& B, int cc, int s0, int s1, double t) {
+  return diag_atb_multi(c, k, mc, {AtbRequest{Abar, B, t}}, cc, s0, s1);
 }
 
 std::vector<Cipher> diag_abt(Context& c, const KeySet& k, MaskCache& mc, const std::vector<std::vector<CtView>>& A,

@@ -173,5 +173,7 @@ Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const s
 Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks);
 // out[g] = sum over t < per of a[g * per + t], per = a.count / groups.
 Batch b_sum_groups(Context& c, BView a, int groups);
+// out[g] = sum of the g-th run of sizes[g] consecutive items (the runs cover the batch in order).
+Batch b_sum_segments(Context& c, BView a, const std::vector<int>& sizes);
 
 }  // namespace hetal

@@ -49,6 +49,11 @@ class _Mat(ctypes.Structure):
                 ("scale", ctypes.c_double)]
 
 
+class _Req(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("a", ctypes.POINTER(_Mat)), ("b", ctypes.POINTER(_Mat)), ("c", ctypes.c_int),
+                ("t", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -96,6 +101,7 @@ _SIGS = {
     "hetal_mat_decrypt": (ctypes.c_int, [_vp, _vp, _matp, _dblp]),
     "hetal_enc_matmul_abt": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
     "hetal_enc_matmul_atb": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
+    "hetal_enc_matmul_batch": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp]),
     "hetal_required_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
     "hetal_counters_get": (ctypes.c_int, [_vp, _i64p]),
     "hetal_counters_reset": (ctypes.c_int, [_vp]),
@@ -429,6 +435,30 @@ class Context:
                                          int(c), float(t), ctypes.byref(s)))
         out._update(s)
         return out
+
+    def enc_matmul_batch(self, keys, reqs):
+        """[(op, a, b, c, t), ...] with op "abt" or "atb" -> the list of results, each exactly what
+        enc_matmul_abt / enc_matmul_atb returns for it; requests sharing (op, c, s0, levels, scales) run in lockstep."""
+        n = len(reqs)
+        mats, outs = [], []
+        arr = (_Req * max(n, 1))()
+        for i, (op, a, b, c, t) in enumerate(reqs):
+            if op not in ("abt", "atb"):
+                raise ValueError("op must be 'abt' or 'atb'")
+            sa, sb = a._struct(), b._struct()
+            mats += [sa, sb]
+            if op == "abt":
+                lv = min(a.level, b.level) - 3
+                out = Matrix(self, a.n_rb * self.ct_words(lv) if lv >= 0 else 1, a.s0, 0, 0.0)
+            else:
+                out = Matrix(self, b.n_cb * self.ct_words(max(a.level, b.level)), b.s0, 0, 0.0)
+            outs.append(out)
+            arr[i] = _Req(0 if op == "abt" else 1, ctypes.pointer(sa), ctypes.pointer(sb), int(c), float(t))
+        structs = (_Mat * max(n, 1))(*[o._struct() for o in outs])
+        _check(_lib.hetal_enc_matmul_batch(self._h, keys._h, arr, n, structs))
+        for o, s in zip(outs, structs):
+            o._update(s)
+        return outs
 
     def enc_matmul_atb(self, keys, abar, b, c, t=1.0):
         lvl = max(abar.level, b.level)
