@@ -343,6 +343,87 @@ def paper_shapes(reps):
         torch.cuda.empty_cache()
 
 
+def uneven_requests(seed, count, per_shape):
+    """`count` seeded products of uneven shapes: rows 32..512, inner dimension 64..1024, classes 2..16, half DiagABT
+    (forward) and half DiagATB (gradient).  Standard encoding: s0 = 128 and c = 16 for all; per-shape encoding:
+    s0 = the next power of two >= rows, c = the next power of two >= classes."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        rows = int(rng.integers(32, 513))
+        inner = int(rng.integers(64, 1025))
+        classes = int(rng.integers(2, 17))
+        if per_shape:
+            s0 = 1 << max(5, (rows - 1).bit_length())
+            c = 1 << max(1, (classes - 1).bit_length())
+        else:
+            s0, c = S0, C_PAD
+        reqs.append(dict(op="abt" if i % 2 == 0 else "atb", rows=rows, inner=inner, classes=classes, s0=s0, c=c))
+    return reqs
+
+
+def uneven(count, per_shape):
+    """Many uneven products: one batched call against the same products issued one by one (one JSON line)."""
+    import torch
+    from paper_2403_14111_amd import hetal, inputs
+    ctx = hetal.Context("n16l12")
+    sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
+    spec = uneven_requests(SEEDS["data"] + 7, count, per_shape)
+    steps = set()
+    for r in spec:
+        steps |= set(ctx.required_rot_steps(0 if r["op"] == "abt" else 1, r["c"], r["s0"]))
+    log("%d requests, %d rotation keys" % (len(spec), len(steps)))
+    keys = ctx.keys_create()
+    ra, re_ = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
+    keys.gen_relin(sk, ra, re_)
+    for g in sorted(set(ctx.galois_rot(r) for r in steps) | {ctx.galois_conj()}):
+        ra, re_ = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(1, g), ctx.dnum, ctx.primes, ctx.n)
+        keys.gen_galois(sk, g, ra, re_)
+    reqs = []
+    first = 0
+    for n, r in enumerate(spec):
+        def enc(mat, tiling):
+            nonlocal first
+            nb = int(np.prod(ctx.mat_blocks(mat.shape[0], mat.shape[1], r["s0"], tiling, r["c"])))
+            ea, ee = enc_randomness(ctx, nb, LEVEL, first)
+            first += nb
+            return ctx.mat_encrypt(sk, mat, r["s0"], LEVEL, 2.0 ** 40, ea, ee, tiling=tiling, c=r["c"])
+        X = inputs.features(SEEDS["data"] + 100 + n, r["rows"], r["inner"])
+        if r["op"] == "abt":
+            W = inputs.weights(SEEDS["data"] + 100 + n, r["classes"], r["inner"])
+            reqs.append(("abt", enc(X, 0), enc(W, 1), r["c"], 1.0))
+        else:
+            PY = inputs.toy_matrix(SEEDS["data"] + 100 + n, r["rows"], r["classes"], 0) * 0.1
+            reqs.append(("atb", enc(PY, 2), enc(X, 0), r["c"], 1.0))
+    groups = len(set((r[0], r[3], r[1].s0) for r in reqs))
+
+    def one_by_one():
+        return [ctx.enc_matmul_abt(keys, a, b, c, t) if op == "abt" else ctx.enc_matmul_atb(keys, a, b, c, t)
+                for op, a, b, c, t in reqs]
+
+    one_by_one()
+    ctx.enc_matmul_batch(keys, reqs)  # warm-up: masks encoded and cached
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = one_by_one()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bat = ctx.enc_matmul_batch(keys, reqs)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    same = all(x.level == y.level and x.n_rb == y.n_rb and x.n_cb == y.n_cb and
+               torch.equal(x.buf[:x.n_rb * x.n_cb * ctx.ct_words(x.level)],
+                           y.buf[:y.n_rb * y.n_cb * ctx.ct_words(y.level)]) for x, y in zip(seq, bat))
+    print(json.dumps({"uneven_matmuls": count, "encoding": "per-shape s0, c" if per_shape else "s0=128, c=16",
+                      "lockstep_groups": groups, "one_by_one_s": round(t_seq, 4), "batched_s": round(t_bat, 4),
+                      "one_by_one_matmuls_per_s": round(count / t_seq, 2),
+                      "batched_matmuls_per_s": round(count / t_bat, 2), "speedup": round(t_seq / t_bat, 3),
+                      "bitexact_batched_vs_one_by_one": bool(same),
+                      "shapes": [[r["op"], r["rows"], r["inner"], r["classes"], r["s0"], r["c"]] for r in spec]}),
+          flush=True)
+
+
 def cpu_baseline(X, W, gpu_abt_coeffs):
     """The oracle (never tuned) on one full DiagABT of the same workload."""
     from oracle import ckks
@@ -397,6 +478,9 @@ def main():
                          "WRITE_SIZE/) as markdown; --steps is the trace run's step count, --pmc-steps the counter "
                          "runs' one")
     ap.add_argument("--pmc-steps", type=int, default=2)
+    ap.add_argument("--uneven", type=int, default=0, metavar="COUNT",
+                    help="instead of the benchmark: COUNT seeded uneven products, one batched call against one by "
+                         "one, with the standard and the per-shape encodings (one JSON line each)")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the benchmark: DiagABT / DiagATB (both branches) at the paper's Table 4 shapes, "
                          "one JSON line per shape (median of --steps calls)")
@@ -416,6 +500,10 @@ def main():
     torch.cuda.set_device(0)
     if args.paper_shapes:
         paper_shapes(args.steps)
+        return
+    if args.uneven:
+        uneven(args.uneven, False)
+        uneven(args.uneven, True)
         return
     log("context + keys")
     ctx = hetal.Context("n16l12")
