@@ -100,16 +100,25 @@ PROFILE_CLASSES = [
 PROFILE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "kernels_n16l12_matmul_step.md")
 
 
-def kernel_sources_digest():
-    """sha256 over the HIP sources: a recorded counter profile is only valid for the sources it was taken on."""
+# the sources each profiled kernel class is built from
+KERNEL_SOURCES = {"ntt": ("ntt.hip", "modarith.hpp", "hetal_internal.hpp"),
+                  "rns": ("rns_kernels.hip", "modarith.hpp", "hetal_internal.hpp")}
+
+
+def kernel_sources_digest(cls=None):
+    """sha256 over the HIP sources of a kernel class (all of them for None): a recorded counter profile is only
+    valid for the sources it was taken on."""
     import hashlib
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2403_14111_amd", "csrc")
+    if cls is None:
+        files = sorted(f for f in os.listdir(d) if f.endswith((".hip", ".hpp")))
+    else:
+        files = KERNEL_SOURCES["ntt" if cls.startswith("ntt_") else "rns"]
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -242,7 +251,7 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
               "traffic_json: " + json.dumps({"bytes_per_launch": {k: round(v) for k, v in per_launch.items()},
                                              "avg_us": {k: round(a[1] / a[0] / 1e3, 2) for k, a in agg.items()
                                                         if k in dict(PROFILE_CLASSES).values()},
-                                             "sources_sha256": kernel_sources_digest()})]
+                                             "sources_sha256": {k: kernel_sources_digest(k) for k in per_launch}})]
     return "\n".join(lines)
 
 
@@ -253,7 +262,8 @@ def recorded_traffic(cls):
             for line in fh:
                 if line.startswith("traffic_json: "):
                     rec = json.loads(line[len("traffic_json: "):])
-                    if rec.get("sources_sha256") == kernel_sources_digest():
+                    digests = rec.get("sources_sha256")
+                    if isinstance(digests, dict) and digests.get(cls) == kernel_sources_digest(cls):
                         return rec["bytes_per_launch"].get(cls)
     except OSError:
         pass
