@@ -434,6 +434,64 @@ def uneven(count, per_shape):
           flush=True)
 
 
+def serve_bench(clients, count, rate, budget_gib):
+    """The request loop under Poisson arrivals: `clients` clients, each with its own keys and data (the 128x768x10
+    forward and gradient products of the benchmark, in the standard encoding), alternating DiagABT and DiagATB
+    requests; p50 / p99 latency beside throughput (one JSON line)."""
+    import torch
+    from paper_2403_14111_amd import hetal, inputs, serving
+    ctx = hetal.Context("n16l12")
+    server = serving.Server(ctx, int(budget_gib * 2 ** 30), sync=torch.cuda.synchronize)
+    data = {}
+    for cl in range(clients):
+        log("client %d: keys and data" % cl)
+        sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"] + 1 + cl, ctx.n))
+        keys = ctx.keys_create()
+        ra, re_ = inputs.switch_key_randomness(SEEDS["keys"] + 1 + cl, inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
+        keys.gen_relin(sk, ra, re_)
+        for g in sorted(set(ctx.galois_rot(r) for r in key_steps(ctx)) | {ctx.galois_conj()}):
+            ra, re_ = inputs.switch_key_randomness(SEEDS["keys"] + 1 + cl, inputs.key_id(1, g), ctx.dnum, ctx.primes,
+                                                   ctx.n)
+            keys.gen_galois(sk, g, ra, re_)
+        X = inputs.features(SEEDS["data"] + 200 + cl, A_ROWS, FEAT)
+        W = inputs.weights(SEEDS["data"] + 200 + cl, CLASSES, FEAT)
+        lab = inputs.labels(SEEDS["data"] + 200 + cl, A_ROWS, CLASSES)
+        PY = inputs.softmax_minus_onehot(X @ W.T, lab, CLASSES)
+        data[cl] = encrypt_inputs(ctx, sk, X, W, PY)
+        server.add_client(cl, keys)
+    rng = np.random.default_rng(SEEDS["data"] + 300)
+    arrivals = serving.poisson_arrivals(rng, rate, count)
+    who = rng.integers(0, clients, size=count)
+    reqs = []
+    for i, (t, cl) in enumerate(zip(arrivals, who)):
+        gx, gw, gpy = data[int(cl)]
+        if i % 2 == 0:
+            reqs.append(serving.Request(i, int(cl), "abt", gx, gw, C_PAD, 1.0, t))
+        else:
+            reqs.append(serving.Request(i, int(cl), "atb", gpy, gx, C_PAD, 1.0, t))
+    # warm-up: one request of each kind per client (masks encoded and cached, pool buffers sized)
+    for cl in range(clients):
+        gx, gw, gpy = data[cl]
+        ctx.enc_matmul_batch(server.keys[cl], [("abt", gx, gw, C_PAD, 1.0), ("atb", gpy, gx, C_PAD, 1.0)])
+    torch.cuda.synchronize()
+    log("serving %d requests at %.1f/s from %d clients" % (count, rate, clients))
+    finished = serving.serve(server, reqs)
+    summary = serving.latency_summary(finished, rate)
+    sizes = [n for _, n, _ in server.rounds]
+    # a sample of served results against the same products computed alone
+    same = True
+    for r in finished[:: max(1, len(finished) // 8)]:
+        gx, gw, gpy = data[r.client]
+        alone = ctx.enc_matmul_batch(server.keys[r.client], [(r.op, r.a, r.b, r.c, r.t)])[0]
+        w = alone.n_rb * alone.n_cb * ctx.ct_words(alone.level)
+        same = same and r.result.level == alone.level and torch.equal(r.result.buf[:w], alone.buf[:w])
+    summary.update(clients=clients, rounds=len(sizes), mean_requests_per_round=round(float(np.mean(sizes)), 2),
+                   max_requests_per_round=int(max(sizes)), memory_budget_gib=budget_gib,
+                   bitexact_sampled_vs_alone=bool(same), workload="alternating DiagABT / DiagATB 128x768x10 "
+                   "(c=16, s0=128, level 11), per-client keys resident")
+    print(json.dumps({"serving": summary}), flush=True)
+
+
 def cpu_baseline(X, W, gpu_abt_coeffs):
     """The oracle (never tuned) on one full DiagABT of the same workload."""
     from oracle import ckks
@@ -491,6 +549,12 @@ def main():
     ap.add_argument("--uneven", type=int, default=0, metavar="COUNT",
                     help="instead of the benchmark: COUNT seeded uneven products, one batched call against one by "
                          "one, with the standard and the per-shape encodings (one JSON line each)")
+    ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
+                    help="instead of the benchmark: serve COUNT requests arriving as a Poisson process "
+                         "(--rate per second, --clients clients, --budget-gib admission budget); one JSON line")
+    ap.add_argument("--rate", type=float, default=60.0)
+    ap.add_argument("--clients", type=int, default=4)
+    ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the benchmark: DiagABT / DiagATB (both branches) at the paper's Table 4 shapes, "
                          "one JSON line per shape (median of --steps calls)")
@@ -514,6 +578,9 @@ def main():
     if args.uneven:
         uneven(args.uneven, False)
         uneven(args.uneven, True)
+        return
+    if args.serve:
+        serve_bench(args.clients, args.serve, args.rate, args.budget_gib)
         return
     log("context + keys")
     ctx = hetal.Context("n16l12")
