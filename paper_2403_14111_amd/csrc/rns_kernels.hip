@@ -1,8 +1,17 @@
-// RNS kernels for gfx950: hybrid key switching (ModUp, the key inner product
-// with the Galois automorphism fused into its loads, ModDown), rescale, and
-// the elementwise operations.  All of these stream limbs through HBM once;
-// each thread handles one coefficient index, so consecutive lanes touch
-// consecutive words of a limb.
+// RNS kernels for gfx950 and the key-switch and rescale schedules built on them.
+//
+// A hybrid key switch (Sec. 2.2) runs as: the inverse NTT of the input's c1,
+// its last stage also applying the ModUp conversion's first factor; the
+// forward NTT of the ModUp rows, its first pass computing the conversion; the
+// key inner product, with the Galois automorphism fused into its loads; the
+// inverse NTT of the special rows, scaled for ModDown's conversion; and the
+// forward NTT of the ModDown rows, with the conversion in its first pass and
+// the combine (acc - conv) P^-1 + addends in its last (see ntt.hip).  The
+// standalone ModUp / ModDown conversion kernels here serve parameter sets the
+// fused passes do not cover (more than 4 terms, or other ring sizes).
+//
+// The kernels stream limbs through HBM once; each thread handles one
+// coefficient index, so consecutive lanes touch consecutive words of a limb.
 #include "hetal_internal.hpp"
 
 namespace hetal {
