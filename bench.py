@@ -130,15 +130,22 @@ def profile_class(name):
 
 
 def timed_window(names, steps):
-    """Indices of the last `steps` repetitions of the step's kernel sequence (the timed region)."""
-    # The largest period whose `steps` copies end the trace: shorter accidental periods (a step ending in two
-    # equal kernels) are passed over, and multiples of the true period would need more identical steps than ran.
+    """Indices of the last `steps` repetitions of the step's kernel sequence (the timed region).  The step length
+    is the period p whose p-periodic suffix of the trace is longest (ties to the smaller p): multiples of the true
+    period cover no more, and accidental short periods (a step ending in two equal kernels) cover less."""
     n = len(names)
-    for p in range(n // steps, 0, -1):
-        lo = n - steps * p
-        if all(names[i] == names[i + p] for i in range(n - p - 1, lo - 1, -1)):
-            return lo, n, p
-    raise SystemExit("no %d-fold repeated step found in the trace" % steps)
+    best = None
+    for p in range(1, n // steps + 1):
+        m = 0
+        while m < n - p and names[n - 1 - m] == names[n - 1 - m - p]:
+            m += 1
+        span = m + p  # length of the longest p-periodic suffix
+        if span >= steps * p and (best is None or span > best[0]):
+            best = (span, p)
+    if best is None:
+        raise SystemExit("no %d-fold repeated step found in the trace" % steps)
+    p = best[1]
+    return n - steps * p, n, p
 
 
 def read_dispatches(path, counter=None):
