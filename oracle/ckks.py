@@ -120,6 +120,8 @@ PRESETS = {
     "toy": dict(log_n=12, num_q=5, num_p=1, dnum=5),
     # 2^16 ring, q_0 (50-bit) + 11 x 40-bit, three special primes, dnum = 4.
     "n16l12": dict(log_n=16, num_q=12, num_p=3, dnum=4),
+    # 2^12 ring with the 2^16 ring's moduli chain shape (deep pipelines at test sizes).
+    "n12l12": dict(log_n=12, num_q=12, num_p=3, dnum=4),
 }
 
 
@@ -356,6 +358,22 @@ def decrypt(prm, sk, ct):
     return Pt(m, ct.scale)
 
 
+def refresh(prm, sk, ct, a_rand, e_rand):
+    """A fresh encryption at the top level of the message of `ct`, made by the key holder:
+    decrypt, lift the plaintext polynomial from q_0 (centred; every other limb must agree,
+    i.e. |m| < q_0 / 2), re-encrypt with the given randomness (a_rand over all ciphertext
+    primes).  The scale is kept.  This stands in for bootstrapping, which this library does
+    not provide: the server hands the ciphertext back to the client."""
+    pt = decrypt(prm, sk, ct)
+    q0 = prm.q[0]
+    m0 = pt.m[0].astype(np.int64)
+    m0 = np.where(pt.m[0] > q0 // 2, m0 - np.int64(q0), m0)
+    for i in range(1, pt.level + 1):
+        if not np.array_equal(reduce_signed(m0, [prm.q[i]], prm.log_n)[0], pt.m[i]):
+            raise OverflowError("message too large to lift from q_0")
+    return encrypt(prm, sk, Pt(reduce_signed(m0, prm.q, prm.log_n), ct.scale), a_rand, e_rand)
+
+
 # --------------------------------------------------------------------------
 # Key switching
 # --------------------------------------------------------------------------
@@ -488,6 +506,39 @@ class Evaluator:
         qs = self.prm.q[:a.level + 1]
         lg = self.prm.log_n
         return Ct(np.stack([polymul(a.c[0], pt.m, qs, lg), polymul(a.c[1], pt.m, qs, lg)]), a.scale * pt.scale)
+
+    # -- constants (App. softmax evaluates real polynomials on ciphertexts) --
+    def cmult_const(self, a, value, sigma):
+        """Multiply by the real constant `value` encoded at scale `sigma`: the integer
+        K = round(value * sigma) (ties to even) times both polynomials; the scale
+        becomes scale * sigma.  No level is consumed (a rescale usually follows)."""
+        k = round(float(value) * float(sigma))
+        if abs(k) >= 1 << 62:
+            raise OverflowError("constant does not fit in 62 bits")
+        self._count("cmult_const")
+        qs = self.prm.q[:a.level + 1]
+        ks = [k % q for q in qs]
+        lg = self.prm.log_n
+        return Ct(np.stack([mul_scalar(a.c[0], ks, qs, lg), mul_scalar(a.c[1], ks, qs, lg)]),
+                  a.scale * float(sigma))
+
+    def add_const(self, a, value):
+        """Add the real constant `value` to every slot: K = round(value * scale) is added to
+        the constant coefficient of c0 (a constant polynomial decodes to K / scale in
+        every slot)."""
+        k = round(float(value) * a.scale)
+        if abs(k) >= 1 << 62:
+            raise OverflowError("constant does not fit in 62 bits")
+        out = a.copy()
+        for i, q in enumerate(self.prm.q[:a.level + 1]):
+            out.c[0, i, 0] = np.uint64((int(out.c[0, i, 0]) + k) % q)
+        return out
+
+    def add_plain(self, a, values):
+        """Add slot values encoded at the ciphertext's level and scale to c0."""
+        pt = encode(self.prm, values, a.level, a.scale)
+        qs = self.prm.q[:a.level + 1]
+        return Ct(np.stack([add(a.c[0], pt.m, qs), a.c[1].copy()]), a.scale)
 
     def mask_plaintext(self, values, level):
         """A mask (slot values) encoded at `level` with scale q_level, so that

@@ -27,7 +27,8 @@ import numpy as np
 SIGMA = 3.2
 ERROR_BOUND = 19
 
-_PURPOSES = ("secret", "ksk_a", "ksk_e", "enc_a", "enc_e", "features", "weights", "labels", "toy", "slots")
+_PURPOSES = ("secret", "ksk_a", "ksk_e", "enc_a", "enc_e", "features", "weights", "labels", "toy", "slots", "logits",
+             "refresh_a", "refresh_e")
 
 
 def _rng(seed, purpose, *index):
@@ -79,6 +80,16 @@ def switch_key_randomness(seed, kid, dnum, all_moduli, n):
 def encryption_randomness(seed, index, moduli, n):
     """(a, e) of one encryption at the level given by `moduli`: a uint64 [l, n], e int64 [n]."""
     return uniform_mod(_rng(seed, "enc_a", index), moduli, n), gaussian_error(_rng(seed, "enc_e", index), n)
+
+
+def refresh_randomness(seed, index, moduli, n):
+    """(a, e) of the index-th re-encryption by the key holder (a over every ciphertext prime)."""
+    return uniform_mod(_rng(seed, "refresh_a", index), moduli, n), gaussian_error(_rng(seed, "refresh_e", index), n)
+
+
+def logits(seed, rows, cols, bound):
+    """Softmax inputs: uniform in [-bound, bound] (the sampling of the softmax error table)."""
+    return _rng(seed, "logits", rows, cols).uniform(-bound, bound, size=(rows, cols))
 
 
 def features(seed, rows, cols):
