@@ -499,6 +499,70 @@ def serve_bench(clients, count, rate, budget_gib):
     print(json.dumps({"serving": summary}), flush=True)
 
 
+def softmax_bench(reps):
+    """ASoftmax (App. softmax, Alg. "Row-wise softmax approximation") at the forward product's shape: the
+    128 x 10 logits, classes padded to c' = 16 and tiled horizontally (s0 = 128), input at level 8 (DiagABT's
+    output level), N = 2^16.  The pipeline needs ~100 levels; the key holder refreshes (decrypt and re-encrypt,
+    standing in for the paper's bootstrapping), timed apart from the server's work.  Two inputs: the workload's
+    own logits X W^T, and logits uniform in [-64, 64] (the extended domain).  One JSON line."""
+    import torch
+    from paper_2403_14111_amd import hetal, inputs
+    ctx = hetal.Context("n16l12")
+    sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
+    keys = ctx.keys_create()
+    a, e = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
+    keys.gen_relin(sk, a, e)
+    for g in sorted(set(ctx.galois_rot(r) for r in ctx.softmax_rot_steps(CLASSES, S0))):
+        a, e = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(1, g), ctx.dnum, ctx.primes, ctx.n)
+        keys.gen_galois(sk, g, a, e)
+    X, W, _ = workload()
+    cases = {"workload_logits": X @ W.T, "uniform_64": inputs.logits(SEEDS["data"] + 400, A_ROWS, CLASSES, 64.0)}
+    out = {}
+    for name, M in cases.items():
+        ea, ee = enc_randomness(ctx, 1, 8, 5000)
+        gm = ctx.mat_encrypt(sk, M, S0, 8, 2.0 ** 40, ea, ee, tiling=2, c=C_PAD)
+        spent = [0.0]
+        counter = [0]
+
+        def randomness(i):
+            return inputs.refresh_randomness(SEEDS["enc"] + 77, counter[0] + i, ctx.q, ctx.n)
+        base = ctx.refresher(sk, randomness)
+
+        def timed(user, ct_ptr):
+            t0 = time.perf_counter()
+            rc = base(user, ct_ptr)
+            torch.cuda.synchronize()
+            spent[0] += time.perf_counter() - t0
+            return rc
+        fn = hetal.REFRESH_FN(timed)
+        res, nref = ctx.softmax_approx(keys, gm, CLASSES, refresh=fn)   # warm-up: masks encoded and cached
+        totals, clients = [], []
+        ctx.reset_counters()
+        for _ in range(reps):
+            spent[0] = 0.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, nref = ctx.softmax_approx(keys, gm, CLASSES, refresh=fn)
+            torch.cuda.synchronize()
+            totals.append(time.perf_counter() - t0)
+            clients.append(spent[0])
+        cnt = ctx.counters()
+        dec = ctx.mat_decrypt(sk, res)[:A_ROWS, :CLASSES]
+        ex = np.exp(M - M.max(axis=1, keepdims=True))
+        ex /= ex.sum(axis=1, keepdims=True)
+        server = [t - c for t, c in zip(totals, clients)]
+        out[name] = {"ms_per_softmax": round(1e3 * float(np.median(totals)), 2),
+                     "server_ms": round(1e3 * float(np.median(server)), 2),
+                     "key_holder_refresh_ms": round(1e3 * float(np.median(clients)), 2),
+                     "refreshes": nref, "input_range": [round(float(M.min()), 3), round(float(M.max()), 3)],
+                     "max_abs_err_vs_softmax": float(np.abs(dec - ex).max()),
+                     "mean_abs_err_vs_softmax": float(np.abs(dec - ex).mean()),
+                     "per_call": {k: v // reps for k, v in cnt.items() if k in ("rot", "mult", "rescale", "keyswitch")}}
+        log("%s: %s" % (name, out[name]))
+    print(json.dumps({"softmax_approx": out, "shape": "128 x 10 -> c'=16, s0=128, s1=256, level 8, N=2^16",
+                      "reps": reps}), flush=True)
+
+
 def cpu_baseline(X, W, gpu_abt_coeffs):
     """The oracle (never tuned) on one full DiagABT of the same workload."""
     from oracle import ckks
@@ -562,6 +626,8 @@ def main():
     ap.add_argument("--rate", type=float, default=60.0)
     ap.add_argument("--clients", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--softmax", type=int, default=0, metavar="REPS",
+                    help="time the softmax approximation (App. softmax) at the forward product's shape, REPS runs")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the benchmark: DiagABT / DiagATB (both branches) at the paper's Table 4 shapes, "
                          "one JSON line per shape (median of --steps calls)")
@@ -585,6 +651,9 @@ def main():
     if args.uneven:
         uneven(args.uneven, False)
         uneven(args.uneven, True)
+        return
+    if args.softmax:
+        softmax_bench(args.softmax)
         return
     if args.serve:
         serve_bench(args.clients, args.serve, args.rate, args.budget_gib)

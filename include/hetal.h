@@ -247,6 +247,72 @@ int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_m
  * (PRotUp branch).  *n: in, capacity of out; out, count written. */
 int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int c, int s0, int32_t* out, int* n);
 
+/* ---- Constants and the softmax approximation (App. softmax) ----
+ *
+ * CMult by a real constant: both polynomials times the integer K = round(value * sigma) (ties to even),
+ * no level used; the scale becomes ct->scale * sigma (rescale afterwards to consume one level; sigma =
+ * q_level keeps the scale).  E_OVERFLOW when |K| >= 2^62. */
+int hetal_cmult_const(hetal_ctx* ctx, const hetal_ct* ct, double value, double sigma, hetal_ct* out);
+/* value added to every slot: K = round(value * scale) added to c0's constant coefficient.  E_OVERFLOW as above. */
+int hetal_add_const(hetal_ctx* ctx, const hetal_ct* ct, double value, hetal_ct* out);
+/* ct + pt (c0 + m): pt at ct's level (E_LEVEL) and scale up to 1e-9 (E_SCALE). */
+int hetal_add_plain(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, hetal_ct* out);
+/* Re-encryption by the key holder, standing in for bootstrapping (which this library does not provide):
+ * decrypt, lift the plaintext polynomial from q_0 (its centred residue; every other limb must agree,
+ * i.e. |m| < q_0 / 2, else E_OVERFLOW), encrypt at the top level with the caller's randomness (a: host
+ * uint64 [num_q][N] uniform modulo each ciphertext prime, e: host int64 [N]).  The scale is kept.  out
+ * may alias ct and needs room for the top level.  This hands the ciphertext to the client: it is outside
+ * the paper's threat model and meant for pipelines deeper than the modulus chain. */
+int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, const uint64_t* a, const int64_t* e,
+                  hetal_ct* out);
+
+/* Called by the deep pipelines below when a ciphertext has fewer levels than its next step needs: it
+ * must overwrite *ct (the library's buffer, with room for the top level; do not change ct->data) with an
+ * encryption of the same message at the top level and the same scale, e.g. by hetal_refresh, and return
+ * HETAL_OK.  Other return values abort the pipeline with that code. */
+typedef int (*hetal_refresh_fn)(void* user, hetal_ct* ct);
+
+/* sum_k coeffs[k] x^k (degree >= 1) in the power basis: x^k = x^a x^b with a the largest power of two
+ * below k (k/2 twice for a power of two), each product relinearised and rescaled; every term brought to
+ * the lowest level by mod-drop and multiplied by coeffs[k] at the scale that lands on ct's scale; the
+ * constant term added last.  The result has ct's scale (to rounding) and sits max_k (depth of x^k) + 1
+ * levels lower.  If ct has fewer levels, it is first passed to `refresh` (E_LEVEL without one).
+ * out needs room for the top level. */
+int hetal_poly_eval(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, const double* coeffs, int degree,
+                    hetal_refresh_fn refresh, void* user, hetal_ct* out);
+
+/* Parameters of the softmax approximation (App. softmax).  Defaults from hetal_softmax_default_params:
+ * R = 8, L = 2, n = 5 (inputs in [-128, 128]), precise = 1, extend = 1, comp_g = 3, exp_B = 8,
+ * exp_degree = 12 with the L^2 projection of e^t on [-1, 1], inv_R = 100, inv_iters = 16. */
+typedef struct {
+  double R;              /* AExp's range [-R, R], the base interval of the domain extension */
+  double L;              /* domain extension ratio */
+  int n;                 /* domain extension steps: inputs up to L^n R / 2 in magnitude */
+  int precise;           /* apply the degree-5 inverse correction after the extension */
+  int extend;            /* apply the domain extension at all */
+  int comp_g;            /* compositions of g in the comparison f(g(..g(x))) */
+  int exp_B;             /* AExp(x) = p(x / B)^B; a power of two */
+  int exp_degree;        /* degree of p, at most 31 */
+  double exp_coeffs[32]; /* monomial coefficients of p(x / B), [0 .. exp_degree] */
+  double inv_R;          /* AInv's scaling: Goldschmidt's iteration on x / inv_R, converging for x < 2 inv_R */
+  int inv_iters;         /* Goldschmidt steps */
+} hetal_softmax_params;
+
+/* Fills the defaults above (no context needed). */
+int hetal_softmax_default_params(hetal_softmax_params* out);
+/* Rotation steps hetal_softmax_approx needs, for key generation (as hetal_required_rot_steps). */
+int hetal_softmax_rot_steps(const hetal_ctx* ctx, int c, int s0, int32_t* out, int* n);
+/* Row-wise softmax approximation (Alg. "Row-wise softmax approximation"): m is the encryption of an
+ * a x c matrix tiled horizontally (tiling 2 of hetal_mat_encrypt with c' = the power of two >= c;
+ * n_cb = 1; E_SHAPE otherwise); out receives ASoftmax(m) in the same layout, zero in the padded
+ * classes.  The pipeline needs about 100 levels: whenever an operand has fewer than its next step
+ * needs, it is passed to `refresh` (E_LEVEL without one).  *refreshes (may be NULL) receives the
+ * number of refresh calls.  out needs room for n_rb ciphertexts at the top level.  Where the paper is
+ * silent or garbled the library takes the readings stated at the top of its softmax source. */
+int hetal_softmax_approx(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* m, int c,
+                         const hetal_softmax_params* params, hetal_refresh_fn refresh, void* user, hetal_mat* out,
+                         int* refreshes);
+
 /* Operation counters since the last reset: [0] rotations, [1] conjugations,
  * [2] Mult, [3] CMult, [4] rescales, [5] key switches, [6] NTT limb
  * transforms, [7] kernel launches. */

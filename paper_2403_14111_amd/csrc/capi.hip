@@ -1,12 +1,14 @@
 // extern "C" entry points: argument validation, error translation, and the
 // host <-> device transfers of the client-side calls.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "hetal.h"
 #include "matrix.hpp"
+#include "softmax.hpp"
 
 using namespace hetal;
 
@@ -500,6 +502,128 @@ int hetal_mod_drop(hetal_ctx* ctx, const hetal_ct* ct, int level, hetal_ct* out)
   });
 }
 
+int hetal_cmult_const(hetal_ctx* ctx, const hetal_ct* ct, double value, double sigma, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, ct, "ciphertext");
+    check_out(ctx->c, out, ct->level);
+    need(sigma > 0 && std::isfinite(value), HETAL_E_INVALID_ARG, "sigma must be positive and value finite");
+    Context& c = ctx->c;
+    const int lv = ct->level;
+    Batch r = b_mul_const(c, BView{ct->data, lv, 1, ct->scale, c.ct_words(lv)}, value, sigma);
+    HCHECK(hipMemcpyAsync(out->data, r.d, c.ct_words(lv) * 8, hipMemcpyDeviceToDevice, c.stream));
+    out->level = lv;
+    out->scale = r.scale;
+  });
+}
+
+int hetal_add_const(hetal_ctx* ctx, const hetal_ct* ct, double value, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    check_ct(ctx->c, ct, "ciphertext");
+    check_out(ctx->c, out, ct->level);
+    need(std::isfinite(value), HETAL_E_INVALID_ARG, "value must be finite");
+    Context& c = ctx->c;
+    const int lv = ct->level;
+    Batch r = b_add_const(c, BView{ct->data, lv, 1, ct->scale, c.ct_words(lv)}, value);
+    HCHECK(hipMemcpyAsync(out->data, r.d, c.ct_words(lv) * 8, hipMemcpyDeviceToDevice, c.stream));
+    out->level = lv;
+    out->scale = r.scale;
+  });
+}
+
+int hetal_add_plain(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    Context& c = ctx->c;
+    check_ct(c, ct, "ciphertext");
+    check_pt(c, pt);
+    need(pt->level == ct->level, HETAL_E_LEVEL, "plaintext and ciphertext levels differ");
+    need(std::abs(pt->scale - ct->scale) <= 1e-9 * std::max(std::abs(pt->scale), std::abs(ct->scale)), HETAL_E_SCALE,
+         "plaintext and ciphertext scales differ");
+    check_out(c, out, ct->level);
+    const int lv = ct->level;
+    Batch r = b_add_plain(c, BView{ct->data, lv, 1, ct->scale, c.ct_words(lv)}, pt->data);
+    HCHECK(hipMemcpyAsync(out->data, r.d, c.ct_words(lv) * 8, hipMemcpyDeviceToDevice, c.stream));
+    out->level = lv;
+    out->scale = ct->scale;
+  });
+}
+
+int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, const uint64_t* a, const int64_t* e,
+                  hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_ct(c, ct, "ciphertext");
+    const int top = c.num_q - 1;
+    check_out(c, out, top);
+    const size_t poly = c.poly_words(top);
+    Tmp an(c.pool, poly), en(c.pool, poly);
+    load_randomness(c, a, e, top, 1, an, en);
+    const double s = ct->scale;
+    Tmp res(c.pool, c.ct_words(top));
+    refresh_encrypt(c, sk->key.s, view_of(ct), an, en, res);
+    HCHECK(hipMemcpyAsync(out->data, res.p, c.ct_words(top) * 8, hipMemcpyDeviceToDevice, c.stream));
+    HCHECK(hipStreamSynchronize(c.stream));
+    out->level = top;
+    out->scale = s;
+  });
+}
+
+int hetal_poly_eval(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, const double* coeffs, int degree,
+                    hetal_refresh_fn refresh, void* user, hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && keys && coeffs, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_ct(c, ct, "ciphertext");
+    check_out(c, out, c.num_q - 1);
+    need(degree >= 1 && degree <= 64, HETAL_E_INVALID_ARG, "degree must be in [1, 64]");
+    std::vector<double> co(coeffs, coeffs + degree + 1);
+    for (double v : co) need(std::isfinite(v), HETAL_E_INVALID_ARG, "coefficients must be finite");
+    Refresher rf{refresh, user, 0};
+    const int lv = ct->level;
+    Batch r = poly_eval(c, keys->set, BView{ct->data, lv, 1, ct->scale, c.ct_words(lv)}, co, rf);
+    HCHECK(hipMemcpyAsync(out->data, r.d, c.ct_words(r.level) * 8, hipMemcpyDeviceToDevice, c.stream));
+    out->level = r.level;
+    out->scale = r.scale;
+  });
+}
+
+int hetal_softmax_default_params(hetal_softmax_params* out) {
+  return guarded([&] {
+    need(out != nullptr, HETAL_E_INVALID_ARG, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->R = 8.0;
+    out->L = 2.0;
+    out->n = 5;
+    out->precise = 1;
+    out->extend = 1;
+    out->comp_g = 3;
+    out->exp_B = 8;
+    out->exp_degree = 12;
+    const std::vector<double> p = default_exp_coeffs(12, 8);
+    for (int i = 0; i <= 12; ++i) out->exp_coeffs[i] = p[i];
+    out->inv_R = 100.0;
+    out->inv_iters = 16;
+  });
+}
+
+int hetal_softmax_rot_steps(const hetal_ctx* ctx, int cc, int s0, int32_t* out, int* n) {
+  return guarded([&] {
+    need(ctx && n, HETAL_E_INVALID_ARG, "null argument");
+    const Context& c = ctx->c;
+    need(s0 > 0 && c.slots % s0 == 0, HETAL_E_SHAPE, "s0 must divide N/2");
+    need(cc >= 1, HETAL_E_SHAPE, "c must be positive");
+    const std::vector<int> st = softmax_rot_steps(cc, c.slots / s0);
+    if (out) {
+      need(*n >= (int)st.size(), HETAL_E_INVALID_ARG, "output array too small");
+      for (size_t i = 0; i < st.size(); ++i) out[i] = st[i];
+    }
+    *n = (int)st.size();
+  });
+}
+
 int hetal_ct_to_coeff(hetal_ctx* ctx, const hetal_ct* ct, uint64_t* host) {
   return guarded([&] {
     need(ctx && host, HETAL_E_INVALID_ARG, "null argument");
@@ -777,6 +901,43 @@ int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int cc, int s0, int32
     if (out)
       for (size_t i = 0; i < steps.size(); ++i) out[i] = steps[i];
     *n = (int)steps.size();
+  });
+}
+
+int hetal_softmax_approx(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* m, int cc,
+                         const hetal_softmax_params* params, hetal_refresh_fn refresh, void* user, hetal_mat* out,
+                         int* refreshes) {
+  return guarded([&] {
+    need(ctx && keys && params && out && out->data, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_mat(c, m, "M");
+    need(m->n_cb == 1, HETAL_E_SHAPE, "the input must be one block column (horizontally tiled classes)");
+    need(cc >= 1 && cc <= m->s1, HETAL_E_SHAPE, "c out of range");
+    const hetal_softmax_params& p = *params;
+    need(p.R > 0 && p.L > 1 && p.n >= 0 && p.n <= 30 && p.comp_g >= 0 && p.comp_g <= 16 && p.exp_B >= 1 &&
+             p.exp_degree >= 1 && p.exp_degree <= 31 && p.inv_R > 0 && p.inv_iters >= 0 && p.inv_iters <= 64,
+         HETAL_E_INVALID_ARG, "softmax parameters out of range");
+    for (int i = 0; i <= p.exp_degree; ++i)
+      need(std::isfinite(p.exp_coeffs[i]), HETAL_E_INVALID_ARG, "exp coefficients must be finite");
+    need(out->capacity >= (size_t)m->n_rb * c.ct_words(c.num_q - 1), HETAL_E_INVALID_ARG,
+         "output capacity: n_rb ciphertexts at the top level");
+    SoftmaxArgs a;
+    a.R = p.R;
+    a.L = p.L;
+    a.n = p.n;
+    a.precise = p.precise;
+    a.extend = p.extend;
+    a.comp_g = p.comp_g;
+    a.exp_B = p.exp_B;
+    a.exp_coeffs.assign(p.exp_coeffs, p.exp_coeffs + p.exp_degree + 1);
+    a.inv_R = p.inv_R;
+    a.inv_iters = p.inv_iters;
+    Refresher rf{refresh, user, 0};
+    Batch res = softmax_approx(c, keys->set, ctx->masks,
+                               BView{m->data, m->level, m->n_rb, m->scale, c.ct_words(m->level)}, cc, m->s0, m->s1, a,
+                               rf);
+    store_blocks(c, res, out, m->n_rb, 1, m->s0, m->s1);
+    if (refreshes) *refreshes = rf.count;
   });
 }
 

@@ -27,8 +27,12 @@ __global__ void mask_kernel(double* __restrict__ re, double* __restrict__ im, in
     if (d == cc / 2) vi = -0.5 * t;
   } else if (kind == MASK_FIRST_COL) {
     vr = j == 0 ? 1.0 : 0.0;
-  } else {
+  } else if (kind == MASK_LEFT_COLS) {
     vr = j < s1 - k ? 1.0 : 0.0;
+  } else if (kind == MASK_PAD_COLS) {
+    vr = j % cc >= k ? t : 0.0;
+  } else {
+    vr = j >= k ? t : 0.0;
   }
   re[idx] = vr;
   im[idx] = vi;
@@ -229,6 +233,13 @@ const u64* mask_pt(Context& c, MaskCache& cache, MaskKind kind, int k, int cc, i
   encode_slots(c, re, im, 1, 0, level, (double)c.primes[level], pt, 0);
   cache.pts[key] = pt;
   return pt;
+}
+
+void mask_slots(Context& c, MaskKind kind, int k, int cc, int s0, int s1, double t, double* d_re, double* d_im) {
+  const int s = s0 * s1;
+  c.begin_launch();
+  hipLaunchKernelGGL(mask_kernel, dim3((s + 255) / 256), dim3(256), 0, c.stream, d_re, d_im, (int)kind, k, cc, s0, s1, t);
+  c.end_launch(KC_ENCODE, 0.0);
 }
 
 Cipher cmult_mask(Context& c, MaskCache& cache, CtView a, MaskKind kind, int k, int cc, int s0, int s1, double t) {

@@ -84,7 +84,9 @@ Cipher rotate(Context& c, const KeySet& k, CtView a, int r);
 Cipher conjugate(Context& c, const KeySet& k, CtView a);
 
 // Masks: slot patterns of one s0 x s1 block, encoded at `level` with scale q_level.
-enum MaskKind { MASK_OFFDIAG_CPLX = 0, MASK_FIRST_COL = 1, MASK_LEFT_COLS = 2 };
+// MASK_LEFT_COLS: 1 on the columns j < s1 - k.  MASK_PAD_COLS: t on the columns with j mod cc >= k.
+// MASK_COLS_FROM: t on the columns j >= k.
+enum MaskKind { MASK_OFFDIAG_CPLX = 0, MASK_FIRST_COL = 1, MASK_LEFT_COLS = 2, MASK_PAD_COLS = 3, MASK_COLS_FROM = 4 };
 struct MaskCache {
   std::map<std::tuple<int, int, int, int, int, double, int>, u64*> pts;
   ~MaskCache();
@@ -92,6 +94,8 @@ struct MaskCache {
 };
 const u64* mask_pt(Context& c, MaskCache& cache, MaskKind kind, int k, int cc, int s0, int s1, double t, int level);
 Cipher cmult_mask(Context& c, MaskCache& cache, CtView a, MaskKind kind, int k, int cc, int s0, int s1, double t);
+// Slot values (device, [s0 * s1] each) of a mask block.
+void mask_slots(Context& c, MaskKind kind, int k, int cc, int s0, int s1, double t, double* d_re, double* d_im);
 
 void encode_slots(Context& c, const double* d_re, const double* d_im, int count, size_t slot_stride, int level,
                   double scale, u64* out, size_t out_stride);

@@ -54,6 +54,15 @@ class _Req(ctypes.Structure):
                 ("t", ctypes.c_double)]
 
 
+class SoftmaxParams(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double), ("L", ctypes.c_double), ("n", ctypes.c_int), ("precise", ctypes.c_int),
+                ("extend", ctypes.c_int), ("comp_g", ctypes.c_int), ("exp_B", ctypes.c_int),
+                ("exp_degree", ctypes.c_int), ("exp_coeffs", ctypes.c_double * 32), ("inv_R", ctypes.c_double),
+                ("inv_iters", ctypes.c_int)]
+
+
+REFRESH_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(_Ct))
+
 _vp = ctypes.c_void_p
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -103,6 +112,15 @@ _SIGS = {
     "hetal_enc_matmul_atb": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
     "hetal_enc_matmul_batch": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp]),
     "hetal_required_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
+    "hetal_cmult_const": (ctypes.c_int, [_vp, _ctp, ctypes.c_double, ctypes.c_double, _ctp]),
+    "hetal_add_const": (ctypes.c_int, [_vp, _ctp, ctypes.c_double, _ctp]),
+    "hetal_add_plain": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
+    "hetal_refresh": (ctypes.c_int, [_vp, _vp, _ctp, _u64p, _i64p, _ctp]),
+    "hetal_poly_eval": (ctypes.c_int, [_vp, _vp, _ctp, _dblp, ctypes.c_int, REFRESH_FN, _vp, _ctp]),
+    "hetal_softmax_default_params": (ctypes.c_int, [ctypes.POINTER(SoftmaxParams)]),
+    "hetal_softmax_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
+    "hetal_softmax_approx": (ctypes.c_int, [_vp, _vp, _matp, ctypes.c_int, ctypes.POINTER(SoftmaxParams), REFRESH_FN,
+                                            _vp, _matp, _intp]),
     "hetal_counters_get": (ctypes.c_int, [_vp, _i64p]),
     "hetal_counters_reset": (ctypes.c_int, [_vp]),
     "hetal_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -148,7 +166,15 @@ PRESETS = {
     "toy": dict(log_n=12, num_q=5, num_p=1, dnum=5, q0_bits=50, q_bits=40),
     # 2^16 ring, q_0 (50-bit) + 11 x 40-bit, three special primes, dnum = 4.
     "n16l12": dict(log_n=16, num_q=12, num_p=3, dnum=4, q0_bits=50, q_bits=40),
+    # 2^12 ring with the 2^16 ring's modulus chain shape (deep pipelines at test sizes).
+    "n12l12": dict(log_n=12, num_q=12, num_p=3, dnum=4, q0_bits=50, q_bits=40),
 }
+
+
+def softmax_default_params():
+    p = SoftmaxParams()
+    _check(_lib.hetal_softmax_default_params(ctypes.byref(p)))
+    return p
 
 
 class Ciphertext:
@@ -468,6 +494,68 @@ class Context:
                                          int(c), float(t), ctypes.byref(s)))
         out._update(s)
         return out
+
+    # -- constants, refresh, polynomials, softmax (App. softmax) --
+    def cmult_const(self, a, value, sigma):
+        return self._unary(_lib.hetal_cmult_const, a, a.level, ctypes.byref(a._struct()), float(value), float(sigma))
+
+    def add_const(self, a, value):
+        return self._unary(_lib.hetal_add_const, a, a.level, ctypes.byref(a._struct()), float(value))
+
+    def add_plain(self, a, pt):
+        return self._unary(_lib.hetal_add_plain, a, a.level, ctypes.byref(a._struct()), ctypes.byref(pt._struct()))
+
+    def refresh(self, sk, ct, a, e):
+        a, ap = _u64(a)
+        e, ep = _i64(e)
+        assert a.shape == (self.num_q, self.n) and e.shape == (self.n,)
+        return self._unary(_lib.hetal_refresh, ct, self.max_level, sk._h, ctypes.byref(ct._struct()), ap, ep)
+
+    def refresher(self, sk, randomness):
+        """A refresh callback for the deep pipelines: the key holder re-encrypts in place (hetal_refresh) with
+        randomness(i) -> (a, e) for the i-th call.  Keep the returned object alive while the pipeline runs."""
+        count = [0]
+
+        def cb(_user, ct_ptr):
+            try:
+                a, e = randomness(count[0])
+                count[0] += 1
+                a, ap = _u64(a)
+                e, ep = _i64(e)
+                return _lib.hetal_refresh(self._h, sk._h, ct_ptr, ap, ep, ct_ptr)
+            except Exception:  # the library turns a failed refresh into an error of the pipeline
+                return -1
+        fn = REFRESH_FN(cb)
+        fn.calls = count
+        return fn
+
+    def poly_eval(self, keys, ct, coeffs, refresh=None):
+        co, cp = _dbl(coeffs)
+        out = self.new_ct(self.max_level)
+        s = out._struct()
+        _check(_lib.hetal_poly_eval(self._h, keys._h, ctypes.byref(ct._struct()), cp, len(co) - 1,
+                                    refresh if refresh is not None else REFRESH_FN(), None, ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def softmax_rot_steps(self, c, s0):
+        n = ctypes.c_int(0)
+        _check(_lib.hetal_softmax_rot_steps(self._h, int(c), int(s0), None, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        _check(_lib.hetal_softmax_rot_steps(self._h, int(c), int(s0), out.ctypes.data_as(_i32p), ctypes.byref(n)))
+        return [int(x) for x in out[:n.value]]
+
+    def softmax_approx(self, keys, m, c, params=None, refresh=None):
+        """ASoftmax of a horizontally tiled a x c matrix -> (matrix, number of refreshes)."""
+        p = softmax_default_params() if params is None else params
+        out = Matrix(self, m.n_rb * self.ct_words(self.max_level), m.s0, 0, 0.0)
+        s = out._struct()
+        nref = ctypes.c_int(0)
+        _check(_lib.hetal_softmax_approx(self._h, keys._h, ctypes.byref(m._struct()), int(c), ctypes.byref(p),
+                                         refresh if refresh is not None else REFRESH_FN(), None, ctypes.byref(s),
+                                         ctypes.byref(nref)))
+        out._update(s)
+        return out, nref.value
 
     def required_rot_steps(self, op, c, s0):
         n = ctypes.c_int(0)

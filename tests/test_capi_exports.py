@@ -38,3 +38,22 @@ def test_binding_covers_every_symbol():
         pytest.skip("torch missing")
     from paper_2403_14111_amd import hetal
     assert sorted(hetal.exported_symbols()) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_softmax_default_parameters_match_the_oracle():
+    """The library's own defaults (no GPU needed): the paper's parameters, and an AExp polynomial equal to
+    the oracle's L^2 projection to 1e-11 on [-8, 8] (the monomial coefficients themselves are
+    ill-conditioned in their top terms)."""
+    import numpy as np
+    from oracle import softmax as sm
+    from paper_2403_14111_amd import hetal
+    p = hetal.softmax_default_params()
+    ref = sm.SoftmaxParams()
+    assert (p.R, p.L, p.n, p.precise, p.extend, p.comp_g, p.exp_B, p.exp_degree, p.inv_R, p.inv_iters) == \
+        (ref.R, ref.L, ref.n, 1, 1, ref.comp_g, ref.exp_B, ref.exp_degree, ref.inv_R, ref.inv_iters)
+    x = np.linspace(-8, 8, 2001)
+    mine = np.polynomial.polynomial.polyval(x, np.array(p.exp_coeffs[:p.exp_degree + 1]))
+    theirs = np.polynomial.polynomial.polyval(x, np.array(sm.exp_coeffs()))
+    assert np.abs(mine / theirs - 1).max() < 1e-11
+    assert all(v == 0.0 for v in p.exp_coeffs[p.exp_degree + 1:])

@@ -1,0 +1,169 @@
+"""GPU parity of the softmax approximation (App. softmax) and the constant operations under it: every
+ciphertext is compared word for word with the oracle, from the same seeded inputs, refreshes included."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ckks
+from oracle import matrix as mx
+from oracle import softmax as sm
+from paper_2403_14111_amd import inputs
+from tests.gpu_setup import encrypt_slots_gpu, make_gpu
+from tests.oracle_setup import encrypt_slots, make_oracle
+from tests.test_gpu_parity import compare_blocks, enc_mat_both, same
+from tests.test_oracle_softmax import refresher as oracle_refresher
+
+pytestmark = pytest.mark.gpu
+
+S0, S1 = 16, 128
+SEED = 2300
+
+
+def note(msg):
+    print("[case] softmax " + msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def deep():
+    steps = sorted(set(sm.rotation_steps(10, S1)) | set(sm.rotation_steps(3, S1)))
+    note("n12l12 context + keys (%d rotations)" % len(steps))
+    ctx, sk, keys = make_gpu("n12l12", seed=SEED, rot_steps=steps, conj=False)
+    ev = make_oracle("n12l12", seed=SEED, rot_steps=steps, conj=False)
+    return ctx, sk, keys, ev
+
+
+def gpu_refresher(ctx, sk, seed):
+    return ctx.refresher(sk, lambda i: inputs.refresh_randomness(seed, i, ctx.q, ctx.n))
+
+
+def test_rotation_steps_match_the_oracle(deep):
+    ctx = deep[0]
+    for c in (3, 10, 16):
+        assert ctx.softmax_rot_steps(c, S0) == sm.rotation_steps(c, S1)
+
+
+def test_constant_operations_bit_exact(deep):
+    ctx, sk, keys, ev = deep
+    note("constants")
+    lv = 5
+    z = inputs.slot_values(31, ctx.slots)
+    g = encrypt_slots_gpu(ctx, sk, z, lv, seed=3300, index=0)
+    o = encrypt_slots(ev, z, lv, seed=3300, index=0)
+    q = float(ctx.q[lv])
+    same(ctx.ct_to_coeff(ctx.rescale(ctx.cmult_const(g, -0.3, q))), ev.rescale(ev.cmult_const(o, -0.3, q)))
+    for v, sig in ((7.0, 1.0), (-1.0, 1.0), (512.0, 1.0), (1.0, q * 1.0000137)):
+        r = ctx.cmult_const(g, v, sig)
+        ro = ev.cmult_const(o, v, sig)
+        same(ctx.ct_to_coeff(r), ro)
+        assert r.scale == ro.scale
+    for v in (2.5, -0.5, 1.0):
+        same(ctx.ct_to_coeff(ctx.add_const(g, v)), ev.add_const(o, v))
+    vals = np.where(np.arange(ctx.slots) % 16 >= 10, -0.5, 0.0)
+    same(ctx.ct_to_coeff(ctx.add_plain(g, ctx.encode(vals, lv, g.scale))), ev.add_plain(o, vals))
+
+
+def test_refresh_bit_exact_and_overflow(deep):
+    ctx, sk, keys, ev = deep
+    note("refresh")
+    z = inputs.slot_values(32, ctx.slots, bound=3.0)
+    g = encrypt_slots_gpu(ctx, sk, z, 3, seed=3300, index=1, scale=2.0 ** 40 * 1.25)
+    o = encrypt_slots(ev, z, 3, seed=3300, index=1, scale=2.0 ** 40 * 1.25)
+    a, e = inputs.refresh_randomness(SEED, 77, ctx.q, ctx.n)
+    r = ctx.refresh(sk, g, a, e)
+    ro = ckks.refresh(ev.prm, ev.sk, o, a, e)
+    assert r.level == ctx.max_level and r.scale == g.scale
+    same(ctx.ct_to_coeff(r), ro)
+    big = encrypt_slots_gpu(ctx, sk, np.full(ctx.slots, 2000.0), 3, seed=3300, index=2)
+    from paper_2403_14111_amd import hetal
+    with pytest.raises(hetal.HetalError) as ei:
+        ctx.refresh(sk, big, a, e)
+    assert ei.value.name == "E_OVERFLOW"
+
+
+@pytest.mark.parametrize("which", ["g", "comp", "dep", "dep_inv", "exp"])
+@pytest.mark.parametrize("level", [11, 2])
+def test_poly_eval_bit_exact(deep, which, level):
+    ctx, sk, keys, ev = deep
+    note("poly %s level %d" % (which, level))
+    prm = sm.SoftmaxParams()
+    coeffs = {"g": sm.g_coeffs(), "comp": sm.comp_out_coeffs(), "dep": sm.dep_coeffs(prm, 2),
+              "dep_inv": sm.dep_inv_coeffs(prm), "exp": sm.exp_coeffs()}[which]
+    z = inputs.slot_values(33, ctx.slots, bound=0.9, complex_=False)
+    g = encrypt_slots_gpu(ctx, sk, z, level, seed=3300, index=3)
+    o = encrypt_slots(ev, z, level, seed=3300, index=3)
+    seed = SEED + 10 + level
+    gr = gpu_refresher(ctx, sk, seed)
+    out = ctx.poly_eval(keys, g, coeffs, refresh=gr)
+    S = sm.Steps(ev, ev.prm.q, ev.prm.max_level, oracle_refresher(ev, seed))
+    ref = S.poly([o], coeffs)[0]
+    assert gr.calls[0] == S.refreshes
+    assert out.level == ref.level and out.scale == ref.scale
+    same(ctx.ct_to_coeff(out), ref)
+
+
+def test_poly_eval_without_levels_needs_a_refresh(deep):
+    ctx, sk, keys, ev = deep
+    from paper_2403_14111_amd import hetal
+    g = encrypt_slots_gpu(ctx, sk, inputs.slot_values(34, ctx.slots), 1, seed=3300, index=4)
+    with pytest.raises(hetal.HetalError) as ei:
+        ctx.poly_eval(keys, g, sm.g_coeffs())
+    assert ei.value.name == "E_LEVEL"
+
+
+@pytest.mark.parametrize("c", [10, 3])
+def test_softmax_bit_exact(deep, c):
+    """The whole Alg. softmax on a 20 x c matrix (two row blocks), refreshes included, word for word."""
+    ctx, sk, keys, ev = deep
+    note("approx c=%d" % c)
+    cp = mx.next_pow2(c)
+    M = inputs.logits(80 + c, 20, c, 32.0)
+    gm, oblocks = enc_mat_both(ctx, sk, ev, M, S0, 8, 2, cp, seed=90 + c)
+    seed = SEED + 100 + c
+    gr = gpu_refresher(ctx, sk, seed)
+    gout, nref = ctx.softmax_approx(keys, gm, c, refresh=gr)
+    prm = sm.SoftmaxParams()
+    oout, onref = sm.asoftmax_blocks(ev, [row[0] for row in oblocks], c, S0, S1, prm, sm.exp_coeffs(), ev.prm.q,
+                                     ev.prm.max_level, oracle_refresher(ev, seed))
+    assert nref == onref == gr.calls[0]
+    assert gout.level == oout[0].level and gout.scale == oout[0].scale
+    compare_blocks(ctx, gout, oout)
+    res = ctx.mat_decrypt(sk, gout)[:20, :c]
+    assert np.abs(res - sm.asoftmax_rows(M, prm)).max() < 1e-4
+    assert np.abs(res - sm.softmax_rows(M)).max() < 0.03
+
+
+def test_softmax_argument_errors(deep):
+    ctx, sk, keys, ev = deep
+    from paper_2403_14111_amd import hetal
+    M = inputs.logits(99, 4, 10, 8.0)
+    gm, _ = enc_mat_both(ctx, sk, ev, M, S0, 8, 2, 16, seed=99)
+    with pytest.raises(hetal.HetalError) as ei:
+        ctx.softmax_approx(keys, gm, 10)                       # no refresh: ~100 levels are not there
+    assert ei.value.name == "E_LEVEL"
+    with pytest.raises(hetal.HetalError) as ei:
+        ctx.softmax_approx(keys, gm, 200, refresh=gpu_refresher(ctx, sk, 1))
+    assert ei.value.name == "E_SHAPE"
+
+
+def test_softmax_full_ring_bench_shape():
+    """N = 2^16 at the benchmark's shape (128 x 10 -> c' = 16, s0 = 128): accurate against the plain form."""
+    s0 = 128
+    s1 = 32768 // s0
+    steps = sm.rotation_steps(10, s1)
+    note("full ring context + keys")
+    ctx, sk, keys = make_gpu("n16l12", seed=2400, rot_steps=steps, conj=False)
+    M = inputs.logits(81, 128, 10, 64.0)
+    blocks = mx.block_encode(mx.tile_horizontal(np.hstack([M, np.zeros((128, 6))]), s1), s0, s1)
+    rand = [inputs.encryption_randomness(95, 0, ctx.q[:9], ctx.n)]
+    gm = ctx.mat_encrypt(sk, M, s0, 8, 2.0 ** 40, np.stack([rand[0][0]]), np.stack([rand[0][1]]), tiling=2, c=16)
+    assert len(blocks) == 1
+    note("full ring approx")
+    gout, nref = ctx.softmax_approx(keys, gm, 10, refresh=gpu_refresher(ctx, sk, 2401))
+    assert nref > 0
+    res = ctx.mat_decrypt(sk, gout)
+    prm = sm.SoftmaxParams()
+    want = np.zeros((128, 16))
+    want[:, :10] = sm.asoftmax_rows(M, prm)
+    assert np.abs(res[:128] - np.tile(want, (1, s1 // 16))).max() < 1e-4
+    assert np.abs(res[:128, :10] - sm.softmax_rows(M)).max() < 0.03
