@@ -563,6 +563,90 @@ def softmax_bench(reps):
                       "reps": reps}), flush=True)
 
 
+def nag_gamma(t):
+    """gamma_t = (1 - lambda_t) / lambda_{t+1}, lambda_0 = 0, lambda_{t+1} = (1 + sqrt(1 + 4 lambda_t^2)) / 2."""
+    lam = 0.0
+    for _ in range(t):
+        lam = (1.0 + np.sqrt(1.0 + 4.0 * lam * lam)) / 2.0
+    return (1.0 - lam) / ((1.0 + np.sqrt(1.0 + 4.0 * lam * lam)) / 2.0)
+
+
+def train_bench(steps):
+    """Consecutive encrypted training steps (the protocol's step 3(a): NAG with P = ASoftmax(X V^T), Sec. 3) on
+    one mini-batch of the benchmark shape: X 128 x 769 (768 features and the bias column), 10 classes (c' = 16),
+    s0 = 128, N = 2^16, inputs encrypted at level 11, learning rate 1 over the batch size.  Refreshes by the key
+    holder are timed apart.  The decrypted weights are checked against the same steps in FP64 with the exact
+    softmax.  One JSON line."""
+    import torch
+    from paper_2403_14111_amd import hetal, inputs
+    ctx = hetal.Context("n16l12")
+    sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
+    keys = ctx.keys_create()
+    a, e = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
+    keys.gen_relin(sk, a, e)
+    rot = set(ctx.softmax_rot_steps(CLASSES, S0)) | set(ctx.required_rot_steps(0, C_PAD, S0)) | \
+        set(ctx.required_rot_steps(1, C_PAD, S0)) | set(ctx.required_rot_steps(2, C_PAD, S0))
+    for g in sorted(set(ctx.galois_rot(r) for r in rot) | {ctx.galois_conj()}):
+        a, e = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(1, g), ctx.dnum, ctx.primes, ctx.n)
+        keys.gen_galois(sk, g, a, e)
+    X = np.hstack([inputs.features(SEEDS["data"], A_ROWS, FEAT), np.ones((A_ROWS, 1))])
+    Y = np.eye(CLASSES)[inputs.labels(SEEDS["data"], A_ROWS, CLASSES)]
+    W0 = inputs.weights(SEEDS["data"], CLASSES, FEAT + 1)
+
+    def enc(M, tiling, first):
+        nb = int(np.prod(ctx.mat_blocks(M.shape[0], M.shape[1], S0, tiling, C_PAD)))
+        ea, ee = enc_randomness(ctx, nb, LEVEL, first)
+        return ctx.mat_encrypt(sk, M, S0, LEVEL, 2.0 ** 40, ea, ee, tiling=tiling, c=C_PAD)
+    gx, gy, gw = enc(X, 0, 6000), enc(Y, 2, 6100), enc(W0, 1, 6200)
+    gv = gw
+    lr = 1.0 / A_ROWS
+    spent = [0.0]
+    base = ctx.refresher(sk, lambda i: inputs.refresh_randomness(SEEDS["enc"] + 99, i, ctx.q, ctx.n))
+
+    def timed(user, ct_ptr):
+        t0 = time.perf_counter()
+        rc = base(user, ct_ptr)
+        torch.cuda.synchronize()
+        spent[0] += time.perf_counter() - t0
+        return rc
+    fn = hetal.REFRESH_FN(timed)
+    ctx.nag_step(keys, gx, gy, gw, gv, CLASSES, lr, nag_gamma(1), refresh=fn)   # warm-up: masks cached
+    Wp, Vp = W0.copy(), W0.copy()
+    totals, clients, nrefs = [], [], []
+    for t in range(1, steps + 1):
+        gamma = nag_gamma(t)
+        spent[0] = 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gw, gv, nref = ctx.nag_step(keys, gx, gy, gw, gv, CLASSES, lr, gamma, refresh=fn)
+        torch.cuda.synchronize()
+        totals.append(time.perf_counter() - t0)
+        clients.append(spent[0])
+        nrefs.append(nref)
+        L = X @ Vp.T
+        P = np.exp(L - L.max(axis=1, keepdims=True))
+        P /= P.sum(axis=1, keepdims=True)
+        Wn = Vp - lr * (P - Y).T @ X
+        Vp, Wp = (1.0 - gamma) * Wn + gamma * Wp, Wn
+        log("step %d: %.1f ms (%d refreshes)" % (t, 1e3 * totals[-1], nref))
+    got = ctx.mat_decrypt(sk, gw)[:CLASSES, :FEAT + 1]
+
+    def ce(Wm):
+        L = X @ Wm.T
+        L = L - L.max(axis=1, keepdims=True)
+        return float(-np.mean(np.sum(Y * (L - np.log(np.exp(L).sum(axis=1, keepdims=True))), axis=1)))
+    server = [t_ - c_ for t_, c_ in zip(totals, clients)]
+    print(json.dumps({"train_step": {
+        "ms_per_step": round(1e3 * float(np.median(totals)), 1),
+        "server_ms": round(1e3 * float(np.median(server)), 1),
+        "key_holder_refresh_ms": round(1e3 * float(np.median(clients)), 1),
+        "refreshes_per_step": nrefs, "steps": steps,
+        "max_abs_err_W_vs_fp64": float(np.abs(got - Wp).max()),
+        "cross_entropy": {"start": round(ce(W0), 5), "encrypted": round(ce(got), 5), "fp64": round(ce(Wp), 5)},
+        "shape": "X 128 x 769 (bias column), 10 classes -> c'=16, s0=128, s1=256, N=2^16, inputs at level 11",
+        "lr": lr}}), flush=True)
+
+
 def cpu_baseline(X, W, gpu_abt_coeffs):
     """The oracle (never tuned) on one full DiagABT of the same workload."""
     from oracle import ckks
@@ -628,6 +712,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--softmax", type=int, default=0, metavar="REPS",
                     help="time the softmax approximation (App. softmax) at the forward product's shape, REPS runs")
+    ap.add_argument("--train-step", type=int, default=0, metavar="STEPS",
+                    help="time STEPS consecutive encrypted NAG training steps (softmax included)")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the benchmark: DiagABT / DiagATB (both branches) at the paper's Table 4 shapes, "
                          "one JSON line per shape (median of --steps calls)")
@@ -654,6 +740,9 @@ def main():
         return
     if args.softmax:
         softmax_bench(args.softmax)
+        return
+    if args.train_step:
+        train_bench(args.train_step)
         return
     if args.serve:
         serve_bench(args.clients, args.serve, args.rate, args.budget_gib)

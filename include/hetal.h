@@ -258,18 +258,21 @@ int hetal_add_const(hetal_ctx* ctx, const hetal_ct* ct, double value, hetal_ct* 
 /* ct + pt (c0 + m): pt at ct's level (E_LEVEL) and scale up to 1e-9 (E_SCALE). */
 int hetal_add_plain(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, hetal_ct* out);
 /* Re-encryption by the key holder, standing in for bootstrapping (which this library does not provide):
- * decrypt, lift the plaintext polynomial from q_0 (its centred residue; every other limb must agree,
- * i.e. |m| < q_0 / 2, else E_OVERFLOW), encrypt at the top level with the caller's randomness (a: host
- * uint64 [num_q][N] uniform modulo each ciphertext prime, e: host int64 [N]).  The scale is kept.  out
- * may alias ct and needs room for the top level.  This hands the ciphertext to the client: it is outside
- * the paper's threat model and meant for pipelines deeper than the modulus chain. */
-int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, const uint64_t* a, const int64_t* e,
-                  hetal_ct* out);
+ * decrypt, lift the plaintext polynomial m from q_0 (its centred residue; every other limb must agree,
+ * i.e. |m| < q_0 / 2, else E_OVERFLOW), re-encode it at `scale` as rint(m * scale / ct->scale) (ties to
+ * even; scale 0 keeps the scale and m), encrypt at the top level with the caller's randomness (a: host
+ * uint64 [num_q][N] uniform modulo each ciphertext prime, e: host int64 [N]).  out may alias ct and needs
+ * room for the top level.  This hands the ciphertext to the client: it is outside the paper's threat model
+ * and meant for pipelines deeper than the modulus chain.  Re-encoding at a fixed scale (2^40) keeps chains
+ * of squarings from driving the scale away from the primes. */
+int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, double scale, const uint64_t* a,
+                  const int64_t* e, hetal_ct* out);
 
 /* Called by the deep pipelines below when a ciphertext has fewer levels than its next step needs: it
  * must overwrite *ct (the library's buffer, with room for the top level; do not change ct->data) with an
- * encryption of the same message at the top level and the same scale, e.g. by hetal_refresh, and return
- * HETAL_OK.  Other return values abort the pipeline with that code. */
+ * encryption of the same message at the top level, e.g. by hetal_refresh, and return HETAL_OK; the library
+ * reads back the new scale (the items of one batch must get the same one).  Other return values abort the
+ * pipeline with that code. */
 typedef int (*hetal_refresh_fn)(void* user, hetal_ct* ct);
 
 /* sum_k coeffs[k] x^k (degree >= 1) in the power basis: x^k = x^a x^b with a the largest power of two
@@ -312,6 +315,19 @@ int hetal_softmax_rot_steps(const hetal_ctx* ctx, int c, int s0, int32_t* out, i
 int hetal_softmax_approx(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* m, int c,
                          const hetal_softmax_params* params, hetal_refresh_fn refresh, void* user, hetal_mat* out,
                          int* refreshes);
+
+/* One step of the encrypted training loop (the protocol's step 3(a), Sec. 3's NAG update):
+ *   P = ASoftmax(X V^T),  W_out = V - lr (P - Y)^T X,  V_out = (1 - gamma) W_out + gamma W,
+ * with lr = alpha / N (learning rate over batch size) and gamma the schedule's gamma_t, both chosen by the
+ * caller.  X: a x b features, untiled (n_rb x n_cb blocks).  Y: a x c one-hot labels tiled horizontally with
+ * c' = the power of two >= c (n_rb x 1).  W, V: c x b weights tiled vertically (1 x n_cb; tiling 1 of
+ * hetal_mat_encrypt with c').  X V^T is DiagABT (Alg. 1) and the gradient DiagATB (Alg. 4, t = -lr).  X and V
+ * are refreshed below 3 levels, P - Y below 4, and the softmax refreshes as in hetal_softmax_approx (E_LEVEL
+ * without a refresh callback).  E_SHAPE unless 2 <= c, c' <= s0 and c' | s1.  W_out and V_out (distinct) need
+ * room for n_cb ciphertexts at the top level; *refreshes (may be NULL) counts all refresh calls. */
+int hetal_nag_step(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* x, const hetal_mat* y, const hetal_mat* w,
+                   const hetal_mat* v, int c, double lr, double gamma, const hetal_softmax_params* params,
+                   hetal_refresh_fn refresh, void* user, hetal_mat* w_out, hetal_mat* v_out, int* refreshes);
 
 /* Operation counters since the last reset: [0] rotations, [1] conjugations,
  * [2] Mult, [3] CMult, [4] rescales, [5] key switches, [6] NTT limb

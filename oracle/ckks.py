@@ -358,12 +358,15 @@ def decrypt(prm, sk, ct):
     return Pt(m, ct.scale)
 
 
-def refresh(prm, sk, ct, a_rand, e_rand):
+def refresh(prm, sk, ct, a_rand, e_rand, scale=None):
     """A fresh encryption at the top level of the message of `ct`, made by the key holder:
-    decrypt, lift the plaintext polynomial from q_0 (centred; every other limb must agree,
-    i.e. |m| < q_0 / 2), re-encrypt with the given randomness (a_rand over all ciphertext
-    primes).  The scale is kept.  This stands in for bootstrapping, which this library does
-    not provide: the server hands the ciphertext back to the client."""
+    decrypt, lift the plaintext polynomial m from q_0 (centred; every other limb must agree,
+    i.e. |m| < q_0 / 2), re-encode it at `scale` as round(m * (scale / ct.scale)) (ties to
+    even; `scale` None keeps the scale and m), re-encrypt with the given randomness (a_rand
+    over all ciphertext primes).  This stands in for bootstrapping, which this library does
+    not provide: the server hands the ciphertext back to the client.  Re-encoding at a fixed
+    scale stops the drift that chains of squarings give the scale (each doubles its log
+    distance from the primes)."""
     pt = decrypt(prm, sk, ct)
     q0 = prm.q[0]
     m0 = pt.m[0].astype(np.int64)
@@ -371,7 +374,11 @@ def refresh(prm, sk, ct, a_rand, e_rand):
     for i in range(1, pt.level + 1):
         if not np.array_equal(reduce_signed(m0, [prm.q[i]], prm.log_n)[0], pt.m[i]):
             raise OverflowError("message too large to lift from q_0")
-    return encrypt(prm, sk, Pt(reduce_signed(m0, prm.q, prm.log_n), ct.scale), a_rand, e_rand)
+    new_scale = ct.scale if scale is None else float(scale)
+    if scale is not None:
+        r = new_scale / ct.scale
+        m0 = np.rint(m0.astype(np.float64) * r).astype(np.int64)
+    return encrypt(prm, sk, Pt(reduce_signed(m0, prm.q, prm.log_n), new_scale), a_rand, e_rand)
 
 
 # --------------------------------------------------------------------------

@@ -44,8 +44,11 @@ Readings (the paper is silent or garbled here; each is also listed with the desi
     term c_k x^k is brought to the common level by mod-drop and multiplied by c_k encoded at the
     scale that lands on the input's scale; the constant term is added last.
   * Levels: an operand whose level is below what the next step needs is refreshed (handed back
-    to the key holder and re-encrypted at the top level, see ``ckks.refresh``); the paper
-    bootstraps instead.  Sums of ciphertexts whose scales differ bring the second operand to
+    to the key holder and re-encrypted at the top level and the scale 2^40, see ``ckks.refresh``);
+    the paper bootstraps instead.  Re-encoding at a fixed scale matters: Goldschmidt's 16
+    squarings double the scale's log distance from the primes at every step, which at N = 2^16
+    (primes up to 5e-6 below 2^40) would leave the output at scale ~2^52 and overflow the
+    constants of a following training step.  Sums of ciphertexts whose scales differ bring the second operand to
     the first's scale with a constant 1 encoded at the matching scale (one level).
 
 Parity status: the plain form is pinned by the closed form of f, the DEP lemmas, the
@@ -522,4 +525,5 @@ class ScaledSim:
         return ScaledSim.Ct(np.roll(a.z, -r), a.level, a.scale)
 
     def refresh(self, a):
-        return ScaledSim.Ct(a.z, self.prm.max_level, a.scale)
+        """The key holder's refresh: top level, re-encoded at the parameter set's scale."""
+        return ScaledSim.Ct(a.z, self.prm.max_level, self.prm.scale)

@@ -550,8 +550,8 @@ int hetal_add_plain(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, heta
   });
 }
 
-int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, const uint64_t* a, const int64_t* e,
-                  hetal_ct* out) {
+int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, double scale, const uint64_t* a,
+                  const int64_t* e, hetal_ct* out) {
   return guarded([&] {
     need(ctx && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
     Context& c = ctx->c;
@@ -561,9 +561,10 @@ int hetal_refresh(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, const 
     const size_t poly = c.poly_words(top);
     Tmp an(c.pool, poly), en(c.pool, poly);
     load_randomness(c, a, e, top, 1, an, en);
-    const double s = ct->scale;
+    need(std::isfinite(scale) && scale >= 0.0, HETAL_E_SCALE, "scale must be 0 (keep) or positive");
+    const double s = scale > 0.0 ? scale : ct->scale;
     Tmp res(c.pool, c.ct_words(top));
-    refresh_encrypt(c, sk->key.s, view_of(ct), an, en, res);
+    refresh_encrypt(c, sk->key.s, view_of(ct), scale, an, en, res);
     HCHECK(hipMemcpyAsync(out->data, res.p, c.ct_words(top) * 8, hipMemcpyDeviceToDevice, c.stream));
     HCHECK(hipStreamSynchronize(c.stream));
     out->level = top;
@@ -904,6 +905,8 @@ int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int cc, int s0, int32
   });
 }
 
+static SoftmaxArgs softmax_args(const hetal_softmax_params& p);
+
 int hetal_softmax_approx(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* m, int cc,
                          const hetal_softmax_params* params, hetal_refresh_fn refresh, void* user, hetal_mat* out,
                          int* refreshes) {
@@ -913,30 +916,70 @@ int hetal_softmax_approx(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
     check_mat(c, m, "M");
     need(m->n_cb == 1, HETAL_E_SHAPE, "the input must be one block column (horizontally tiled classes)");
     need(cc >= 1 && cc <= m->s1, HETAL_E_SHAPE, "c out of range");
-    const hetal_softmax_params& p = *params;
-    need(p.R > 0 && p.L > 1 && p.n >= 0 && p.n <= 30 && p.comp_g >= 0 && p.comp_g <= 16 && p.exp_B >= 1 &&
-             p.exp_degree >= 1 && p.exp_degree <= 31 && p.inv_R > 0 && p.inv_iters >= 0 && p.inv_iters <= 64,
-         HETAL_E_INVALID_ARG, "softmax parameters out of range");
-    for (int i = 0; i <= p.exp_degree; ++i)
-      need(std::isfinite(p.exp_coeffs[i]), HETAL_E_INVALID_ARG, "exp coefficients must be finite");
     need(out->capacity >= (size_t)m->n_rb * c.ct_words(c.num_q - 1), HETAL_E_INVALID_ARG,
          "output capacity: n_rb ciphertexts at the top level");
-    SoftmaxArgs a;
-    a.R = p.R;
-    a.L = p.L;
-    a.n = p.n;
-    a.precise = p.precise;
-    a.extend = p.extend;
-    a.comp_g = p.comp_g;
-    a.exp_B = p.exp_B;
-    a.exp_coeffs.assign(p.exp_coeffs, p.exp_coeffs + p.exp_degree + 1);
-    a.inv_R = p.inv_R;
-    a.inv_iters = p.inv_iters;
+    const SoftmaxArgs a = softmax_args(*params);
     Refresher rf{refresh, user, 0};
     Batch res = softmax_approx(c, keys->set, ctx->masks,
                                BView{m->data, m->level, m->n_rb, m->scale, c.ct_words(m->level)}, cc, m->s0, m->s1, a,
                                rf);
     store_blocks(c, res, out, m->n_rb, 1, m->s0, m->s1);
+    if (refreshes) *refreshes = rf.count;
+  });
+}
+
+static SoftmaxArgs softmax_args(const hetal_softmax_params& p) {
+  need(p.R > 0 && p.L > 1 && p.n >= 0 && p.n <= 30 && p.comp_g >= 0 && p.comp_g <= 16 && p.exp_B >= 1 &&
+           p.exp_degree >= 1 && p.exp_degree <= 31 && p.inv_R > 0 && p.inv_iters >= 0 && p.inv_iters <= 64,
+       HETAL_E_INVALID_ARG, "softmax parameters out of range");
+  for (int i = 0; i <= p.exp_degree; ++i)
+    need(std::isfinite(p.exp_coeffs[i]), HETAL_E_INVALID_ARG, "exp coefficients must be finite");
+  SoftmaxArgs a;
+  a.R = p.R;
+  a.L = p.L;
+  a.n = p.n;
+  a.precise = p.precise;
+  a.extend = p.extend;
+  a.comp_g = p.comp_g;
+  a.exp_B = p.exp_B;
+  a.exp_coeffs.assign(p.exp_coeffs, p.exp_coeffs + p.exp_degree + 1);
+  a.inv_R = p.inv_R;
+  a.inv_iters = p.inv_iters;
+  return a;
+}
+
+int hetal_nag_step(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* x, const hetal_mat* y, const hetal_mat* w,
+                   const hetal_mat* v, int cc, double lr, double gamma, const hetal_softmax_params* params,
+                   hetal_refresh_fn refresh, void* user, hetal_mat* w_out, hetal_mat* v_out, int* refreshes) {
+  return guarded([&] {
+    need(ctx && keys && params && w_out && v_out && w_out->data && v_out->data, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_mat(c, x, "X");
+    check_mat(c, y, "Y");
+    check_mat(c, w, "W");
+    check_mat(c, v, "V");
+    const int s0 = x->s0, s1 = x->s1;
+    need(y->s0 == s0 && w->s0 == s0 && v->s0 == s0, HETAL_E_SHAPE, "all matrices need one block shape");
+    need(y->n_rb == x->n_rb && y->n_cb == 1, HETAL_E_SHAPE, "Y: one block per block row of X (tiled classes)");
+    need(w->n_rb == 1 && v->n_rb == 1 && w->n_cb == x->n_cb && v->n_cb == x->n_cb, HETAL_E_SHAPE,
+         "W and V: one block row, one block per block column of X");
+    int cp = 1;
+    while (cp < cc) cp *= 2;
+    need(cc >= 2 && cp <= s0 && s1 % cp == 0, HETAL_E_SHAPE, "need 2 <= c, c' <= s0 and c' | s1");
+    need(std::isfinite(lr) && std::isfinite(gamma), HETAL_E_INVALID_ARG, "lr and gamma must be finite");
+    const size_t top_words = c.ct_words(c.num_q - 1);
+    need(w_out->capacity >= (size_t)x->n_cb * top_words && v_out->capacity >= (size_t)x->n_cb * top_words,
+         HETAL_E_INVALID_ARG, "output capacity: n_cb ciphertexts at the top level");
+    need(w_out->data != v_out->data, HETAL_E_INVALID_ARG, "W and V outputs must differ");
+    const SoftmaxArgs a = softmax_args(*params);
+    Refresher rf{refresh, user, 0};
+    auto bv = [&](const hetal_mat* m) {
+      return BView{m->data, m->level, m->n_rb * m->n_cb, m->scale, c.ct_words(m->level)};
+    };
+    NagResult r = nag_step(c, keys->set, ctx->masks, bv(x), x->n_rb, x->n_cb, bv(y), bv(w), bv(v), cc, s0, s1, lr,
+                           gamma, a, rf);
+    store_blocks(c, r.W, w_out, 1, x->n_cb, s0, s1);
+    store_blocks(c, r.V, v_out, 1, x->n_cb, s0, s1);
     if (refreshes) *refreshes = rf.count;
   });
 }

@@ -21,6 +21,7 @@
 #include <map>
 #include <set>
 
+#include "matrix.hpp"
 #include "softmax.hpp"
 
 namespace hetal {
@@ -79,23 +80,33 @@ __global__ void __launch_bounds__(TPB) add_plain_kernel(const u64* __restrict__ 
   out[item * out_stride + (size_t)row * n + k] = v;
 }
 
-// Coefficient-form plaintext m (rows 0..level) lifted from q_0: y = [m_0]_centred, out[i] = y mod q_i for the
-// out_rows primes; *bad is set when a row i <= level disagrees with y mod q_i.
+// Coefficient-form plaintext m (rows 0..level) lifted from q_0: y = [m_0]_centred (*bad is set when a row
+// i <= level disagrees with y mod q_i), re-encoded as rint(y * ratio) when `rescale` (ties to even), and written
+// modulo each of the out_rows primes.
 __global__ void __launch_bounds__(TPB) lift_q0_kernel(const u64* __restrict__ m, int level, u64* __restrict__ out,
                                                       int out_rows, const ModInfo* __restrict__ mods, int log_n,
-                                                      int* __restrict__ bad) {
+                                                      double ratio, int rescale, int* __restrict__ bad) {
   const int n = 1 << log_n;
   const int k = blockIdx.x * TPB + threadIdx.x;
   const u64 q0 = mods[0].q;
   const u64 v = m[k];
   const bool neg = v > q0 / 2;
-  const u64 mag = neg ? q0 - v : v;  // |y|
+  u64 mag = neg ? q0 - v : v;  // |y|
+  for (int i = 1; i <= level; ++i) {
+    const u64 q = mods[i].q;
+    const u64 r = mag % q;
+    if ((neg ? (r ? q - r : 0) : r) != m[(size_t)i * n + k]) *bad = 1;
+  }
+  bool sneg = neg;
+  if (rescale) {
+    const double z = rint((double)(neg ? -(i64)mag : (i64)mag) * ratio);
+    sneg = z < 0.0;
+    mag = (u64)(sneg ? -z : z);
+  }
   for (int i = 0; i < out_rows; ++i) {
     const u64 q = mods[i].q;
     const u64 r = mag % q;
-    const u64 y = neg ? (r ? q - r : 0) : r;
-    if (i <= level && y != m[(size_t)i * n + k]) *bad = 1;
-    out[(size_t)i * n + k] = y;
+    out[(size_t)i * n + k] = sneg ? (r ? q - r : 0) : r;
   }
 }
 
@@ -154,7 +165,8 @@ Batch b_add_plain(Context& c, BView a, const u64* pt) {
   return o;
 }
 
-void refresh_encrypt(Context& c, const u64* s, CtView ct, const u64* a_ntt, const u64* e_ntt, u64* out) {
+void refresh_encrypt(Context& c, const u64* s, CtView ct, double scale, const u64* a_ntt, const u64* e_ntt,
+                     u64* out) {
   const int top = c.num_q - 1;
   const size_t poly = c.poly_words(ct.level);
   Tmp m(c.pool, poly);
@@ -165,8 +177,11 @@ void refresh_encrypt(Context& c, const u64* s, CtView ct, const u64* a_ntt, cons
   Tmp flag(c.pool, 1);
   HCHECK(hipMemsetAsync(flag.p, 0, 8, c.stream));
   c.begin_launch();
+  const int rescale = scale > 0.0 ? 1 : 0;
+  const double ratio = rescale ? scale / ct.scale : 1.0;
+  if (rescale && !(std::fabs(ratio) < 1e12)) fail(HETAL_E_SCALE, "refresh scale ratio out of range");
   hipLaunchKernelGGL(lift_q0_kernel, dim3((unsigned)(c.n / TPB)), dim3(TPB), 0, c.stream, m.p, ct.level, lifted.p,
-                     top + 1, c.d_mod, c.log_n, reinterpret_cast<int*>(flag.p));
+                     top + 1, c.d_mod, c.log_n, ratio, rescale, reinterpret_cast<int*>(flag.p));
   c.end_launch(KC_ELEMWISE, 8.0 * c.n * (ct.level + 1 + top + 1));
   int bad = 0;
   HCHECK(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, c.stream));
@@ -237,12 +252,13 @@ struct Steps {
       h.scale = x.scale();
       const int rc = rf.fn(rf.user, &h);
       if (rc != HETAL_OK) fail(rc, "refresh callback failed");
-      if (h.data != buf.p || h.level != top || std::abs(h.scale - x.scale()) > 1e-9 * std::abs(x.scale()))
-        fail(HETAL_E_INVALID_ARG, "refresh must re-encrypt in place at the top level with the same scale");
+      if (h.data != buf.p || h.level != top || !(h.scale > 0.0) || !std::isfinite(h.scale))
+        fail(HETAL_E_INVALID_ARG, "refresh must re-encrypt in place at the top level with a positive scale");
+      if (i > 0 && h.scale != out.scale) fail(HETAL_E_SCALE, "refresh gave the items of one batch different scales");
+      out.scale = h.scale;
       HCHECK(hipMemcpyAsync(out.d + (size_t)i * wtop, buf.p, wtop * 8, hipMemcpyDeviceToDevice, c.stream));
       rf.count += 1;
     }
-    out.scale = x.scale();
     return Val(std::move(out));
   }
 
@@ -468,6 +484,37 @@ Batch softmax_approx(Context& c, const KeySet& k, MaskCache& mc, BView m, int cc
   Val sm = S.mult(Val(e.v), Val(z.v), false);
   for (int j = cp; j < s1; j *= 2) sm = S.combine(Val(sm.v), S.rot(sm, -j), false);
   return owned(c, std::move(sm));
+}
+
+NagResult nag_step(Context& c, const KeySet& k, MaskCache& mc, BView X, int n_rb, int n_cb, BView Y, BView W,
+                   BView V, int cls, int s0, int s1, double lr, double gamma, const SoftmaxArgs& a, Refresher& rf) {
+  int cp = 1;
+  while (cp < cls) cp *= 2;
+  Steps S{c, k, &mc, rf, s0, s1};
+  Val Xv = S.need(Val(X), 3);
+  Val Vv = S.need(Val(V), 3);
+  std::vector<std::vector<CtView>> A(n_rb);
+  for (int i = 0; i < n_rb; ++i)
+    for (int j = 0; j < n_cb; ++j) A[i].push_back(Xv.v.item(i * n_cb + j));
+  std::vector<CtView> Bbar;
+  for (int j = 0; j < n_cb; ++j) Bbar.push_back(Vv.v.item(j));
+  Batch L = diag_abt_batch(c, k, mc, A, Bbar, cp, s0, s1, 1.0);
+  Batch P = softmax_approx(c, k, mc, L.v(), cls, s0, s1, a, rf);
+  L = Batch();
+  Val D = S.combine(Val(P.v()), Val(Y), true);
+  D = S.need(std::move(D), 4);
+  std::vector<CtView> Abar;
+  for (int i = 0; i < n_rb; ++i) Abar.push_back(D.v.item(i));
+  Batch G = diag_atb_batch(c, k, mc, Abar, A, cp, s0, s1, -lr);
+  Val Wn = S.combine(Val(Vv.v), Val(G.v()), false);
+  // the two scalings in this order (each may refresh its operand)
+  Val t1 = S.cconst(Val(Wn.v), 1.0 - gamma);
+  Val t2 = S.cconst(Val(W), gamma);
+  Val Vn = S.combine(std::move(t1), std::move(t2), false);
+  NagResult r;
+  r.W = owned(c, std::move(Wn));
+  r.V = owned(c, std::move(Vn));
+  return r;
 }
 
 std::vector<double> default_exp_coeffs(int degree, int B) {

@@ -18,7 +18,7 @@ Batch b_add_const(Context& c, BView a, double value);
 Batch b_add_plain(Context& c, BView a, const u64* pt);
 
 // Refresh by the key holder: called with a ciphertext (the library's buffer, room for the top level) that it must
-// replace, in place, by an encryption of the same message at the top level and the same scale.
+// replace, in place, by an encryption of the same message at the top level; the new scale is read back.
 struct Refresher {
   hetal_refresh_fn fn = nullptr;
   void* user = nullptr;
@@ -44,12 +44,24 @@ Batch softmax_approx(Context& c, const KeySet& k, MaskCache& mc, BView m, int cc
 
 std::vector<int> softmax_rot_steps(int cc, int s1);
 
+// One step of the encrypted training loop (NAG, Sec. 3): P = ASoftmax(X V^T) (DiagABT, then the softmax),
+// W' = V - lr (P - Y)^T X (DiagATB with t = -lr), V' = (1 - gamma) W' + gamma W.  X: n_rb x n_cb untiled blocks; Y:
+// n_rb one-hot blocks tiled horizontally; W, V: n_cb blocks tiled vertically.  X and V are refreshed below 3
+// levels, P - Y below 4.
+struct NagResult {
+  Batch W, V;
+};
+NagResult nag_step(Context& c, const KeySet& k, MaskCache& mc, BView X, int n_rb, int n_cb, BView Y, BView W,
+                   BView V, int cls, int s0, int s1, double lr, double gamma, const SoftmaxArgs& a, Refresher& rf);
+
 // Default AExp polynomial: the L^2 projection of e^t on [-1, 1] onto degree `degree`, as monomial coefficients of
 // p(x / B).
 std::vector<double> default_exp_coeffs(int degree, int B);
 
 // Client-side refresh: decrypt, lift the plaintext from q_0 (centred; E_OVERFLOW when another limb disagrees),
-// re-encrypt at the top level with the caller's randomness (a_ntt, e_ntt: NTT form over q_0..q_{num_q-1}).
-void refresh_encrypt(Context& c, const u64* s, CtView ct, const u64* a_ntt, const u64* e_ntt, u64* out);
+// re-encode it at `scale` (rint(m * scale / ct.scale); scale <= 0 keeps it), re-encrypt at the top level with the
+// caller's randomness (a_ntt, e_ntt: NTT form over q_0..q_{num_q-1}).
+void refresh_encrypt(Context& c, const u64* s, CtView ct, double scale, const u64* a_ntt, const u64* e_ntt,
+                     u64* out);
 
 }  // namespace hetal

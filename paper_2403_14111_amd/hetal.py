@@ -115,12 +115,15 @@ _SIGS = {
     "hetal_cmult_const": (ctypes.c_int, [_vp, _ctp, ctypes.c_double, ctypes.c_double, _ctp]),
     "hetal_add_const": (ctypes.c_int, [_vp, _ctp, ctypes.c_double, _ctp]),
     "hetal_add_plain": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
-    "hetal_refresh": (ctypes.c_int, [_vp, _vp, _ctp, _u64p, _i64p, _ctp]),
+    "hetal_refresh": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_double, _u64p, _i64p, _ctp]),
     "hetal_poly_eval": (ctypes.c_int, [_vp, _vp, _ctp, _dblp, ctypes.c_int, REFRESH_FN, _vp, _ctp]),
     "hetal_softmax_default_params": (ctypes.c_int, [ctypes.POINTER(SoftmaxParams)]),
     "hetal_softmax_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
     "hetal_softmax_approx": (ctypes.c_int, [_vp, _vp, _matp, ctypes.c_int, ctypes.POINTER(SoftmaxParams), REFRESH_FN,
                                             _vp, _matp, _intp]),
+    "hetal_nag_step": (ctypes.c_int, [_vp, _vp, _matp, _matp, _matp, _matp, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(SoftmaxParams), REFRESH_FN, _vp, _matp, _matp,
+                                      _intp]),
     "hetal_counters_get": (ctypes.c_int, [_vp, _i64p]),
     "hetal_counters_reset": (ctypes.c_int, [_vp]),
     "hetal_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -505,15 +508,18 @@ class Context:
     def add_plain(self, a, pt):
         return self._unary(_lib.hetal_add_plain, a, a.level, ctypes.byref(a._struct()), ctypes.byref(pt._struct()))
 
-    def refresh(self, sk, ct, a, e):
+    def refresh(self, sk, ct, a, e, scale=0.0):
+        """The key holder's re-encryption at the top level (scale 0 keeps the scale)."""
         a, ap = _u64(a)
         e, ep = _i64(e)
         assert a.shape == (self.num_q, self.n) and e.shape == (self.n,)
-        return self._unary(_lib.hetal_refresh, ct, self.max_level, sk._h, ctypes.byref(ct._struct()), ap, ep)
+        return self._unary(_lib.hetal_refresh, ct, self.max_level, sk._h, ctypes.byref(ct._struct()),
+                           float(scale), ap, ep)
 
-    def refresher(self, sk, randomness):
-        """A refresh callback for the deep pipelines: the key holder re-encrypts in place (hetal_refresh) with
-        randomness(i) -> (a, e) for the i-th call.  Keep the returned object alive while the pipeline runs."""
+    def refresher(self, sk, randomness, scale=2.0 ** 40):
+        """A refresh callback for the deep pipelines: the key holder re-encrypts in place (hetal_refresh) at
+        `scale`, with randomness(i) -> (a, e) for the i-th call.  Keep the returned object alive while the
+        pipeline runs."""
         count = [0]
 
         def cb(_user, ct_ptr):
@@ -522,7 +528,7 @@ class Context:
                 count[0] += 1
                 a, ap = _u64(a)
                 e, ep = _i64(e)
-                return _lib.hetal_refresh(self._h, sk._h, ct_ptr, ap, ep, ct_ptr)
+                return _lib.hetal_refresh(self._h, sk._h, ct_ptr, float(scale), ap, ep, ct_ptr)
             except Exception:  # the library turns a failed refresh into an error of the pipeline
                 return -1
         fn = REFRESH_FN(cb)
@@ -556,6 +562,22 @@ class Context:
                                          ctypes.byref(nref)))
         out._update(s)
         return out, nref.value
+
+    def nag_step(self, keys, x, y, w, v, c, lr, gamma, params=None, refresh=None):
+        """One NAG step of the encrypted training loop -> (W_{t+1}, V_{t+1}, number of refreshes)."""
+        p = softmax_default_params() if params is None else params
+        words = x.n_cb * self.ct_words(self.max_level)
+        wo = Matrix(self, words, x.s0, 0, 0.0)
+        vo = Matrix(self, words, x.s0, 0, 0.0)
+        sw, sv = wo._struct(), vo._struct()
+        nref = ctypes.c_int(0)
+        _check(_lib.hetal_nag_step(self._h, keys._h, ctypes.byref(x._struct()), ctypes.byref(y._struct()),
+                                   ctypes.byref(w._struct()), ctypes.byref(v._struct()), int(c), float(lr),
+                                   float(gamma), ctypes.byref(p), refresh if refresh is not None else REFRESH_FN(),
+                                   None, ctypes.byref(sw), ctypes.byref(sv), ctypes.byref(nref)))
+        wo._update(sw)
+        vo._update(sv)
+        return wo, vo, nref.value
 
     def required_rot_steps(self, op, c, s0):
         n = ctypes.c_int(0)

@@ -74,6 +74,10 @@ def test_refresh_bit_exact_and_overflow(deep):
     ro = ckks.refresh(ev.prm, ev.sk, o, a, e)
     assert r.level == ctx.max_level and r.scale == g.scale
     same(ctx.ct_to_coeff(r), ro)
+    r = ctx.refresh(sk, g, a, e, scale=2.0 ** 40)               # re-encoded at 2^40
+    ro = ckks.refresh(ev.prm, ev.sk, o, a, e, 2.0 ** 40)
+    assert r.scale == ro.scale == 2.0 ** 40
+    same(ctx.ct_to_coeff(r), ro)
     big = encrypt_slots_gpu(ctx, sk, np.full(ctx.slots, 2000.0), 3, seed=3300, index=2)
     from paper_2403_14111_amd import hetal
     with pytest.raises(hetal.HetalError) as ei:
@@ -161,6 +165,7 @@ def test_softmax_full_ring_bench_shape():
     note("full ring approx")
     gout, nref = ctx.softmax_approx(keys, gm, 10, refresh=gpu_refresher(ctx, sk, 2401))
     assert nref > 0
+    assert abs(np.log2(gout.scale) - 40.0) < 0.01          # refreshes re-encode at 2^40: no compounding drift
     res = ctx.mat_decrypt(sk, gout)
     prm = sm.SoftmaxParams()
     want = np.zeros((128, 16))

@@ -217,6 +217,15 @@ def test_refresh_keeps_the_message_and_scale():
     want = ckks.add(m_old, ckks.reduce_signed(e2, prm.q[:2], prm.log_n), prm.q[:2])
     assert np.array_equal(m_new[:2], want)
     assert np.abs(ckks.decode(prm, ckks.decrypt(prm, ev.sk, fresh)) - z).max() < 1e-6
+    # re-encoded at scale 2^40: the polynomial is round(m * 2^40 / scale), plus the fresh error
+    re = ckks.refresh(prm, ev.sk, ct, a2, e2, prm.scale)
+    assert re.scale == prm.scale and re.level == prm.max_level
+    m0 = np.array([v - prm.q[0] if v > prm.q[0] // 2 else v for v in m_old[0].tolist()], dtype=np.int64)
+    m1 = np.rint(m0 * (prm.scale / ct.scale)).astype(np.int64)
+    want = ckks.add(ckks.reduce_signed(m1, prm.q[:2], prm.log_n), ckks.reduce_signed(e2, prm.q[:2], prm.log_n),
+                    prm.q[:2])
+    assert np.array_equal(ckks.decrypt(prm, ev.sk, re).m[:2], want)
+    assert np.abs(ckks.decode(prm, ckks.decrypt(prm, ev.sk, re)) - z).max() < 1e-6
 
 
 def test_encrypted_constant_operations():
@@ -240,7 +249,7 @@ def refresher(ev, seed):
     def refresh(ct):
         a, e = inputs.refresh_randomness(seed, count[0], ev.prm.q, ev.prm.n)
         count[0] += 1
-        return ckks.refresh(ev.prm, ev.sk, ct, a, e)
+        return ckks.refresh(ev.prm, ev.sk, ct, a, e, ev.prm.scale)
     return refresh
 
 
