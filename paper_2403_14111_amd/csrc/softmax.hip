@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <set>
 
 #include "matrix.hpp"
@@ -199,15 +200,17 @@ namespace {
 // Ciphertexts of one step: either the caller's (a view) or owned here.
 struct Val {
   Batch own;
+  std::shared_ptr<Batch> shared;  // a part of a batch several values were computed in
   BView v;
   Val() : v{nullptr, -1, 0, 0.0, 0} {}
   explicit Val(BView x) : v(x) {}
   explicit Val(Batch&& b) : own(std::move(b)) { v = own.v(); }
-  Val(Val&& o) noexcept : own(std::move(o.own)), v(o.v) {
+  Val(Val&& o) noexcept : own(std::move(o.own)), shared(std::move(o.shared)), v(o.v) {
     if (own.d) v = own.v();
   }
   Val& operator=(Val&& o) noexcept {
     own = std::move(o.own);
+    shared = std::move(o.shared);
     v = o.v;
     if (own.d) v = own.v();
     return *this;
@@ -311,6 +314,44 @@ struct Steps {
     return Val(b_rescale(c, p.v()));
   }
 
+  // Independent products as one lockstep Mult + rescale: every item goes through the operations it would get
+  // alone, and each result gets the scale a single product would ((s_a s_b) / q).  Only when no operand needs a
+  // refresh and all pairs land on one level (else false, nothing done), so the refresh order is unchanged.
+  bool mult_group(const std::vector<std::pair<BView, BView>>& ops, std::vector<Val>& out) {
+    int lv = -1;
+    for (const auto& op : ops) {
+      if (op.first.level < 1 || op.second.level < 1) return false;
+      const int l = std::min(op.first.level, op.second.level);
+      if (lv >= 0 && l != lv) return false;
+      lv = l;
+    }
+    std::vector<Val> held;
+    held.reserve(2 * ops.size());
+    std::vector<CtView> va, vb;
+    for (const auto& op : ops) {
+      held.push_back(drop(Val(op.first), lv));
+      held.push_back(drop(Val(op.second), lv));
+      const BView a = held[held.size() - 2].v, b = held.back().v;
+      for (int i = 0; i < a.count; ++i) {
+        va.push_back(a.item(i));
+        vb.push_back(b.item(i));
+      }
+    }
+    Batch p = b_hmult(c, k, va, vb);
+    auto r = std::make_shared<Batch>(b_rescale(c, p.v()));
+    const size_t w = c.ct_words(lv - 1);
+    size_t off = 0;
+    out.clear();
+    for (const auto& op : ops) {
+      Val x;
+      x.shared = r;
+      x.v = BView{r->d + off * w, lv - 1, op.first.count, op.first.scale * op.second.scale / (double)c.primes[lv], w};
+      off += op.first.count;
+      out.push_back(std::move(x));
+    }
+    return true;
+  }
+
   Val combine(Val a, Val b, bool subtract) {
     const double sa = a.scale(), sb = b.scale();
     if (std::abs(sa - sb) > 1e-9 * std::max(std::abs(sa), std::abs(sb))) {
@@ -347,11 +388,26 @@ struct Steps {
     }
     std::map<int, Val> pw;
     pw[1] = std::move(x);
-    for (int kk : needed) {
-      if (kk == 1) continue;
-      const int a = split_hi(kk), b = kk - a;
-      // the factors stay in the table: the product works on views of them
-      pw[kk] = mult(Val(pw[a].v), Val(pw[b].v), a == b);
+    // the powers of one depth are independent: one batched product per depth (the factors stay in the table)
+    int maxd = 0;
+    for (int kk : needed) maxd = std::max(maxd, power_depth(kk));
+    for (int d = 1; d <= maxd; ++d) {
+      std::vector<int> kd;
+      std::vector<std::pair<BView, BView>> ops;
+      for (int kk : needed)
+        if (kk > 1 && power_depth(kk) == d) {
+          kd.push_back(kk);
+          ops.push_back({pw[split_hi(kk)].v, pw[kk - split_hi(kk)].v});
+        }
+      std::vector<Val> res;
+      if (mult_group(ops, res)) {
+        for (size_t i = 0; i < kd.size(); ++i) pw[kd[i]] = std::move(res[i]);
+      } else {
+        for (int kk : kd) {
+          const int a = split_hi(kk), b = kk - a;
+          pw[kk] = mult(Val(pw[a].v), Val(pw[b].v), a == b);
+        }
+      }
     }
     int lt = 1 << 30;
     for (int kk : ks) lt = std::min(lt, pw[kk].level() - 1);
@@ -451,8 +507,15 @@ Batch softmax_approx(Context& c, const KeySet& k, MaskCache& mc, BView m, int cc
     for (int t = 0; t < a.comp_g; ++t) y = S.poly(std::move(y), g_coeffs());
     Val comp = S.poly(std::move(y), comp_out_coeffs());
     Val onem = S.add_const(S.mulint(comp, -1), 1.0);
-    Val t1 = S.mult(Val(mmax.v), Val(comp.v), false);
-    Val t2 = S.mult(Val(mrot.v), Val(onem.v), false);
+    Val t1, t2;
+    std::vector<Val> both;
+    if (S.mult_group({{mmax.v, comp.v}, {mrot.v, onem.v}}, both)) {
+      t1 = std::move(both[0]);
+      t2 = std::move(both[1]);
+    } else {
+      t1 = S.mult(Val(mmax.v), Val(comp.v), false);
+      t2 = S.mult(Val(mrot.v), Val(onem.v), false);
+    }
     mmax = S.combine(std::move(t1), std::move(t2), false);
   }
   mmax = S.mask(std::move(mmax), MASK_FIRST_COL, 0);
@@ -476,9 +539,19 @@ Batch softmax_approx(Context& c, const KeySet& k, MaskCache& mc, BView m, int cc
   Val y = S.cconst(std::move(s), 1.0 / a.inv_R);
   Val bq = S.add_const(S.mulint(y, -1), 1.0);
   Val av = S.add_const(bq, 1.0);
+  // b <- b^2, a <- a (1 + b), pipelined: a's product of one step runs with the next step's square (both read the
+  // same b) as one batch whenever neither needs a refresh; otherwise in the order written.
+  if (a.inv_iters > 0) bq = S.mult(Val(bq.v), Val(bq.v), true);
   for (int t = 0; t < a.inv_iters; ++t) {
-    bq = S.mult(Val(bq.v), Val(bq.v), true);
-    av = S.mult(Val(av.v), S.add_const(bq, 1.0), false);
+    Val onep = S.add_const(bq, 1.0);
+    std::vector<Val> both;
+    if (t + 1 < a.inv_iters && S.mult_group({{av.v, onep.v}, {bq.v, bq.v}}, both)) {
+      av = std::move(both[0]);
+      bq = std::move(both[1]);
+    } else {
+      av = S.mult(Val(av.v), std::move(onep), false);
+      if (t + 1 < a.inv_iters) bq = S.mult(Val(bq.v), Val(bq.v), true);
+    }
   }
   Val z = S.cconst(std::move(av), 1.0 / a.inv_R);
   Val sm = S.mult(Val(e.v), Val(z.v), false);
