@@ -571,14 +571,18 @@ def nag_gamma(t):
     return (1.0 - lam) / ((1.0 + np.sqrt(1.0 + 4.0 * lam * lam)) / 2.0)
 
 
-def train_bench(steps):
+def train_bench(steps, rows=A_ROWS, classes=CLASSES):
     """Consecutive encrypted training steps (the protocol's step 3(a): NAG with P = ASoftmax(X V^T), Sec. 3) on
-    one mini-batch of the benchmark shape: X 128 x 769 (768 features and the bias column), 10 classes (c' = 16),
-    s0 = 128, N = 2^16, inputs encrypted at level 11, learning rate 1 over the batch size.  Refreshes by the key
-    holder are timed apart.  The decrypted weights are checked against the same steps in FP64 with the exact
-    softmax.  One JSON line."""
+    one mini-batch: X rows x 769 (768 features and the bias column), `classes` classes padded to c' (a power of
+    two), s0 = rows (one block row), N = 2^16, inputs encrypted at level 11, learning rate 1 over the batch size.
+    Refreshes by the key holder are timed apart.  The decrypted weights are checked against the same steps in
+    FP64 with the exact softmax.  One JSON line."""
     import torch
     from paper_2403_14111_amd import hetal, inputs
+    A_ROWS, CLASSES, S0 = rows, classes, rows
+    C_PAD = 1
+    while C_PAD < CLASSES:
+        C_PAD *= 2
     ctx = hetal.Context("n16l12")
     sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
     keys = ctx.keys_create()
@@ -643,8 +647,8 @@ def train_bench(steps):
         "refreshes_per_step": nrefs, "steps": steps,
         "max_abs_err_W_vs_fp64": float(np.abs(got - Wp).max()),
         "cross_entropy": {"start": round(ce(W0), 5), "encrypted": round(ce(got), 5), "fp64": round(ce(Wp), 5)},
-        "shape": "X 128 x 769 (bias column), 10 classes -> c'=16, s0=128, s1=256, N=2^16, inputs at level 11",
-        "lr": lr}}), flush=True)
+        "shape": "X %d x 769 (bias column), %d classes -> c'=%d, s0=%d, s1=%d, N=2^16, inputs at level 11"
+                 % (A_ROWS, CLASSES, C_PAD, S0, ctx.slots // S0), "lr": lr}}), flush=True)
 
 
 def cpu_baseline(X, W, gpu_abt_coeffs):
@@ -714,6 +718,8 @@ def main():
                     help="time the softmax approximation (App. softmax) at the forward product's shape, REPS runs")
     ap.add_argument("--train-step", type=int, default=0, metavar="STEPS",
                     help="time STEPS consecutive encrypted NAG training steps (softmax included)")
+    ap.add_argument("--train-shape", default="128x10", metavar="ROWSxCLASSES",
+                    help="mini-batch rows and classes of --train-step (features 768 + bias), e.g. 256x100")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the benchmark: DiagABT / DiagATB (both branches) at the paper's Table 4 shapes, "
                          "one JSON line per shape (median of --steps calls)")
@@ -742,7 +748,8 @@ def main():
         softmax_bench(args.softmax)
         return
     if args.train_step:
-        train_bench(args.train_step)
+        rows, classes = (int(v) for v in args.train_shape.split("x"))
+        train_bench(args.train_step, rows, classes)
         return
     if args.serve:
         serve_bench(args.clients, args.serve, args.rate, args.budget_gib)
