@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,12 @@ using namespace hetal;
 struct hetal_ctx {
   Context c;
   MaskCache masks;
+  // A second stream for independent groups of hetal_enc_matmul_batch, sharing c's tables (created on first use;
+  // side_masks is declared after side so that it returns its buffers to side's pool before side goes).
+  std::unique_ptr<Context> side;
+  MaskCache side_masks;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t join[2] = {nullptr, nullptr};
 };
 
 struct hetal_sk {
@@ -120,6 +127,15 @@ int hetal_ctx_create(const hetal_params* params, void* stream, hetal_ctx** out) 
 void hetal_ctx_destroy(hetal_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->c.stream);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side_stream);
+    for (auto& kv : ctx->side_masks.pts) ctx->side->pool.put(kv.second);
+    ctx->side_masks.pts.clear();
+    context_free(*ctx->side);
+    ctx->side.reset();
+    (void)hipStreamDestroy(ctx->side_stream);
+    for (hipEvent_t e : ctx->join) (void)hipEventDestroy(e);
+  }
   for (auto& kv : ctx->masks.pts) ctx->c.pool.put(kv.second);
   ctx->masks.pts.clear();
   for (auto& t : ctx->c.timed) {
@@ -808,6 +824,38 @@ int hetal_enc_matmul_atb(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
   });
 }
 
+// The second stream of a context (see hetal_ctx), created on first use.
+static Context& side_context(hetal_ctx* ctx) {
+  if (!ctx->side) {
+    HCHECK(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking));
+    HCHECK(hipEventCreateWithFlags(&ctx->join[0], hipEventDisableTiming));
+    HCHECK(hipEventCreateWithFlags(&ctx->join[1], hipEventDisableTiming));
+    std::unique_ptr<Context> s(new Context());
+    context_share(*s, ctx->c, ctx->side_stream);
+    ctx->side = std::move(s);
+  }
+  return *ctx->side;
+}
+
+// While alive: the side stream starts after the work queued so far on the main stream, and (at the end, also
+// when an error unwinds) the main stream waits for everything queued on the side stream; the side counters are
+// folded into the main ones.
+struct SideJoin {
+  hetal_ctx* ctx;
+  SideJoin(hetal_ctx* x) : ctx(x) {
+    HCHECK(hipEventRecord(ctx->join[0], ctx->c.stream));
+    HCHECK(hipStreamWaitEvent(ctx->side_stream, ctx->join[0], 0));
+  }
+  ~SideJoin() {
+    (void)hipEventRecord(ctx->join[1], ctx->side_stream);
+    (void)hipStreamWaitEvent(ctx->c.stream, ctx->join[1], 0);
+    for (int i = 0; i < 8; ++i) {
+      ctx->c.counters[i] += ctx->side->counters[i];
+      ctx->side->counters[i] = 0;
+    }
+  }
+};
+
 int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
                            hetal_mat* outs) {
   return guarded([&] {
@@ -843,7 +891,19 @@ int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_m
       }
       groups[std::make_tuple(r.op, r.c, r.a->s0, lv_a, lv_b, r.a->scale, r.b->scale)].push_back(i);
     }
+    // Independent groups alternate between the main stream and a second one, so that one group's small
+    // launches overlap the other's (unless per-kernel timing is on, which wants kernels one at a time).
+    const bool two = groups.size() >= 2 && !c.timing;
+    std::unique_ptr<SideJoin> joined;
+    if (two) {
+      side_context(ctx);
+      joined.reset(new SideJoin(ctx));
+    }
+    int gi = 0;
     for (auto& kv : groups) {
+      const bool on_side = two && (gi++ % 2 == 1);
+      Context& cx = on_side ? *ctx->side : c;
+      MaskCache& mcx = on_side ? ctx->side_masks : ctx->masks;
       const int op = std::get<0>(kv.first), cc = std::get<1>(kv.first), s0 = std::get<2>(kv.first);
       const int s1 = c.slots / s0;
       const std::vector<int>& idx = kv.second;
@@ -859,7 +919,7 @@ int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_m
           q.t = r.t;
           rq.push_back(std::move(q));
         }
-        res = diag_abt_multi(c, keys->set, ctx->masks, rq, cc, s0, s1);
+        res = diag_abt_multi(cx, keys->set, mcx, rq, cc, s0, s1);
       } else {
         std::vector<AtbRequest> rq;
         for (int i : idx) {
@@ -871,16 +931,17 @@ int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_m
           q.t = r.t;
           rq.push_back(std::move(q));
         }
-        res = diag_atb_multi(c, keys->set, ctx->masks, rq, cc, s0, s1);
+        res = diag_atb_multi(cx, keys->set, mcx, rq, cc, s0, s1);
       }
       // request i's blocks follow the earlier requests' in the result
       int first = 0;
-      const size_t w = c.ct_words(res.level);
+      const size_t w = cx.ct_words(res.level);
       for (int i : idx) {
         const hetal_matmul_req& r = reqs[i];
         const int nb = op == 0 ? r.a->n_rb : r.b->n_cb;
         hetal_mat* o = &outs[i];
-        HCHECK(hipMemcpyAsync(o->data, res.d + (size_t)first * w, (size_t)nb * w * 8, hipMemcpyDeviceToDevice, c.stream));
+        HCHECK(hipMemcpyAsync(o->data, res.d + (size_t)first * w, (size_t)nb * w * 8, hipMemcpyDeviceToDevice,
+                              cx.stream));
         o->n_rb = op == 0 ? nb : 1;
         o->n_cb = op == 0 ? 1 : nb;
         o->s0 = s0;

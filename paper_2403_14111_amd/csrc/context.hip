@@ -356,9 +356,43 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
   HCHECK(hipStreamSynchronize(stream));
 }
 
+void context_share(Context& d, const Context& s, hipStream_t stream) {
+  d.log_n = s.log_n;
+  d.n = s.n;
+  d.slots = s.slots;
+  d.num_q = s.num_q;
+  d.num_p = s.num_p;
+  d.dnum = s.dnum;
+  d.alpha = s.alpha;
+  d.nprimes = s.nprimes;
+  d.primes = s.primes;
+  d.stream = stream;
+  d.d_mod = s.d_mod;
+  d.d_tw_fwd = s.d_tw_fwd;
+  d.d_tw_inv = s.d_tw_inv;
+  d.d_pc = s.d_pc;
+  d.d_modup = s.d_modup;
+  d.d_moddown = s.d_moddown;
+  d.d_modup_scale = s.d_modup_scale;
+  d.d_moddown_scale = s.d_moddown_scale;
+  d.d_rescale = s.d_rescale;
+  d.d_roots = s.d_roots;
+  d.d_pow5 = s.d_pow5;
+  d.d_rows = s.d_rows;
+  for (int t = 0; t < NUM_ROW_TABLES; ++t) {
+    d.row_off[t] = s.row_off[t];
+    d.row_cnt[t] = s.row_cnt[t];
+  }
+  d.h_modup = s.h_modup;
+  d.h_moddown = s.h_moddown;
+  d.h_pc = s.h_pc;
+  d.owns_tables = false;
+}
+
 void context_free(Context& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   else (void)hipDeviceSynchronize();
+  if (!c.owns_tables) return;
   void* ptrs[] = {c.d_mod,     c.d_tw_fwd, c.d_tw_inv, c.d_pc,   c.d_modup,         c.d_moddown,
                   c.d_rescale, c.d_roots,  c.d_pow5,   c.d_rows, c.d_modup_scale, c.d_moddown_scale};
   for (void* p : ptrs)

@@ -181,6 +181,7 @@ struct Context {
   std::vector<ModUpTab> h_modup;
   ModDownTab h_moddown;
   std::vector<PrimeConsts> h_pc;
+  bool owns_tables = true;  // false for a context sharing another's device tables (context_share)
 
   Pool pool;
   int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -225,6 +226,9 @@ struct Context {
 
 void context_init(Context& c, const hetal_params& p, hipStream_t stream);
 void context_free(Context& c);
+// A second context on `stream` using src's parameters and device tables (not copied, not freed by it), with a pool,
+// counters and timing of its own: work on two streams at once.
+void context_share(Context& dst, const Context& src, hipStream_t stream);
 
 // ---------------------------------------------------------------- kernels
 // Optional separate input of a transform: row r of item b is read from
