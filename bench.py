@@ -198,6 +198,8 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
              ] + (["    python bench.py --steps %d --warmup 2 --no-cpu-baseline > BENCH.json" % steps] if bench else []) + [
              "    python bench.py --trace-summary DIR --steps %d --pmc-steps %d%s" % (
                  steps, pmc_steps, " --bench-json BENCH.json" if bench else ""), "",
+             "The profiled runs (--profile) issue the two products as single calls on one stream, so that every "
+             "step repeats kernel for kernel; the benchmark itself runs them on two streams (the line at the end).  "
              "Timed region: the last %d steps of the trace (%d kernels per step).  HBM MB/launch: FETCH_SIZE and "
              "WRITE_SIZE (KiB per dispatch) scaled by what they read for the closing plain copy, averaged over the "
              "class's launches in the counter runs' timed steps.  HBM frac: those bytes per launch over the average "
