@@ -681,15 +681,30 @@ def cpu_baseline(X, W, gpu_abt_coeffs):
 
     xb = enc(mx.block_encode(X, S0, s1)[0], 0)
     wb = enc(mx.block_encode(mx.tile_vertical(Wp, S0), S0, s1)[0], 100)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = ckks.LIB.orc_max_threads()
     t0 = time.perf_counter()
     out = mx.diag_abt(ev, [xb], wb, C_PAD, S0, s1, 1.0)
     dt = time.perf_counter() - t0
     same = gpu_abt_coeffs is not None and np.array_equal(gpu_abt_coeffs, out[0].c)
+    # one rotation at level 11, on all threads and on one
+    hrot = {}
+    for n in (threads, 1):
+        ckks.LIB.orc_set_threads(n)
+        t1 = time.perf_counter()
+        ev.rot(xb[0], 1)
+        hrot[n] = time.perf_counter() - t1
+    ckks.LIB.orc_set_threads(threads)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=1.0 / dt, unit="matmuls/s", cores=threads, kind="oracle",
                 sample="one full DiagABT of the forward product (128x768x16, N=2^16, level 11): %.1f s on %d "
                        "OpenMP threads" % (dt, threads),
-                seconds=dt), same
+                seconds=dt, cpu_model=model, nproc=os.cpu_count(),
+                hrot_level11_s={"threads_%d" % threads: round(hrot[threads], 3), "one_thread": round(hrot[1], 3)}), same
 
 
 def main():

@@ -53,6 +53,8 @@ def _load():
         "orc_encode": (ctypes.c_int, [_dblp, _dblp, ctypes.c_int, ctypes.c_double, _i64p]),
         "orc_reduce_signed": (None, [_i64p, _u64p, ctypes.c_int, ctypes.c_int, _u64p]),
         "orc_crt_centered": (None, [_u64p, ctypes.c_int, ctypes.c_int, _u64p, _dblp]),
+        "orc_set_threads": (None, [ctypes.c_int]),
+        "orc_max_threads": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -26,6 +26,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 typedef uint64_t u64;
 typedef int64_t i64;
@@ -569,3 +570,7 @@ void orc_crt_centered(const u64* limbs, int count, int log_n, const u64* qs, dou
         else out[k] = (double)x;
     }
 }
+
+/* Thread count of the parallel loops above (timing only; results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
