@@ -377,6 +377,30 @@ def test_matmul_batch_equals_single_calls(toy_mm):
     assert ei.value.name == "E_SHAPE"
 
 
+def test_matmul_batch_error_on_the_second_stream_leaves_the_context_usable():
+    """A batch whose DiagATB group (run on the second stream) misses a Galois key fails with E_NO_KEY part way;
+    the streams are joined all the same, and the next batch on the same context is word for word the single
+    calls'."""
+    from paper_2403_14111_amd import hetal
+    s0, s1, c = 16, 128, 8
+    note("matmul batch error on the second stream")
+    ctx, sk, keys = make_gpu("toy", seed=2002, rot_steps=sorted(mx.rotation_steps("abt", c, s0, s1)))
+
+    def enc(mat, tiling, seed):
+        return enc_mat_gpu(ctx, sk, mat, s0, 4, tiling, c, seed)[0]
+    A = inputs.toy_matrix(6200, 16, 32, 0)
+    B = inputs.toy_matrix(6200, 8, 32, 1)
+    P = inputs.toy_matrix(6201, 16, 8, 0)
+    ga, gb, gp = enc(A, 0, 61), enc(B, 1, 62), enc(P, 2, 63)
+    with pytest.raises(hetal.HetalError) as ei:
+        ctx.enc_matmul_batch(keys, [("abt", ga, gb, c, 1.0), ("atb", gp, ga, c, 1.0)])
+    assert ei.value.name == "E_NO_KEY"
+    outs = ctx.enc_matmul_batch(keys, [("abt", ga, gb, c, 1.0), ("abt", ga, gb, 4, 0.5)])
+    for (cc, t), out in zip(((c, 1.0), (4, 0.5)), outs):
+        single = ctx.enc_matmul_abt(keys, ga, gb, cc, t)
+        assert np.array_equal(ctx.ct_to_coeff(ctx.mat_block(out, 0)), ctx.ct_to_coeff(ctx.mat_block(single, 0)))
+
+
 def test_matmul_shape_and_level_errors(toy_mm):
     from paper_2403_14111_amd import hetal
     ctx, sk, keys, ev = toy_mm
