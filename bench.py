@@ -14,7 +14,7 @@ Inputs are seeded synthetic data with the shapes of the paper's ViT / MPNet
 768-dimensional features; keys, masks and ciphertexts are resident in HBM
 before the timed region.  One step = one DiagABT + one DiagATB.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -746,7 +746,7 @@ def main():
         print(trace_summary(args.trace_summary, args.steps, args.pmc_steps, args.bench_json))
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
