@@ -714,6 +714,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--hrot-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (e.g. under a profiler)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the step as a HIP graph recorded once (hetal_enc_matmul_batch_graph)")
     ap.add_argument("--profile", action="store_true",
                     help="profiler run: warmup + timed steps + one plain copy of 256 MiB (counter calibration); "
                          "no event-timing pass, HRot loop or oracle leg")
@@ -772,6 +774,8 @@ def main():
         serve_bench(args.clients, args.serve, args.rate, args.budget_gib)
         return
     log("context + keys")
+    if args.graph:
+        torch.cuda.set_stream(torch.cuda.Stream())   # graph capture needs a created stream
     ctx = hetal.Context("n16l12")
     sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
     t0 = time.perf_counter()
@@ -779,14 +783,25 @@ def main():
     log("%d keys in %.1f s" % (nkeys, time.perf_counter() - t0))
     X, W, PY = workload()
     gx, gw, gpy = encrypt_inputs(ctx, sk, X, W, PY)
+    reqs = [("abt", gx, gw, C_PAD, 1.0), ("atb", gpy, gx, C_PAD, 1.0)]
+    graph = None
+    if args.graph:
+        log("recording the step into a HIP graph")
+        graph_outs, graph = ctx.enc_matmul_batch_graph(keys, reqs)
 
-    def step():
+    def eager_step():
         # one batched call: the two products are independent, and the library runs them on two streams (under a
         # profiler the single calls, one stream, so that the trace repeats kernel for kernel)
         if args.profile:
             return ctx.enc_matmul_abt(keys, gx, gw, C_PAD, 1.0), ctx.enc_matmul_atb(keys, gpy, gx, C_PAD, 1.0)
-        y, g = ctx.enc_matmul_batch(keys, [("abt", gx, gw, C_PAD, 1.0), ("atb", gpy, gx, C_PAD, 1.0)])
+        y, g = ctx.enc_matmul_batch(keys, reqs)
         return y, g
+
+    def step():
+        if graph is not None:
+            graph.launch()
+            return graph_outs[0], graph_outs[1]
+        return eager_step()
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
@@ -835,19 +850,19 @@ def main():
     # with timing on the library runs the products one at a time on one stream (events per kernel); one untimed
     # step of that path first encodes the masks its context has not cached yet
     ctx.timing_enable(True)
-    step()
+    eager_step()
     ctx.timing_enable(True)
     torch.cuda.synchronize()
     t_ev = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        eager_step()
     torch.cuda.synchronize()
     elapsed_ev = time.perf_counter() - t_ev
     kt = ctx.timing_get()
     ctx.timing_enable(False)
     counters_step = None
     ctx.reset_counters()
-    step()
+    eager_step()
     torch.cuda.synchronize()
     counters_step = ctx.counters()
     dom = max(kt, key=lambda k: kt[k]["ms"])
@@ -916,6 +931,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {
+            "execution": "HIP graph replay" if args.graph else "batched call, two streams",
             "workload": "DiagABT <X W^T> (X 128x768, W 10x768 -> c=16) + DiagATB <(P-Y)^T X> (128x10 -> 16), "
                         "one step = both products",
             "ring": "N=2^16, 12 ciphertext primes (50+11x40 bits) + 3 special primes, dnum=4, scale 2^40",

@@ -242,6 +242,20 @@ typedef struct {
 int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
                            hetal_mat* outs);
 
+/* The products of hetal_enc_matmul_batch recorded into a HIP graph, for callers that repeat the same batch (a
+ * training loop over fixed buffers, a serving loop): the call runs the batch twice eagerly (encoding the masks
+ * and sizing the library's buffer pools), then records the same work, both streams included, into a graph and
+ * returns it; hetal_graph_launch replays it on the context's stream, reading the requests' input matrices and
+ * writing `outs` again (their contents at launch time are what is used).  The graph keeps pointers to the
+ * inputs, outputs and library buffers: keep all of them alive and unmoved, and the keys unchanged, until
+ * hetal_graph_destroy.  The context must be on a stream it was given (not the legacy default stream; E_INVALID_ARG)
+ * and per-kernel timing off.  Errors as hetal_enc_matmul_batch; E_DEVICE if the capture fails. */
+typedef struct hetal_graph hetal_graph;
+int hetal_enc_matmul_batch_graph(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                                 hetal_mat* outs, hetal_graph** out);
+int hetal_graph_launch(hetal_graph* g);
+void hetal_graph_destroy(hetal_graph* g);
+
 /* Rotation steps (signed, left positive) the algorithms need, for key
  * generation: op 0 = DiagABT, 1 = DiagATB (RotLeft branch), 2 = DiagATB
  * (PRotUp branch).  *n: in, capacity of out; out, count written. */

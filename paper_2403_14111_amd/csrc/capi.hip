@@ -856,9 +856,9 @@ struct SideJoin {
   }
 };
 
-int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
-                           hetal_mat* outs) {
-  return guarded([&] {
+static void matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                         hetal_mat* outs) {
+  {
     need(ctx && keys && reqs && outs && count >= 0, HETAL_E_INVALID_ARG, "null argument");
     Context& c = ctx->c;
     // validate everything first; then group by what makes the algorithm's step sequence identical
@@ -951,7 +951,62 @@ int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_m
         first += nb;
       }
     }
+  }
+}
+
+int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                           hetal_mat* outs) {
+  return guarded([&] { matmul_batch(ctx, keys, reqs, count, outs); });
+}
+
+struct hetal_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hetal_ctx* ctx = nullptr;
+};
+
+int hetal_enc_matmul_batch_graph(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                                 hetal_mat* outs, hetal_graph** out) {
+  return guarded([&] {
+    need(ctx && out, HETAL_E_INVALID_ARG, "null argument");
+    need(ctx->c.stream != nullptr, HETAL_E_INVALID_ARG, "graph capture needs the context on a created stream");
+    need(!ctx->c.timing, HETAL_E_INVALID_ARG, "per-kernel timing is on");
+    // two eager runs: the first encodes the masks (each keeps a pool buffer), the second leaves the pools
+    // holding the buffers of every size the recorded run asks for (no allocation is allowed while recording)
+    matmul_batch(ctx, keys, reqs, count, outs);
+    matmul_batch(ctx, keys, reqs, count, outs);
+    HCHECK(hipStreamSynchronize(ctx->c.stream));
+    if (ctx->side) HCHECK(hipStreamSynchronize(ctx->side_stream));
+    std::unique_ptr<hetal_graph> g(new hetal_graph());
+    g->ctx = ctx;
+    HCHECK(hipStreamBeginCapture(ctx->c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      matmul_batch(ctx, keys, reqs, count, outs);
+    } catch (...) {
+      hipGraph_t partial = nullptr;
+      (void)hipStreamEndCapture(ctx->c.stream, &partial);
+      if (partial) (void)hipGraphDestroy(partial);
+      throw;
+    }
+    HCHECK(hipStreamEndCapture(ctx->c.stream, &g->graph));
+    HCHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    *out = g.release();
   });
+}
+
+int hetal_graph_launch(hetal_graph* g) {
+  return guarded([&] {
+    need(g && g->exec && g->ctx, HETAL_E_INVALID_ARG, "null graph");
+    HCHECK(hipGraphLaunch(g->exec, g->ctx->c.stream));
+  });
+}
+
+void hetal_graph_destroy(hetal_graph* g) {
+  if (!g) return;
+  if (g->ctx) (void)hipStreamSynchronize(g->ctx->c.stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 int hetal_required_rot_steps(const hetal_ctx* ctx, int op, int cc, int s0, int32_t* out, int* n) {

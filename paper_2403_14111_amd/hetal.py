@@ -112,6 +112,10 @@ _SIGS = {
     "hetal_enc_matmul_atb": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
     "hetal_enc_matmul_batch": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp]),
     "hetal_required_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
+    "hetal_enc_matmul_batch_graph": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp,
+                                                    ctypes.POINTER(_vp)]),
+    "hetal_graph_launch": (ctypes.c_int, [_vp]),
+    "hetal_graph_destroy": (None, [_vp]),
     "hetal_cmult_const": (ctypes.c_int, [_vp, _ctp, ctypes.c_double, ctypes.c_double, _ctp]),
     "hetal_add_const": (ctypes.c_int, [_vp, _ctp, ctypes.c_double, _ctp]),
     "hetal_add_plain": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
@@ -489,6 +493,31 @@ class Context:
             o._update(s)
         return outs
 
+    def enc_matmul_batch_graph(self, keys, reqs):
+        """enc_matmul_batch recorded into a HIP graph -> (outputs, graph); graph.launch() recomputes the outputs
+        from the inputs' current contents.  The inputs, outputs and keys must stay alive while the graph is."""
+        n = len(reqs)
+        outs, keep = [], []
+        arr = (_Req * max(n, 1))()
+        for i, (op, a, b, c, t) in enumerate(reqs):
+            if op not in ("abt", "atb"):
+                raise ValueError("op must be 'abt' or 'atb'")
+            sa, sb = a._struct(), b._struct()
+            keep += [sa, sb, a, b]
+            if op == "abt":
+                lv = min(a.level, b.level) - 3
+                out = Matrix(self, a.n_rb * self.ct_words(lv) if lv >= 0 else 1, a.s0, 0, 0.0)
+            else:
+                out = Matrix(self, b.n_cb * self.ct_words(max(a.level, b.level)), b.s0, 0, 0.0)
+            outs.append(out)
+            arr[i] = _Req(0 if op == "abt" else 1, ctypes.pointer(sa), ctypes.pointer(sb), int(c), float(t))
+        structs = (_Mat * max(n, 1))(*[o._struct() for o in outs])
+        h = _vp()
+        _check(_lib.hetal_enc_matmul_batch_graph(self._h, keys._h, arr, n, structs, ctypes.byref(h)))
+        for o, s in zip(outs, structs):
+            o._update(s)
+        return outs, Graph(self, h, keep + outs + [keys])
+
     def enc_matmul_atb(self, keys, abar, b, c, t=1.0):
         lvl = max(abar.level, b.level)
         out = Matrix(self, b.n_cb * self.ct_words(lvl), b.s0, 0, 0.0)
@@ -586,6 +615,21 @@ class Context:
         _check(_lib.hetal_required_rot_steps(self._h, int(op), int(c), int(s0), out.ctypes.data_as(_i32p),
                                              ctypes.byref(n)))
         return [int(x) for x in out[:n.value]]
+
+
+class Graph:
+    """A recorded batch of products (Context.enc_matmul_batch_graph); keeps what it reads and writes alive."""
+
+    def __init__(self, ctx, h, keep):
+        self.ctx, self._h, self._keep = ctx, h, keep
+
+    def launch(self):
+        _check(_lib.hetal_graph_launch(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.hetal_graph_destroy(self._h)
+            self._h = None
 
 
 class SecretKey:
