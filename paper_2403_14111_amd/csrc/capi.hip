@@ -979,15 +979,22 @@ int hetal_enc_matmul_batch_graph(hetal_ctx* ctx, const hetal_keys* keys, const h
     if (ctx->side) HCHECK(hipStreamSynchronize(ctx->side_stream));
     std::unique_ptr<hetal_graph> g(new hetal_graph());
     g->ctx = ctx;
+    auto recording = [&](bool on) {
+      ctx->c.pool.recording = on;
+      if (ctx->side) ctx->side->pool.recording = on;
+    };
     HCHECK(hipStreamBeginCapture(ctx->c.stream, hipStreamCaptureModeThreadLocal));
+    recording(true);
     try {
       matmul_batch(ctx, keys, reqs, count, outs);
     } catch (...) {
+      recording(false);
       hipGraph_t partial = nullptr;
       (void)hipStreamEndCapture(ctx->c.stream, &partial);
       if (partial) (void)hipGraphDestroy(partial);
       throw;
     }
+    recording(false);
     HCHECK(hipStreamEndCapture(ctx->c.stream, &g->graph));
     HCHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     *out = g.release();

@@ -102,6 +102,7 @@ u64* Pool::get(size_t words) {
     free_.erase(it);
     return p;
   }
+  if (recording) fail(HETAL_E_DEVICE, "a recorded graph needs a buffer size the pool does not hold");
   u64* p = nullptr;
   if (hipMalloc(&p, words * sizeof(u64)) != hipSuccess) {
     (void)hipGetLastError();

@@ -103,6 +103,7 @@ class Pool {
   void release_all();
   ~Pool();
   size_t bytes_held() const { return held_; }
+  bool recording = false;  // while work is recorded into a graph: no allocation (an error instead)
 
  private:
   std::multimap<size_t, u64*> free_;
