@@ -174,13 +174,13 @@ void refresh_encrypt(Context& c, const u64* s, CtView ct, double scale, const u6
   k_decrypt(c, ct.d, s, m, ct.level);
   RowsRef rows = c.rows(ROWS_CT, ct.level);
   ntt_inverse(c, m, 0, 1, RowsRef{rows.d, ct.level + 1});
+  const int rescale = scale > 0.0 ? 1 : 0;
+  const double ratio = rescale ? scale / ct.scale : 1.0;
+  if (rescale && !(std::fabs(ratio) < 1e12)) fail(HETAL_E_SCALE, "refresh scale ratio out of range");
   Tmp lifted(c.pool, c.poly_words(top));
   Tmp flag(c.pool, 1);
   HCHECK(hipMemsetAsync(flag.p, 0, 8, c.stream));
   c.begin_launch();
-  const int rescale = scale > 0.0 ? 1 : 0;
-  const double ratio = rescale ? scale / ct.scale : 1.0;
-  if (rescale && !(std::fabs(ratio) < 1e12)) fail(HETAL_E_SCALE, "refresh scale ratio out of range");
   hipLaunchKernelGGL(lift_q0_kernel, dim3((unsigned)(c.n / TPB)), dim3(TPB), 0, c.stream, m.p, ct.level, lifted.p,
                      top + 1, c.d_mod, c.log_n, ratio, rescale, reinterpret_cast<int*>(flag.p));
   c.end_launch(KC_ELEMWISE, 8.0 * c.n * (ct.level + 1 + top + 1));
