@@ -26,3 +26,14 @@ def encrypt_slots_gpu(ctx, sk, z, level, seed=3000, index=0, scale=None):
     pt = ctx.encode(z, level, 2.0 ** 40 if scale is None else scale)
     a, e = inputs.encryption_randomness(seed, index, ctx.q[:level + 1], ctx.n)
     return ctx.encrypt(sk, pt, a, e)
+
+
+def softmax_params_with(coeffs):
+    """The library's default softmax parameters with the AExp polynomial replaced by `coeffs`, so that both
+    implementations of a bit-exact comparison round the very same constants."""
+    from paper_2403_14111_amd import hetal
+    p = hetal.softmax_default_params()
+    for i in range(len(p.exp_coeffs)):
+        p.exp_coeffs[i] = coeffs[i] if i < len(coeffs) else 0.0
+    p.exp_degree = len(coeffs) - 1
+    return p

@@ -43,7 +43,7 @@ def test_binding_covers_every_symbol():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_softmax_default_parameters_match_the_oracle():
     """The library's own defaults (no GPU needed): the paper's parameters, and an AExp polynomial equal to
-    the oracle's L^2 projection to 1e-11 on [-8, 8] (the monomial coefficients themselves are
+    the stored L^2 projection (the one the parity tests pass to both sides) to 1e-11 on [-8, 8] (the monomial coefficients themselves are
     ill-conditioned in their top terms)."""
     import numpy as np
     from oracle import softmax as sm
@@ -54,6 +54,7 @@ def test_softmax_default_parameters_match_the_oracle():
         (ref.R, ref.L, ref.n, 1, 1, ref.comp_g, ref.exp_B, ref.exp_degree, ref.inv_R, ref.inv_iters)
     x = np.linspace(-8, 8, 2001)
     mine = np.polynomial.polynomial.polyval(x, np.array(p.exp_coeffs[:p.exp_degree + 1]))
-    theirs = np.polynomial.polynomial.polyval(x, np.array(sm.exp_coeffs()))
+    from tests.golden_data import aexp_coeffs
+    theirs = np.polynomial.polynomial.polyval(x, np.array(aexp_coeffs()))
     assert np.abs(mine / theirs - 1).max() < 1e-11
     assert all(v == 0.0 for v in p.exp_coeffs[p.exp_degree + 1:])

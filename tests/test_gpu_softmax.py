@@ -9,7 +9,8 @@ from oracle import ckks
 from oracle import matrix as mx
 from oracle import softmax as sm
 from paper_2403_14111_amd import inputs
-from tests.gpu_setup import encrypt_slots_gpu, make_gpu
+from tests.golden_data import aexp_coeffs
+from tests.gpu_setup import encrypt_slots_gpu, make_gpu, softmax_params_with
 from tests.oracle_setup import encrypt_slots, make_oracle
 from tests.test_gpu_parity import compare_blocks, enc_mat_both, same
 from tests.test_oracle_softmax import refresher as oracle_refresher
@@ -92,7 +93,7 @@ def test_poly_eval_bit_exact(deep, which, level):
     note("poly %s level %d" % (which, level))
     prm = sm.SoftmaxParams()
     coeffs = {"g": sm.g_coeffs(), "comp": sm.comp_out_coeffs(), "dep": sm.dep_coeffs(prm, 2),
-              "dep_inv": sm.dep_inv_coeffs(prm), "exp": sm.exp_coeffs()}[which]
+              "dep_inv": sm.dep_inv_coeffs(prm), "exp": aexp_coeffs()}[which]
     z = inputs.slot_values(33, ctx.slots, bound=0.9, complex_=False)
     g = encrypt_slots_gpu(ctx, sk, z, level, seed=3300, index=3)
     o = encrypt_slots(ev, z, level, seed=3300, index=3)
@@ -125,9 +126,10 @@ def test_softmax_bit_exact(deep, c):
     gm, oblocks = enc_mat_both(ctx, sk, ev, M, S0, 8, 2, cp, seed=90 + c)
     seed = SEED + 100 + c
     gr = gpu_refresher(ctx, sk, seed)
-    gout, nref = ctx.softmax_approx(keys, gm, c, refresh=gr)
+    exp_c = aexp_coeffs()
+    gout, nref = ctx.softmax_approx(keys, gm, c, params=softmax_params_with(exp_c), refresh=gr)
     prm = sm.SoftmaxParams()
-    oout, onref = sm.asoftmax_blocks(ev, [row[0] for row in oblocks], c, S0, S1, prm, sm.exp_coeffs(), ev.prm.q,
+    oout, onref = sm.asoftmax_blocks(ev, [row[0] for row in oblocks], c, S0, S1, prm, exp_c, ev.prm.q,
                                      ev.prm.max_level, oracle_refresher(ev, seed))
     assert nref == onref == gr.calls[0]
     assert gout.level == oout[0].level and gout.scale == oout[0].scale

@@ -9,7 +9,8 @@ from oracle import matrix as mx
 from oracle import softmax as sm
 from oracle import train as tr
 from paper_2403_14111_amd import inputs
-from tests.gpu_setup import make_gpu
+from tests.golden_data import aexp_coeffs
+from tests.gpu_setup import make_gpu, softmax_params_with
 from tests.oracle_setup import make_oracle
 from tests.test_gpu_parity import compare_blocks, enc_mat_both
 from tests.test_oracle_softmax import refresher as oracle_refresher
@@ -39,11 +40,12 @@ def test_nag_step_bit_exact():
     lr, gamma = 0.5 / 20, tr.nag_gamma(3)
     note("gpu step")
     gr = ctx.refresher(sk, lambda i: inputs.refresh_randomness(2501, i, ctx.q, ctx.n))
-    gW, gV, nref = ctx.nag_step(keys, gx, gy, gw, gv, c, lr, gamma, refresh=gr)
+    exp_c = aexp_coeffs()
+    gW, gV, nref = ctx.nag_step(keys, gx, gy, gw, gv, c, lr, gamma, params=softmax_params_with(exp_c), refresh=gr)
     note("oracle step")
     prm = sm.SoftmaxParams()
     oW, oV, onref = tr.nag_step_blocks(ev, ox, [r[0] for r in oy], ow[0], ov[0], c, s0, s1, lr, gamma, prm,
-                                       sm.exp_coeffs(), ev.prm.q, ev.prm.max_level, oracle_refresher(ev, 2501))
+                                       exp_c, ev.prm.q, ev.prm.max_level, oracle_refresher(ev, 2501))
     assert nref == onref == gr.calls[0]
     assert (gW.level, gV.level) == (oW[0].level, oV[0].level)
     compare_blocks(ctx, gW, oW)
