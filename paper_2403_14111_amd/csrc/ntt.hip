@@ -23,7 +23,9 @@
 //    (3 integer multiplies fewer, and no 64-bit register shuffles): it is at
 //    most 3 below the exact quotient, so T lies in [0, 4q).  Forward:
 //    X' = X + T, Y' = X + 4q - T; values stay below (1 + 4 log N) q < 2^57
-//    and one exact Shoup reduction by 1 finishes.  Inverse: values kept in
+//    (below (16 + 4 log N) q <= 80 q for the inputs of a fused conversion)
+//    and one exact Shoup reduction by 1 finishes, or the combine epilogue
+//    takes the lazy values.  Inverse: values kept in
 //    [0, 4q) by one conditional subtraction of 4q on the sum.
 #include "hetal_internal.hpp"
 
@@ -227,12 +229,15 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
           if (!(u & half)) fwd_bfly(x[u], x[u + half], tw_block(l, u), nq, q4);
       }
     }
-    if (FINAL) {
+    if (FINAL && !EPI) {
       const ModInfo m = mods[rj.y];
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = reduce64(x[u], m);
     }
     if (CONTIG && EPI) {
+      // x stays lazy (below 80 q): a + 128 q - x is positive and below 2^58, and the Shoup product by the
+      // combine constant accepts any 64-bit input, so its reduced result is the same.
+      const u64 q128 = q << 7;
       lds_exchange<true>(x, ls, block, spread);
       const int p = rj.x >= epi.l ? 1 : 0;
       const int i = rj.y;
@@ -247,7 +252,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 k = sp_off + sp_step * u;
-        u64 v = mul_shoup(sub_mod(ea[k], x[u], q), cst, cst_sh, q);
+        u64 v = mul_shoup(ea[k] + q128 - x[u], cst, cst_sh, q);
         if (own) v = add_mod(v, own[gather ? galois_source(k, g, log_n) : k], q);
         if (both) v = add_mod(v, both[k], q);
         eo[k] = v;
