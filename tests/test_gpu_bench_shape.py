@@ -38,12 +38,24 @@ def setup():
     return ctx, sk, keys, ev, (X, W, PY), (gx, gw, gpy), (ox, ow, opy), s1
 
 
+_ORACLE = {}
+
+
+def oracle_product(setup, op):
+    """The oracle's output of one product, computed once per module (tens of seconds each)."""
+    ctx, sk, keys, ev, _, _, (ox, ow, opy), s1 = setup
+    if op not in _ORACLE:
+        note("%s 128x768x10 in the oracle" % op)
+        _ORACLE[op] = (mx.diag_abt(ev, ox, ow[0], C, S0, s1, 1.0) if op == "abt"
+                       else mx.diag_atb(ev, opy, ox, C, S0, s1, 1.0))
+    return _ORACLE[op]
+
+
 def test_forward_product_bit_exact(setup):
     ctx, sk, keys, ev, (X, W, PY), (gx, gw, gpy), (ox, ow, opy), s1 = setup
     note("DiagABT 128x768x10 on the GPU")
     gout = ctx.enc_matmul_abt(keys, gx, gw, C, 1.0)
-    note("DiagABT 128x768x10 in the oracle")
-    oout = mx.diag_abt(ev, ox, ow[0], C, S0, s1, 1.0)
+    oout = oracle_product(setup, "abt")
     compare_blocks(ctx, gout, oout)
     Wp = np.vstack([W, np.zeros((C - 10, 768))])
     res = ctx.mat_decrypt(sk, gout)[:128, :s1]
@@ -54,9 +66,19 @@ def test_gradient_product_bit_exact(setup):
     ctx, sk, keys, ev, (X, W, PY), (gx, gw, gpy), (ox, ow, opy), s1 = setup
     note("DiagATB (128x10)^T 128x768 on the GPU")
     gout = ctx.enc_matmul_atb(keys, gpy, gx, C, 1.0)
-    note("DiagATB in the oracle")
-    oout = mx.diag_atb(ev, opy, ox, C, S0, s1, 1.0)
+    oout = oracle_product(setup, "atb")
     compare_blocks(ctx, gout, oout)
     PYp = np.hstack([PY, np.zeros((128, C - 10))])
     res = ctx.mat_decrypt(sk, gout)[:S0, :768]
     assert np.abs(res - np.tile(PYp.T @ X, (S0 // C, 1))).max() < TARGET
+
+
+def test_benchmark_launch_configuration_bit_exact(setup):
+    """Both products as the benchmark times them: one batched call whose two products run on two streams,
+    repeated, every output word against the oracle each time."""
+    ctx, sk, keys, ev, _, (gx, gw, gpy), _, s1 = setup
+    for rep in range(2):
+        note("batched two-stream call, repetition %d" % rep)
+        gabt, gatb = ctx.enc_matmul_batch(keys, [("abt", gx, gw, C, 1.0), ("atb", gpy, gx, C, 1.0)])
+        compare_blocks(ctx, gabt, oracle_product(setup, "abt"))
+        compare_blocks(ctx, gatb, oracle_product(setup, "atb"))
