@@ -198,7 +198,8 @@ int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double 
  * s1 / c times across, the A-underbar of Alg. 4).  The caller sets
  * out->s0 (s1 = N/2 / s0), out->level and out->scale; the library sets n_rb,
  * n_cb.  a: host uint64 [n_rb*n_cb][level+1][N]; e: host int64 [n_rb*n_cb][N].
- * E_SHAPE if c does not divide the tiled dimension. */
+ * E_SHAPE for an empty matrix (rows or cols 0, checked before anything
+ * else), or if c does not divide the tiled dimension. */
 int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int c,
                       const uint64_t* a, const int64_t* e, hetal_mat* out);
 /* Decrypt and decode every block: host double [n_rb*s0][n_cb*s1] (real

@@ -693,9 +693,9 @@ int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double 
 int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int cc,
                       const uint64_t* a, const int64_t* e, hetal_mat* out) {
   return guarded([&] {
+    need(rows > 0 && cols > 0, HETAL_E_SHAPE, "empty matrix");
     need(ctx && sk && host && a && e && out && out->data, HETAL_E_INVALID_ARG, "null argument");
     Context& c = ctx->c;
-    need(rows > 0 && cols > 0, HETAL_E_SHAPE, "empty matrix");
     need(out->s0 > 0 && c.slots % out->s0 == 0, HETAL_E_SHAPE, "s0 must divide N/2");
     const int s0 = out->s0, s1 = c.slots / s0;
     need(out->level >= 0 && out->level < c.num_q, HETAL_E_LEVEL, "level out of range");
