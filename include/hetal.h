@@ -99,6 +99,9 @@ typedef struct {
   double scale;
 } hetal_mat;
 
+/* The message of the last failed call on the calling thread (a failed call
+ * sets it; successful calls leave it).  Owned by the library, valid until
+ * the thread's next failing call. */
 const char* hetal_last_error(void);
 
 /* Context: parameters, precomputed tables (roots of unity, basis-conversion
