@@ -132,7 +132,8 @@ void hetal_sk_destroy(hetal_sk* sk);
  *   ksk_j = (-a_j s + e_j + g_j s', a_j), j < dnum, over all primes, where
  *   g_j = P mod q_i for q_i in digit j and 0 otherwise (0 modulo each p_k).
  * a: host uint64 [dnum][num_q + num_p][N], uniform modulo each prime,
- *    coefficient form; e: host int64 [dnum][N], small signed errors. */
+ *    coefficient form (E_INVALID_ARG if a word is not below its prime);
+ *    e: host int64 [dnum][N], small signed errors. */
 int hetal_keys_create(hetal_ctx* ctx, hetal_keys** out);
 void hetal_keys_destroy(hetal_keys* keys);
 int hetal_keys_gen_relin(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, const uint64_t* a, const int64_t* e);
@@ -151,8 +152,8 @@ int hetal_encode(hetal_ctx* ctx, const double* re, const double* im, int level, 
 int hetal_decode(hetal_ctx* ctx, const hetal_pt* pt, double* re, double* im);
 
 /* Secret-key encryption (c0, c1) = (-a s + m + e, a) at the plaintext's
- * level.  a: host uint64 [level+1][N] uniform modulo q_i, coefficient form;
- * e: host int64 [N]. */
+ * level.  a: host uint64 [level+1][N] uniform modulo q_i, coefficient form
+ * (E_INVALID_ARG if a word is not below its prime); e: host int64 [N]. */
 int hetal_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, const uint64_t* a, const int64_t* e,
                   hetal_ct* out);
 /* m = c0 + c1 s. */
@@ -200,7 +201,8 @@ int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double 
  * down, the B-bar of Alg. 1); 2 horizontal (the rows x c matrix repeated
  * s1 / c times across, the A-underbar of Alg. 4).  The caller sets
  * out->s0 (s1 = N/2 / s0), out->level and out->scale; the library sets n_rb,
- * n_cb.  a: host uint64 [n_rb*n_cb][level+1][N]; e: host int64 [n_rb*n_cb][N].
+ * n_cb.  a: host uint64 [n_rb*n_cb][level+1][N], each word below its prime
+ * (else E_INVALID_ARG); e: host int64 [n_rb*n_cb][N].
  * E_SHAPE for an empty matrix (rows or cols 0, checked before anything
  * else), or if c does not divide the tiled dimension. */
 int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int c,
@@ -279,7 +281,8 @@ int hetal_add_plain(hetal_ctx* ctx, const hetal_ct* ct, const hetal_pt* pt, heta
  * decrypt, lift the plaintext polynomial m from q_0 (its centred residue; every other limb must agree,
  * i.e. |m| < q_0 / 2, else E_OVERFLOW), re-encode it at `scale` as rint(m * scale / ct->scale) (ties to
  * even; scale 0 keeps the scale and m), encrypt at the top level with the caller's randomness (a: host
- * uint64 [num_q][N] uniform modulo each ciphertext prime, e: host int64 [N]).  out may alias ct and needs
+ * uint64 [num_q][N] uniform modulo each ciphertext prime, each word below it (else E_INVALID_ARG), e: host int64
+ * [N]).  out may alias ct and needs
  * room for the top level.  This hands the ciphertext to the client: it is outside the paper's threat model
  * and meant for pipelines deeper than the modulus chain.  Re-encoding at a fixed scale (2^40) keeps chains
  * of squarings from driving the scale away from the primes. */

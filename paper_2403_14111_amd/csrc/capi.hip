@@ -88,8 +88,22 @@ Tmp upload_words(Context& c, const void* host, size_t bytes) {
   return t;
 }
 
+// The transforms take residues in [0, q): caller-supplied uniform randomness is checked on the host
+// ([count][rows][N], row i modulo primes[i]).
+static void check_uniform(const Context& c, const uint64_t* host, int count, int rows) {
+  for (int b = 0; b < count; ++b)
+    for (int i = 0; i < rows; ++i) {
+      const uint64_t* r = host + ((size_t)b * rows + i) * c.n;
+      const uint64_t q = c.primes[i];
+      bool ok = true;
+      for (int k = 0; k < c.n; ++k) ok &= r[k] < q;
+      need(ok, HETAL_E_INVALID_ARG, "uniform randomness not reduced modulo its prime");
+    }
+}
+
 // NTT form of caller-supplied coefficient-form randomness a ([count][l][N]) and e ([count][N]).
 void load_randomness(Context& c, const uint64_t* a_host, const int64_t* e_host, int level, int count, Tmp& a, Tmp& e) {
+  check_uniform(c, a_host, count, level + 1);
   const size_t poly = c.poly_words(level);
   HCHECK(hipStreamSynchronize(c.stream));
   HCHECK(hipMemcpyAsync(a.p, a_host, (size_t)count * poly * 8, hipMemcpyHostToDevice, c.stream));
@@ -222,6 +236,7 @@ void hetal_keys_destroy(hetal_keys* keys) {
 }
 
 static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint64_t* a_host, const int64_t* e_host) {
+  check_uniform(c, a_host, c.dnum, c.nprimes);
   const size_t rows_words = (size_t)c.nprimes * c.n;
   Tmp a(c.pool, (size_t)c.dnum * rows_words);
   Tmp e(c.pool, (size_t)c.dnum * rows_words);

@@ -182,6 +182,7 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
   }
   // twiddles and per-prime constants
   std::vector<ulonglong2> twf((size_t)np * n), twi((size_t)np * n);
+  std::vector<double> twdf((size_t)np * n), twdi((size_t)np * n);
   c.h_pc.assign(np, PrimeConsts{});
   for (int i = 0; i < np; ++i) {
     const u64 q = c.primes[i];
@@ -198,6 +199,8 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
       const size_t at = (size_t)i * n + ntt_twiddle_slot(x, c.log_n);
       twf[at] = make_ulonglong2(wf, shoup(wf, q));
       twi[at] = make_ulonglong2(wi, shoup(wi, q));
+      twdf[at] = (double)wf;
+      twdi[at] = (double)wi;
     }
     PrimeConsts& k = c.h_pc[i];
     k.ninv = invm((u64)n % q, q);
@@ -344,6 +347,11 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
   c.d_mod = upload(mods.data(), mods.size(), stream);
   c.d_tw_fwd = upload(twf.data(), twf.size(), stream);
   c.d_tw_inv = upload(twi.data(), twi.size(), stream);
+  c.d_twd_fwd = upload(twdf.data(), twdf.size(), stream);
+  c.d_twd_inv = upload(twdi.data(), twdi.size(), stream);
+  std::vector<FpMod> fpm(np);
+  for (int i = 0; i < np; ++i) fpm[i] = FpMod{(double)c.primes[i], 1.0 / (double)c.primes[i]};
+  c.d_fpm = upload(fpm.data(), fpm.size(), stream);
   c.d_pc = upload(c.h_pc.data(), c.h_pc.size(), stream);
   c.d_modup = upload(c.h_modup.data(), c.h_modup.size(), stream);
   c.d_moddown = upload(&c.h_moddown, 1, stream);
@@ -371,6 +379,9 @@ void context_share(Context& d, const Context& s, hipStream_t stream) {
   d.d_mod = s.d_mod;
   d.d_tw_fwd = s.d_tw_fwd;
   d.d_tw_inv = s.d_tw_inv;
+  d.d_twd_fwd = s.d_twd_fwd;
+  d.d_twd_inv = s.d_twd_inv;
+  d.d_fpm = s.d_fpm;
   d.d_pc = s.d_pc;
   d.d_modup = s.d_modup;
   d.d_moddown = s.d_moddown;
@@ -395,7 +406,8 @@ void context_free(Context& c) {
   else (void)hipDeviceSynchronize();
   if (!c.owns_tables) return;
   void* ptrs[] = {c.d_mod,     c.d_tw_fwd, c.d_tw_inv, c.d_pc,   c.d_modup,         c.d_moddown,
-                  c.d_rescale, c.d_roots,  c.d_pow5,   c.d_rows, c.d_modup_scale, c.d_moddown_scale};
+                  c.d_rescale, c.d_roots,  c.d_pow5,   c.d_rows, c.d_modup_scale, c.d_moddown_scale,
+                  c.d_twd_fwd, c.d_twd_inv, c.d_fpm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -61,6 +61,11 @@ struct NttScale {
   u64 s0, s0_sh, s1, s1_sh;
 };
 
+// A prime as the NTT kernels' FP64 arithmetic takes it: q and its reciprocal rounded to nearest.
+struct FpMod {
+  double q, qinv;
+};
+
 // q_l^-1 mod q_i (i < l) for the rescale at level l.
 struct RescaleTab {
   u64 inv[MAX_PRIMES];
@@ -168,6 +173,9 @@ struct Context {
   ModInfo* d_mod = nullptr;          // [nprimes]
   ulonglong2* d_tw_fwd = nullptr;    // [nprimes][N]: (psi^brev(x), Shoup) at ntt_twiddle_slot(x)
   ulonglong2* d_tw_inv = nullptr;    // [nprimes][N]: (psi^-brev(x), Shoup) at ntt_twiddle_slot(x)
+  double* d_twd_fwd = nullptr;       // [nprimes][N]: the same twiddles as doubles (exact: below 2^50)
+  double* d_twd_inv = nullptr;
+  FpMod* d_fpm = nullptr;            // [nprimes]: (q, 1/q) as doubles
   PrimeConsts* d_pc = nullptr;       // [nprimes]
   ModUpTab* d_modup = nullptr;       // [num_q levels][dnum]
   ModDownTab* d_moddown = nullptr;   // one table (rows q_0..q_{num_q-1})

@@ -18,15 +18,20 @@
 //  * Loads and stores are arranged so that the 16 threads of a sub-transform
 //    (contiguous pass) or 16 neighbouring columns (strided pass) touch 128
 //    contiguous bytes.
-//  * Butterflies are lazy.  T = Y * W mod q comes from Shoup's method with a
-//    quotient estimate that skips the carries of the low partial products
-//    (3 integer multiplies fewer, and no 64-bit register shuffles): it is at
-//    most 3 below the exact quotient, so T lies in [0, 4q).  Forward:
-//    X' = X + T, Y' = X + 4q - T; values stay below (1 + 4 log N) q < 2^57
-//    (below (16 + 4 log N) q <= 80 q for the inputs of a fused conversion)
-//    and one exact Shoup reduction by 1 finishes, or the combine epilogue
-//    takes the lazy values.  Inverse: values kept in
-//    [0, 4q) by one conditional subtraction of 4q on the sum.
+//  * The arithmetic is FP64, which gfx950 issues at the full vector rate while
+//    64-bit integer products take several half- and quarter-rate 32-bit
+//    multiplies.  Residues (all moduli are below 2^50) are exact integers in
+//    doubles between the loads and the stores, which stay 64-bit integers:
+//      - a*w mod q for |a| <= 2^51, 0 <= w < q: p = fl(a w) and its exact
+//        error e = fma(a, w, -p); f = floor(fl(p * fl(1/q))) is within one of
+//        floor(a w / q) (relative error below 3 * 2^-53), so
+//        r = fma(-f, q, p) + e = a w - f q is exact and lies in (-0.75q, 1.75q);
+//      - v mod q for an integer |v| < 2^52: r = fma(-floor(fl(v * fl(1/q))), q, v)
+//        is exact and lies in [0, q] (the quotient is off by less than 1/q,
+//        and r is an integer).
+//    Every butterfly output is reduced that way, so each stage takes and gives
+//    values in [0, q]; stored results are mapped to [0, q).  Twiddles are
+//    doubles (8 bytes each, no Shoup companion).
 #include "hetal_internal.hpp"
 
 namespace hetal {
@@ -38,19 +43,53 @@ constexpr int NTT_R = 16;
 
 __device__ __forceinline__ int pad_idx(int v) { return v + (v >> 4); }
 
-__device__ __forceinline__ void fwd_bfly(u64& x, u64& y, ulonglong2 w, u64 nq, u64 q4) {
-  const u64 t = mul_shoup_lazy4n(y, w.x, w.y, nq);
-  y = x + q4 - t;
-  x = x + t;
+// u64 below 2^53 -> double, exactly.
+__device__ __forceinline__ double u2d(u64 v) {
+#pragma clang fp contract(off)
+  return __builtin_fma((double)hi32(v), 4294967296.0, (double)lo32(v));
 }
 
-// Gentleman-Sande butterfly without reduction of the sum: with both inputs below b, x + b - y is
-// positive, the sum stays below 2b and the product below 4q.
-__device__ __forceinline__ void inv_bfly(u64& x, u64& y, ulonglong2 w, u64 nq, u64 b) {
-  const u64 s = x + y;
-  const u64 d = x + b - y;
-  y = mul_shoup_lazy4n(d, w.x, w.y, nq);
-  x = s;
+// Integer-valued double in [0, 2^53) -> u64.
+__device__ __forceinline__ u64 d2u(double v) {
+#pragma clang fp contract(off)
+  const double h = __builtin_floor(v * (1.0 / 4294967296.0));
+  const double l = __builtin_fma(-h, 4294967296.0, v);
+  return ((u64)(u32)h << 32) | (u64)(u32)l;
+}
+
+// a w mod q, exact, in (-0.75q, 1.75q), for integers |a| <= 2^51 and 0 <= w < q < 2^50.
+__device__ __forceinline__ double fmul(double a, double w, double q, double qinv) {
+#pragma clang fp contract(off)
+  const double p = a * w;
+  const double e = __builtin_fma(a, w, -p);
+  const double f = __builtin_floor(p * qinv);
+  return __builtin_fma(-f, q, p) + e;
+}
+
+// v mod q, exact, in [0, q], for integers |v| < 2^52.
+__device__ __forceinline__ double fred(double v, double q, double qinv) {
+#pragma clang fp contract(off)
+  return __builtin_fma(-__builtin_floor(v * qinv), q, v);
+}
+
+// [0, q] -> [0, q)
+__device__ __forceinline__ double ffix(double v, double q) { return v >= q ? v - q : v; }
+
+// Cooley-Tukey butterfly on [0, q] values: T = y w, x + T and x - T reduced.
+__device__ __forceinline__ void fwd_bfly(double& x, double& y, double w, double q, double qinv) {
+#pragma clang fp contract(off)
+  const double t = fmul(y, w, q, qinv);
+  y = fred(x - t, q, qinv);
+  x = fred(x + t, q, qinv);
+}
+
+// Gentleman-Sande butterfly on [0, q] values: x + y, and (x - y) w, both reduced.
+__device__ __forceinline__ void inv_bfly(double& x, double& y, double w, double q, double qinv) {
+#pragma clang fp contract(off)
+  const double s = x + y;
+  const double d = x - y;
+  y = fred(fmul(d, w, q, qinv), q, qinv);
+  x = fred(s, q, qinv);
 }
 
 // Workgroups are numbered so that the batch items sharing one (row, chunk) --
@@ -68,23 +107,23 @@ struct PassArgs {
 };
 
 // Transpose through LDS: x[u] is stored at word widx(u) of the workgroup's buffer, then x[u] is
-// loaded from word ridx(u).  The 64-bit residues travel as two 32-bit halves through a 32-bit
+// loaded from word ridx(u).  The 64-bit values travel as two 32-bit halves through a 32-bit
 // buffer, which halves the LDS a workgroup holds.  LEAD_SYNC: the buffer was read before.
 template <bool LEAD_SYNC, class W, class R>
-__device__ __forceinline__ void lds_exchange(u64 (&x)[NTT_R], u32* __restrict__ ls, W widx, R ridx) {
+__device__ __forceinline__ void lds_exchange(double (&x)[NTT_R], u32* __restrict__ ls, W widx, R ridx) {
   if (LEAD_SYNC) __syncthreads();
 #pragma unroll
-  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = lo32(x[u]);
+  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = lo32((u64)__double_as_longlong(x[u]));
   __syncthreads();
   u32 lo[NTT_R];
 #pragma unroll
   for (int u = 0; u < NTT_R; ++u) lo[u] = ls[ridx(u)];
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = hi32(x[u]);
+  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = hi32((u64)__double_as_longlong(x[u]));
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < NTT_R; ++u) x[u] = ((u64)ls[ridx(u)] << 32) | lo[u];
+  for (int u = 0; u < NTT_R; ++u) x[u] = __longlong_as_double((long long)(((u64)ls[ridx(u)] << 32) | lo[u]));
 }
 
 // One pass of 2^L-point sub-transforms.  Two shapes occur:
@@ -93,7 +132,7 @@ __device__ __forceinline__ void lds_exchange(u64 (&x)[NTT_R], u32* __restrict__ 
 //  * contiguous (pass B, CONTIG true): the 2^(log_n - 8) chunks of 256, stages log_n - 8 .. log_n - 1
 //    (L == 8); element v of chunk c sits at 256 c + v.
 // Forward passes run A then B, inverse passes B then A; the second pass of either is the final one
-// (full reduction; for the inverse also the N^-1 scaling).
+// (stored in [0, q); the first pass stores [0, q], read only by the second).  Inputs are in [0, q].
 //
 // Each thread holds 16 elements of one sub-transform: in stages 0..3 of the pass element
 // v = j + T u ("spread"), in stages 4..L-1 element v = 16 j + u ("block").  The twiddle of stage l
@@ -104,11 +143,12 @@ __device__ __forceinline__ void lds_exchange(u64 (&x)[NTT_R], u32* __restrict__ 
 // source rows.  row_scale (inverse strided pass only, may be null): per-row final scaling.
 template <int L, bool INV, bool CONTIG, bool EPI, int CONVK, int CNT>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
-                                                              const ulonglong2* __restrict__ tw,
-                                                              const ModInfo* __restrict__ mods,
+                                                              const double* __restrict__ tw,
+                                                              const FpMod* __restrict__ fpm,
                                                               const PrimeConsts* __restrict__ pc, int log_n, int s0,
                                                               NttEpilogue epi, NttConv cv,
                                                               const NttScale* __restrict__ row_scale) {
+#pragma clang fp contract(off)
   constexpr int SUB = 1 << L;
   constexpr int T = SUB / NTT_R;        // threads per sub-transform
   constexpr int S = NTT_THREADS / T;    // sub-transforms per workgroup
@@ -135,10 +175,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   u64* __restrict__ a = pa.base + (size_t)item * pa.batch_stride + (size_t)rj.x * n;
   const u64* __restrict__ ain =
       pa.src ? pa.src + (size_t)item * pa.src_batch_stride + (size_t)(rj.x * pa.src_row_mul + pa.src_row_add) * n : a;
-  const u64 q = mods[rj.y].q;
-  const u64 q4 = 4 * q;
-  const u64 nq = 0 - q;
-  const ulonglong2* __restrict__ w = tw + (size_t)rj.y * n;
+  const FpMod fm = fpm[rj.y];
+  const double q = fm.q, qi = fm.qinv;
+  const double* __restrict__ w = tw + (size_t)rj.y * n;
 
   const int tid = threadIdx.x;
   const int sl = CONTIG ? tid / T : tid % S;
@@ -160,64 +199,68 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
     return CONTIG ? w[(1 << (s0 + l)) + (sub << l) + (((u >> (8 - l)) << 4) | j)]
                   : w[(1 << l) + ((16 * j + u) >> (L - l))];
   };
-  u64 x[NTT_R];
+  double x[NTT_R];
 
   if (!INV) {
     if (CONVK == CONV_MODUP) {
-      // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t, lazily
+      // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t.  Each product of a
+      // y_i < 2^50 lies in (-0.375 t, 1.375 t); the sum is reduced after two terms and at the end.
       const ModUpTab& tb = cv.modup[rj.x / cv.ext];
       const u64* yb[CNT];
-      u64 cc[CNT], cs[CNT];
+      double cc[CNT];
 #pragma unroll
       for (int i = 0; i < CNT; ++i) {
         // a short last digit has zero constants beyond its length (its row pointer stays in range)
         yb[i] = cv.y + item * cv.y_stride + (size_t)(tb.first + (i < tb.nsrc ? i : 0)) * n;
-        cc[i] = tb.dhat[i][rj.y];
-        cs[i] = tb.dhat_sh[i][rj.y];
+        cc[i] = u2d(tb.dhat[i][rj.y]);
       }
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 pos = sp_off + sp_step * u;
-        u64 s = mul_shoup_lazy4n(yb[0][pos], cc[0], cs[0], nq);
+        double s = fmul(u2d(yb[0][pos]), cc[0], q, qi);
 #pragma unroll
-        for (int i = 1; i < CNT; ++i) s += mul_shoup_lazy4n(yb[i][pos], cc[i], cs[i], nq);
-        x[u] = s;
+        for (int i = 1; i < CNT; ++i) {
+          s = s + fmul(u2d(yb[i][pos]), cc[i], q, qi);
+          if (i == 1 && CNT > 2) s = fred(s, q, qi);
+        }
+        x[u] = fred(s, q, qi);
       }
     } else if (CONVK == CONV_MODDOWN) {
-      // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i, y_k centred, lazily
+      // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i with y_k centred: each
+      // product of a |y_k| < 2^49 lies in (-0.19 q, 1.19 q); reduced after two terms and at the end.
       const int p = rj.x >= cv.l ? 1 : 0;
       const u64* yb[CNT];
-      u64 pk[CNT], cc[CNT], cs[CNT];
+      double pk[CNT], ph[CNT], cc[CNT];
 #pragma unroll
       for (int k = 0; k < CNT; ++k) {
         yb[k] = cv.y + item * cv.y_stride + (size_t)(p * cv.ext + cv.l + k) * n;
-        pk[k] = mods[cv.num_q + k].q;
-        cc[k] = cv.moddown->phat[k][rj.y];
-        cs[k] = cv.moddown->phat_sh[k][rj.y];
+        pk[k] = fpm[cv.num_q + k].q;
+        ph[k] = __builtin_floor(pk[k] * 0.5);  // (p_k - 1) / 2: values above it are taken as negative
+        cc[k] = u2d(cv.moddown->phat[k][rj.y]);
       }
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 pos = sp_off + sp_step * u;
-        u64 s = 0;
+        double s = 0.0;
 #pragma unroll
         for (int k = 0; k < CNT; ++k) {
-          const u64 v = yb[k][pos];
-          const bool neg = v > (pk[k] >> 1);
-          const u64 t = mul_shoup_lazy4n(neg ? pk[k] - v : v, cc[k], cs[k], nq);
-          s += neg ? q4 - t : t;
+          double v = u2d(yb[k][pos]);
+          v = v > ph[k] ? v - pk[k] : v;
+          s = s + fmul(v, cc[k], q, qi);
+          if (k == 1 && CNT > 2) s = fred(s, q, qi);
         }
-        x[u] = s;
+        x[u] = fred(s, q, qi);
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
+      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
     }
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int hu = 8 >> l;
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u)
-        if (!(u & hu)) fwd_bfly(x[u], x[u + hu], tw_spread(l, u), nq, q4);
+        if (!(u & hu)) fwd_bfly(x[u], x[u + hu], tw_spread(l, u), q, qi);
     }
     if (L > 4) {
       lds_exchange<false>(x, ls, spread, block);
@@ -226,22 +269,19 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         const int half = 1 << (L - 1 - l);
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u)
-          if (!(u & half)) fwd_bfly(x[u], x[u + half], tw_block(l, u), nq, q4);
+          if (!(u & half)) fwd_bfly(x[u], x[u + half], tw_block(l, u), q, qi);
       }
     }
     if (FINAL && !EPI) {
-      const ModInfo m = mods[rj.y];
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = reduce64(x[u], m);
+      for (int u = 0; u < NTT_R; ++u) x[u] = ffix(x[u], q);
     }
     if (CONTIG && EPI) {
-      // x stays lazy (below 80 q): a + 128 q - x is positive and below 2^58, and the Shoup product by the
-      // combine constant accepts any 64-bit input, so its reduced result is the same.
-      const u64 q128 = q << 7;
+      // (a - x) c + addends: a - x in [-q, q], its product in (-0.375q, 1.375q), plus two residues
       lds_exchange<true>(x, ls, block, spread);
       const int p = rj.x >= epi.l ? 1 : 0;
       const int i = rj.y;
-      const u64 cst = epi.cst[i], cst_sh = epi.cst_sh[i];
+      const double cst = u2d(epi.cst[i]);
       const u64* __restrict__ ea = epi.a + item * epi.a_stride + ((size_t)p * epi.a_poly_rows + i) * n;
       u64* __restrict__ eo = epi.out + item * epi.out_stride + (size_t)rj.x * n;
       const u64* __restrict__ own = p == 0 ? (epi.add0 ? epi.add0 + item * epi.add0_stride + (size_t)i * n : nullptr)
@@ -252,43 +292,41 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 k = sp_off + sp_step * u;
-        u64 v = mul_shoup(ea[k] + q128 - x[u], cst, cst_sh, q);
-        if (own) v = add_mod(v, own[gather ? galois_source(k, g, log_n) : k], q);
-        if (both) v = add_mod(v, both[k], q);
-        eo[k] = v;
+        double v = fmul(u2d(ea[k]) - x[u], cst, q, qi);
+        if (own) v = v + u2d(own[gather ? galois_source(k, g, log_n) : k]);
+        if (both) v = v + u2d(both[k]);
+        eo[k] = d2u(ffix(fred(v, q, qi), q));
       }
     } else if (CONTIG) {
       lds_exchange<true>(x, ls, block, spread);
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
+      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
     } else if (L > 4) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) (a + bl_step * u)[bl_off] = x[u];
+      for (int u = 0; u < NTT_R; ++u) (a + bl_step * u)[bl_off] = d2u(x[u]);
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
+      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
     }
   } else {
-    // Inputs are below 4q; after k executed stages all values are below 4q 2^k.
     if (CONTIG) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
+      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
       lds_exchange<false>(x, ls, spread, block);
     } else if (L > 4) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + bl_step * u)[bl_off];
+      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + bl_step * u)[bl_off]);
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = (ain + sp_step * u)[sp_off];
+      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
     }
     if (L > 4) {
 #pragma unroll
       for (int l = L - 1; l >= 4; --l) {
         const int half = 1 << (L - 1 - l);
-        const u64 b = q4 << (L - 1 - l);
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u)
-          if (!(u & half)) inv_bfly(x[u], x[u + half], tw_block(l, u), nq, b);
+          if (!(u & half)) inv_bfly(x[u], x[u + half], tw_block(l, u), q, qi);
       }
       if (CONTIG)
         lds_exchange<true>(x, ls, block, spread);
@@ -298,38 +336,30 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
     for (int l = 3; l >= 0; --l) {
       const int hu = 8 >> l;
-      const u64 b = q4 << (L - 1 - l);
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         if (u & hu) continue;
         if (l == 0 && FINAL) {
           // last stage of the transform, N^-1 (or the row's replacement) merged into both outputs
-          NttScale k;
+          double k0, k1;
           if (row_scale) {
-            k = row_scale[rowi];
+            k0 = u2d(row_scale[rowi].s0);
+            k1 = u2d(row_scale[rowi].s1);
           } else {
-            const PrimeConsts& pcr = pc[rj.y];
-            k = NttScale{pcr.ninv, pcr.ninv_sh, pcr.w1ninv, pcr.w1ninv_sh};
+            k0 = u2d(pc[rj.y].ninv);
+            k1 = u2d(pc[rj.y].w1ninv);
           }
-          const u64 s = x[u] + x[u + hu];
-          const u64 d = x[u] + b - x[u + hu];
-          x[u] = mul_shoup_lazy4n(s, k.s0, k.s0_sh, nq);
-          x[u + hu] = mul_shoup_lazy4n(d, k.s1, k.s1_sh, nq);
+          const double s = x[u] + x[u + hu];  // [0, 2q]
+          const double d = x[u] - x[u + hu];  // [-q, q]
+          x[u] = ffix(fred(fmul(s, k0, q, qi), q, qi), q);
+          x[u + hu] = ffix(fred(fmul(d, k1, q, qi), q, qi), q);
         } else {
-          inv_bfly(x[u], x[u + hu], tw_spread(l, u), nq, b);
+          inv_bfly(x[u], x[u + hu], tw_spread(l, u), q, qi);
         }
       }
     }
-    if (FINAL) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = csub(csub(x[u], 2 * q), q);
-    } else {
-      const u64 one_sh = mods[rj.y].one_sh;
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = reduce_lazy4(x[u], one_sh, nq);
-    }
-#pragma unroll
-    for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = x[u];
+    for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
   }
 }
 
@@ -352,7 +382,7 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   pa.batch = batch;
   const int padded = (pa.groups + 7) / 8 * 8;
   dim3 grid((unsigned)(padded * batch)), block(NTT_THREADS);
-  const ulonglong2* tw = INV ? c.d_tw_inv : c.d_tw_fwd;
+  const double* tw = INV ? c.d_twd_inv : c.d_twd_fwd;
   // the strided pass is the 2^L x 256 column view (s0 == 0), the contiguous one the last 8 stages
   const bool contiguous = s0 + L == c.log_n;
   if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
@@ -367,14 +397,14 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   c.begin_launch();
   if (epi) {
     hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, CONV_NONE, 1>), grid, block, 0, c.stream, pa, rows.d, tw,
-                       c.d_mod, c.d_pc, c.log_n, s0, *epi, no_conv, nullptr);
+                       c.d_fpm, c.d_pc, c.log_n, s0, *epi, no_conv, nullptr);
   } else if (cv) {
     const int key = (L == 8 ? 100 : 0) + conv->kind * 10 + conv->count;
     switch (key) {
 #define HETAL_NTT_CONV(LL, K, C)                                                                               \
   case (LL == 8 ? 100 : 0) + K * 10 + C:                                                                     \
     hipLaunchKernelGGL((ntt_pass_kernel<LL, false, false, false, K, C>), grid, block, 0, c.stream, pa, rows.d, tw, \
-                       c.d_mod, c.d_pc, c.log_n, s0, no_epi, *conv, nullptr);                                \
+                       c.d_fpm, c.d_pc, c.log_n, s0, no_epi, *conv, nullptr);                                \
     break;
 #define HETAL_NTT_CONV_L(LL) \
   HETAL_NTT_CONV(LL, 1, 1) HETAL_NTT_CONV(LL, 1, 2) HETAL_NTT_CONV(LL, 1, 3) HETAL_NTT_CONV(LL, 1, 4) \
@@ -391,7 +421,7 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
 #define HETAL_NTT_CASE(LL, CC)                                                                                 \
   case LL * 2 + CC:                                                                                          \
     hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC, false, CONV_NONE, 1>), grid, block, 0, c.stream, pa, rows.d, \
-                       tw, c.d_mod, c.d_pc, c.log_n, s0, no_epi, no_conv, row_scale);                        \
+                       tw, c.d_fpm, c.d_pc, c.log_n, s0, no_epi, no_conv, row_scale);                        \
     break;
       HETAL_NTT_CASE(4, 0)
       HETAL_NTT_CASE(5, 0)
