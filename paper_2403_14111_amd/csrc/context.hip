@@ -181,7 +181,6 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
     mods[i].pad = 0;
   }
   // twiddles and per-prime constants
-  std::vector<ulonglong2> twf((size_t)np * n), twi((size_t)np * n);
   std::vector<double> twdf((size_t)np * n), twdi((size_t)np * n);
   c.h_pc.assign(np, PrimeConsts{});
   for (int i = 0; i < np; ++i) {
@@ -197,8 +196,6 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
     for (int x = 0; x < n; ++x) {
       const u64 wf = pw[brev((u32)x, c.log_n)], wi = pwi[brev((u32)x, c.log_n)];
       const size_t at = (size_t)i * n + ntt_twiddle_slot(x, c.log_n);
-      twf[at] = make_ulonglong2(wf, shoup(wf, q));
-      twi[at] = make_ulonglong2(wi, shoup(wi, q));
       twdf[at] = (double)wf;
       twdi[at] = (double)wi;
     }
@@ -345,8 +342,6 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
   }
 
   c.d_mod = upload(mods.data(), mods.size(), stream);
-  c.d_tw_fwd = upload(twf.data(), twf.size(), stream);
-  c.d_tw_inv = upload(twi.data(), twi.size(), stream);
   c.d_twd_fwd = upload(twdf.data(), twdf.size(), stream);
   c.d_twd_inv = upload(twdi.data(), twdi.size(), stream);
   std::vector<FpMod> fpm(np);
@@ -377,8 +372,6 @@ void context_share(Context& d, const Context& s, hipStream_t stream) {
   d.primes = s.primes;
   d.stream = stream;
   d.d_mod = s.d_mod;
-  d.d_tw_fwd = s.d_tw_fwd;
-  d.d_tw_inv = s.d_tw_inv;
   d.d_twd_fwd = s.d_twd_fwd;
   d.d_twd_inv = s.d_twd_inv;
   d.d_fpm = s.d_fpm;
@@ -405,7 +398,7 @@ void context_free(Context& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   else (void)hipDeviceSynchronize();
   if (!c.owns_tables) return;
-  void* ptrs[] = {c.d_mod,     c.d_tw_fwd, c.d_tw_inv, c.d_pc,   c.d_modup,         c.d_moddown,
+  void* ptrs[] = {c.d_mod,     c.d_pc,     c.d_modup,  c.d_moddown,
                   c.d_rescale, c.d_roots,  c.d_pow5,   c.d_rows, c.d_modup_scale, c.d_moddown_scale,
                   c.d_twd_fwd, c.d_twd_inv, c.d_fpm};
   for (void* p : ptrs)

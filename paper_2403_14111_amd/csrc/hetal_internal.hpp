@@ -171,10 +171,8 @@ struct Context {
   hipStream_t stream = nullptr;
 
   ModInfo* d_mod = nullptr;          // [nprimes]
-  ulonglong2* d_tw_fwd = nullptr;    // [nprimes][N]: (psi^brev(x), Shoup) at ntt_twiddle_slot(x)
-  ulonglong2* d_tw_inv = nullptr;    // [nprimes][N]: (psi^-brev(x), Shoup) at ntt_twiddle_slot(x)
-  double* d_twd_fwd = nullptr;       // [nprimes][N]: the same twiddles as doubles (exact: below 2^50)
-  double* d_twd_inv = nullptr;
+  double* d_twd_fwd = nullptr;       // [nprimes][N]: psi^brev(x) at ntt_twiddle_slot(x), as doubles (exact: < 2^50)
+  double* d_twd_inv = nullptr;       // [nprimes][N]: psi^-brev(x) likewise
   FpMod* d_fpm = nullptr;            // [nprimes]: (q, 1/q) as doubles
   PrimeConsts* d_pc = nullptr;       // [nprimes]
   ModUpTab* d_modup = nullptr;       // [num_q levels][dnum]

@@ -30,8 +30,11 @@
 //        is exact and lies in [0, q] (the quotient is off by less than 1/q,
 //        and r is an integer).
 //    Every butterfly output is reduced that way, so each stage takes and gives
-//    values in [0, q]; stored results are mapped to [0, q).  Twiddles are
-//    doubles (8 bytes each, no Shoup companion).
+//    values in [0, q]; stored results are mapped to [0, q).  Rows of moduli
+//    below 2^42 (most of the chain) skip those reductions within a pass (see
+//    fwd_bfly / inv_bfly).  Twiddles are doubles (8 bytes, no Shoup companion).
+#include <type_traits>
+
 #include "hetal_internal.hpp"
 
 namespace hetal {
@@ -75,22 +78,40 @@ __device__ __forceinline__ double fred(double v, double q, double qinv) {
 // [0, q] -> [0, q)
 __device__ __forceinline__ double ffix(double v, double q) { return v >= q ? v - q : v; }
 
-// Cooley-Tukey butterfly on [0, q] values: T = y w, x + T and x - T reduced.
+// Cooley-Tukey butterfly: T = y w, then x + T and x - T.  Reduced (LAZY false): inputs and outputs in
+// [0, q].  LAZY (moduli below 2^42 only): nothing is reduced; with |y| <= 2^47 the product T lies in
+// (-0.05q, 1.05q), so each stage widens the bound by 1.05q and a pass stays far below 2^47.
+template <bool LAZY>
 __device__ __forceinline__ void fwd_bfly(double& x, double& y, double w, double q, double qinv) {
 #pragma clang fp contract(off)
   const double t = fmul(y, w, q, qinv);
-  y = fred(x - t, q, qinv);
-  x = fred(x + t, q, qinv);
+  if (LAZY) {
+    y = x - t;
+    x = x + t;
+  } else {
+    y = fred(x - t, q, qinv);
+    x = fred(x + t, q, qinv);
+  }
 }
 
-// Gentleman-Sande butterfly on [0, q] values: x + y, and (x - y) w, both reduced.
+// Gentleman-Sande butterfly: x + y, and (x - y) w.  Reduced: [0, q] in and out.  LAZY (moduli below
+// 2^42): nothing is reduced; the sum doubles the bound per stage, so a pass reduces once halfway.
+template <bool LAZY>
 __device__ __forceinline__ void inv_bfly(double& x, double& y, double w, double q, double qinv) {
 #pragma clang fp contract(off)
   const double s = x + y;
   const double d = x - y;
-  y = fred(fmul(d, w, q, qinv), q, qinv);
-  x = fred(s, q, qinv);
+  if (LAZY) {
+    y = fmul(d, w, q, qinv);
+    x = s;
+  } else {
+    y = fred(fmul(d, w, q, qinv), q, qinv);
+    x = fred(s, q, qinv);
+  }
 }
+
+// Moduli below this take the lazy butterflies.
+constexpr double LAZY_MODULUS = 4398046511104.0;  // 2^42
 
 // Workgroups are numbered so that the batch items sharing one (row, chunk) --
 // and so one twiddle range -- run back to back on the same XCD (workgroups
@@ -202,6 +223,12 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   double x[NTT_R];
 
   if (!INV) {
+    // LZ: the lazy butterflies and conversion sums of moduli below 2^42 (see fwd_bfly)
+    auto transform = [&](auto lazy) {
+    constexpr bool LZ = decltype(lazy)::value;
+    // keeps the two instances' identical loads from being merged above the branch (which would hold every
+    // twiddle of the pass in registers at once)
+    asm volatile("" ::: "memory");
     if (CONVK == CONV_MODUP) {
       // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t.  Each product of a
       // y_i < 2^50 lies in (-0.375 t, 1.375 t); the sum is reduced after two terms and at the end.
@@ -221,9 +248,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
         for (int i = 1; i < CNT; ++i) {
           s = s + fmul(u2d(yb[i][pos]), cc[i], q, qi);
-          if (i == 1 && CNT > 2) s = fred(s, q, qi);
+          if (!LZ && i == 1 && CNT > 2) s = fred(s, q, qi);
         }
-        x[u] = fred(s, q, qi);
+        x[u] = LZ ? s : fred(s, q, qi);
       }
     } else if (CONVK == CONV_MODDOWN) {
       // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i with y_k centred: each
@@ -247,9 +274,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
           double v = u2d(yb[k][pos]);
           v = v > ph[k] ? v - pk[k] : v;
           s = s + fmul(v, cc[k], q, qi);
-          if (k == 1 && CNT > 2) s = fred(s, q, qi);
+          if (!LZ && k == 1 && CNT > 2) s = fred(s, q, qi);
         }
-        x[u] = fred(s, q, qi);
+        x[u] = LZ ? s : fred(s, q, qi);
       }
     } else {
 #pragma unroll
@@ -260,7 +287,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       const int hu = 8 >> l;
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u)
-        if (!(u & hu)) fwd_bfly(x[u], x[u + hu], tw_spread(l, u), q, qi);
+        if (!(u & hu)) fwd_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
     }
     if (L > 4) {
       lds_exchange<false>(x, ls, spread, block);
@@ -269,9 +296,19 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         const int half = 1 << (L - 1 - l);
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u)
-          if (!(u & half)) fwd_bfly(x[u], x[u + half], tw_block(l, u), q, qi);
+          if (!(u & half)) fwd_bfly<LZ>(x[u], x[u + half], tw_block(l, u), q, qi);
       }
     }
+    if (LZ) {
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
+    }
+    };
+    // (the epilogue pass keeps to the reduced butterflies: the lazy copy's registers cost it a wave per SIMD)
+    if (!EPI && q < LAZY_MODULUS)
+      transform(std::true_type{});
+    else
+      transform(std::false_type{});
     if (FINAL && !EPI) {
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = ffix(x[u], q);
@@ -309,6 +346,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
     }
   } else {
+    auto transform = [&](auto lazy) {
+    constexpr bool LZ = decltype(lazy)::value;
+    asm volatile("" ::: "memory");  // as in the forward branch
     if (CONTIG) {
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
@@ -326,7 +366,11 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         const int half = 1 << (L - 1 - l);
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u)
-          if (!(u & half)) inv_bfly(x[u], x[u + half], tw_block(l, u), q, qi);
+          if (!(u & half)) inv_bfly<LZ>(x[u], x[u + half], tw_block(l, u), q, qi);
+      }
+      if (LZ) {  // halfway: back to [0, q]
+#pragma unroll
+        for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
       }
       if (CONTIG)
         lds_exchange<true>(x, ls, block, spread);
@@ -349,15 +393,24 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
             k0 = u2d(pc[rj.y].ninv);
             k1 = u2d(pc[rj.y].w1ninv);
           }
-          const double s = x[u] + x[u + hu];  // [0, 2q]
-          const double d = x[u] - x[u + hu];  // [-q, q]
+          const double s = x[u] + x[u + hu];  // [0, 2q] (lazy: below 16q)
+          const double d = x[u] - x[u + hu];
           x[u] = ffix(fred(fmul(s, k0, q, qi), q, qi), q);
           x[u + hu] = ffix(fred(fmul(d, k1, q, qi), q, qi), q);
         } else {
-          inv_bfly(x[u], x[u + hu], tw_spread(l, u), q, qi);
+          inv_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
         }
       }
     }
+    if (LZ && !FINAL) {
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
+    }
+    };
+    if (q < LAZY_MODULUS)
+      transform(std::true_type{});
+    else
+      transform(std::false_type{});
 #pragma unroll
     for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
   }
