@@ -282,7 +282,7 @@ struct NttEpilogue {
 //      sum_k y_k (P / p_k) mod q_i
 //    over the special rows y_k = [x_k (P/p_k)^-1]_{p_k} of polynomial p of `y` (at row p ext + l + k), each
 //    taken in the centred range (-p_k/2, p_k/2].
-// The words are left lazy (below 4 count q); the transform tolerates that.
+// The sums are reduced to [0, q] (for moduli below 2^42 left below 5.5 q, which the lazy butterflies take).
 enum NttConvKind { CONV_NONE = 0, CONV_MODUP = 1, CONV_MODDOWN = 2 };
 struct NttConv {
   int kind = CONV_NONE;
