@@ -6,7 +6,8 @@ from paper_2403_14111_amd import inputs
 
 
 def make_oracle(name, seed=2000, rot_steps=(), conj=True, relin=True):
-    prm = ckks.preset(name)
+    """name: a preset name, or a dict of ckks.Params arguments."""
+    prm = ckks.Params(**name) if isinstance(name, dict) else ckks.preset(name)
     sk = ckks.SecretKey(prm, inputs.ternary_secret(seed, prm.n))
     ev = ckks.Evaluator(prm, sk)
     if relin:
