@@ -225,84 +225,84 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   if (!INV) {
     // LZ: the lazy butterflies and conversion sums of moduli below 2^42 (see fwd_bfly)
     auto transform = [&](auto lazy) {
-    constexpr bool LZ = decltype(lazy)::value;
-    // keeps the two instances' identical loads from being merged above the branch (which would hold every
-    // twiddle of the pass in registers at once)
-    asm volatile("" ::: "memory");
-    if (CONVK == CONV_MODUP) {
-      // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t.  Each product of a
-      // y_i < 2^50 lies in (-0.375 t, 1.375 t); the sum is reduced after two terms and at the end.
-      const ModUpTab& tb = cv.modup[rj.x / cv.ext];
-      const u64* yb[CNT];
-      double cc[CNT];
+      constexpr bool LZ = decltype(lazy)::value;
+      // keeps the two instances' identical loads from being merged above the branch (which would hold every
+      // twiddle of the pass in registers at once)
+      asm volatile("" ::: "memory");
+      if (CONVK == CONV_MODUP) {
+        // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t.  Each product of a
+        // y_i < 2^50 lies in (-0.375 t, 1.375 t); the reducing form reduces the sum after two terms and at the end.
+        const ModUpTab& tb = cv.modup[rj.x / cv.ext];
+        const u64* yb[CNT];
+        double cc[CNT];
 #pragma unroll
-      for (int i = 0; i < CNT; ++i) {
-        // a short last digit has zero constants beyond its length (its row pointer stays in range)
-        yb[i] = cv.y + item * cv.y_stride + (size_t)(tb.first + (i < tb.nsrc ? i : 0)) * n;
-        cc[i] = u2d(tb.dhat[i][rj.y]);
-      }
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) {
-        const u32 pos = sp_off + sp_step * u;
-        double s = fmul(u2d(yb[0][pos]), cc[0], q, qi);
-#pragma unroll
-        for (int i = 1; i < CNT; ++i) {
-          s = s + fmul(u2d(yb[i][pos]), cc[i], q, qi);
-          if (!LZ && i == 1 && CNT > 2) s = fred(s, q, qi);
+        for (int i = 0; i < CNT; ++i) {
+          // a short last digit has zero constants beyond its length (its row pointer stays in range)
+          yb[i] = cv.y + item * cv.y_stride + (size_t)(tb.first + (i < tb.nsrc ? i : 0)) * n;
+          cc[i] = u2d(tb.dhat[i][rj.y]);
         }
-        x[u] = LZ ? s : fred(s, q, qi);
-      }
-    } else if (CONVK == CONV_MODDOWN) {
-      // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i with y_k centred: each
-      // product of a |y_k| < 2^49 lies in (-0.19 q, 1.19 q); reduced after two terms and at the end.
-      const int p = rj.x >= cv.l ? 1 : 0;
-      const u64* yb[CNT];
-      double pk[CNT], ph[CNT], cc[CNT];
 #pragma unroll
-      for (int k = 0; k < CNT; ++k) {
-        yb[k] = cv.y + item * cv.y_stride + (size_t)(p * cv.ext + cv.l + k) * n;
-        pk[k] = fpm[cv.num_q + k].q;
-        ph[k] = __builtin_floor(pk[k] * 0.5);  // (p_k - 1) / 2: values above it are taken as negative
-        cc[k] = u2d(cv.moddown->phat[k][rj.y]);
-      }
+        for (int u = 0; u < NTT_R; ++u) {
+          const u32 pos = sp_off + sp_step * u;
+          double s = fmul(u2d(yb[0][pos]), cc[0], q, qi);
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) {
-        const u32 pos = sp_off + sp_step * u;
-        double s = 0.0;
+          for (int i = 1; i < CNT; ++i) {
+            s = s + fmul(u2d(yb[i][pos]), cc[i], q, qi);
+            if (!LZ && i == 1 && CNT > 2) s = fred(s, q, qi);
+          }
+          x[u] = LZ ? s : fred(s, q, qi);
+        }
+      } else if (CONVK == CONV_MODDOWN) {
+        // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i with y_k centred: each
+        // product of a |y_k| < 2^49 lies in (-0.19 q, 1.19 q); the reducing form reduces after two terms and at the end.
+        const int p = rj.x >= cv.l ? 1 : 0;
+        const u64* yb[CNT];
+        double pk[CNT], ph[CNT], cc[CNT];
 #pragma unroll
         for (int k = 0; k < CNT; ++k) {
-          double v = u2d(yb[k][pos]);
-          v = v > ph[k] ? v - pk[k] : v;
-          s = s + fmul(v, cc[k], q, qi);
-          if (!LZ && k == 1 && CNT > 2) s = fred(s, q, qi);
+          yb[k] = cv.y + item * cv.y_stride + (size_t)(p * cv.ext + cv.l + k) * n;
+          pk[k] = fpm[cv.num_q + k].q;
+          ph[k] = __builtin_floor(pk[k] * 0.5);  // (p_k - 1) / 2: values above it are taken as negative
+          cc[k] = u2d(cv.moddown->phat[k][rj.y]);
         }
-        x[u] = LZ ? s : fred(s, q, qi);
+#pragma unroll
+        for (int u = 0; u < NTT_R; ++u) {
+          const u32 pos = sp_off + sp_step * u;
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < CNT; ++k) {
+            double v = u2d(yb[k][pos]);
+            v = v > ph[k] ? v - pk[k] : v;
+            s = s + fmul(v, cc[k], q, qi);
+            if (!LZ && k == 1 && CNT > 2) s = fred(s, q, qi);
+          }
+          x[u] = LZ ? s : fred(s, q, qi);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
       }
-    } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
-    }
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const int hu = 8 >> l;
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u)
-        if (!(u & hu)) fwd_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
-    }
-    if (L > 4) {
-      lds_exchange<false>(x, ls, spread, block);
-#pragma unroll
-      for (int l = 4; l < L; ++l) {
-        const int half = 1 << (L - 1 - l);
+      for (int l = 0; l < 4; ++l) {
+        const int hu = 8 >> l;
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u)
-          if (!(u & half)) fwd_bfly<LZ>(x[u], x[u + half], tw_block(l, u), q, qi);
+          if (!(u & hu)) fwd_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
       }
-    }
-    if (LZ) {
+      if (L > 4) {
+        lds_exchange<false>(x, ls, spread, block);
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
-    }
+        for (int l = 4; l < L; ++l) {
+          const int half = 1 << (L - 1 - l);
+#pragma unroll
+          for (int u = 0; u < NTT_R; ++u)
+            if (!(u & half)) fwd_bfly<LZ>(x[u], x[u + half], tw_block(l, u), q, qi);
+        }
+      }
+      if (LZ) {
+#pragma unroll
+        for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
+      }
     };
     // (the epilogue pass keeps to the reduced butterflies: the lazy copy's registers cost it a wave per SIMD)
     if (!EPI && q < LAZY_MODULUS)
@@ -347,65 +347,65 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
     }
   } else {
     auto transform = [&](auto lazy) {
-    constexpr bool LZ = decltype(lazy)::value;
-    asm volatile("" ::: "memory");  // as in the forward branch
-    if (CONTIG) {
+      constexpr bool LZ = decltype(lazy)::value;
+      asm volatile("" ::: "memory");  // as in the forward branch
+      if (CONTIG) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
-      lds_exchange<false>(x, ls, spread, block);
-    } else if (L > 4) {
+        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
+        lds_exchange<false>(x, ls, spread, block);
+      } else if (L > 4) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + bl_step * u)[bl_off]);
-    } else {
+        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + bl_step * u)[bl_off]);
+      } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
-    }
-    if (L > 4) {
-#pragma unroll
-      for (int l = L - 1; l >= 4; --l) {
-        const int half = 1 << (L - 1 - l);
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u)
-          if (!(u & half)) inv_bfly<LZ>(x[u], x[u + half], tw_block(l, u), q, qi);
+        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
       }
-      if (LZ) {  // halfway: back to [0, q]
+      if (L > 4) {
+#pragma unroll
+        for (int l = L - 1; l >= 4; --l) {
+          const int half = 1 << (L - 1 - l);
+#pragma unroll
+          for (int u = 0; u < NTT_R; ++u)
+            if (!(u & half)) inv_bfly<LZ>(x[u], x[u + half], tw_block(l, u), q, qi);
+        }
+        if (LZ) {  // halfway: back to [0, q]
+#pragma unroll
+          for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
+        }
+        if (CONTIG)
+          lds_exchange<true>(x, ls, block, spread);
+        else
+          lds_exchange<false>(x, ls, block, spread);
+      }
+#pragma unroll
+      for (int l = 3; l >= 0; --l) {
+        const int hu = 8 >> l;
+#pragma unroll
+        for (int u = 0; u < NTT_R; ++u) {
+          if (u & hu) continue;
+          if (l == 0 && FINAL) {
+            // last stage of the transform, N^-1 (or the row's replacement) merged into both outputs
+            double k0, k1;
+            if (row_scale) {
+              k0 = u2d(row_scale[rowi].s0);
+              k1 = u2d(row_scale[rowi].s1);
+            } else {
+              k0 = u2d(pc[rj.y].ninv);
+              k1 = u2d(pc[rj.y].w1ninv);
+            }
+            const double s = x[u] + x[u + hu];  // [0, 2q] (lazy: below 16q)
+            const double d = x[u] - x[u + hu];
+            x[u] = ffix(fred(fmul(s, k0, q, qi), q, qi), q);
+            x[u + hu] = ffix(fred(fmul(d, k1, q, qi), q, qi), q);
+          } else {
+            inv_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
+          }
+        }
+      }
+      if (LZ && !FINAL) {
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
       }
-      if (CONTIG)
-        lds_exchange<true>(x, ls, block, spread);
-      else
-        lds_exchange<false>(x, ls, block, spread);
-    }
-#pragma unroll
-    for (int l = 3; l >= 0; --l) {
-      const int hu = 8 >> l;
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) {
-        if (u & hu) continue;
-        if (l == 0 && FINAL) {
-          // last stage of the transform, N^-1 (or the row's replacement) merged into both outputs
-          double k0, k1;
-          if (row_scale) {
-            k0 = u2d(row_scale[rowi].s0);
-            k1 = u2d(row_scale[rowi].s1);
-          } else {
-            k0 = u2d(pc[rj.y].ninv);
-            k1 = u2d(pc[rj.y].w1ninv);
-          }
-          const double s = x[u] + x[u + hu];  // [0, 2q] (lazy: below 16q)
-          const double d = x[u] - x[u + hu];
-          x[u] = ffix(fred(fmul(s, k0, q, qi), q, qi), q);
-          x[u + hu] = ffix(fred(fmul(d, k1, q, qi), q, qi), q);
-        } else {
-          inv_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
-        }
-      }
-    }
-    if (LZ && !FINAL) {
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
-    }
     };
     if (q < LAZY_MODULUS)
       transform(std::true_type{});
