@@ -254,7 +254,8 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         }
       } else if (CONVK == CONV_MODDOWN) {
         // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i with y_k centred: each
-        // product of a |y_k| < 2^49 lies in (-0.19 q, 1.19 q); the reducing form reduces after two terms and at the end.
+        // product of a |y_k| < 2^49 lies in (-0.19 q, 1.19 q); the reducing form reduces after two terms
+        // and at the end.
         const int p = rj.x >= cv.l ? 1 : 0;
         const u64* yb[CNT];
         double pk[CNT], ph[CNT], cc[CNT];
