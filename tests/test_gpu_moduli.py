@@ -1,7 +1,8 @@
-"""GPU parity on modulus chains beyond the presets (N = 2^12), for the two forms of the NTT kernels' FP64
-arithmetic and the conversion sums of every length: 49- and 50-bit primes only (all rows take the reducing
-butterflies), 30-bit ciphertext primes (the lazy butterflies at small moduli), and four-prime digits with four
-special primes (four-term ModUp and ModDown sums).  Every word against the oracle."""
+"""GPU parity on modulus chains beyond the presets, every word against the oracle:
+  * 49- and 50-bit primes only (N = 2^12): every row takes the reducing FP64 butterflies;
+  * 30-bit ciphertext primes: the lazy butterflies at small moduli;
+  * four-prime digits with four special primes: four-term ModUp and ModDown sums;
+  * N = 2^13 and 2^15: 5- and 7-stage strided passes, and the basis conversions as kernels of their own."""
 import sys
 
 import numpy as np
@@ -19,6 +20,9 @@ CHAINS = {
     "wide49": dict(log_n=12, num_q=4, num_p=2, dnum=2, q0_bits=50, q_bits=49),
     "small30": dict(log_n=12, num_q=4, num_p=2, dnum=2, q0_bits=50, q_bits=30),
     "alpha4": dict(log_n=12, num_q=8, num_p=4, dnum=2, q0_bits=50, q_bits=40),
+    # other ring sizes: 5- and 7-stage strided passes, and the conversions as kernels of their own
+    "n13": dict(log_n=13, num_q=3, num_p=1, dnum=3, q0_bits=50, q_bits=40),
+    "n15": dict(log_n=15, num_q=4, num_p=2, dnum=2, q0_bits=50, q_bits=40),
 }
 STEPS = (1, -3, 1000)
 
