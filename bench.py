@@ -937,6 +937,8 @@ def main():
             "ring": "N=2^16, 12 ciphertext primes (50+11x40 bits) + 3 special primes, dnum=4, scale 2^40",
             "level_in": LEVEL, "s0": S0, "s1": 32768 // S0, "c": C_PAD,
             "matmuls_per_step": 2,
+            "arithmetic": "residues are 64-bit integers; the NTT passes compute their exact modular products in FP64, "
+                          "the other kernels in 64-bit integers",
         },
         "roofline": roofline,
         "cpu_baseline": {k: v for k, v in (cpu or {}).items() if k != "seconds"} if cpu else None,
