@@ -276,7 +276,8 @@ struct NttEpilogue {
 // reading them (the fast basis conversions of hybrid key switching, never stored):
 //  * CONV_MODUP, rows of ROWS_MODUP: row (digit j, extended row r, prime t) takes
 //      sum_i y_i (D_j / d_i) mod t
-//    over the digit's rows y_i = [x_i (D_j/d_i)^-1]_{d_i} of `y` (coefficient form, rows indexed like the
+//    over the digit's rows y_i = [x_i (D_j/d_i)^-1]_{d_i} of `y` (coefficient form as the bit patterns of exact
+//    doubles, see ntt_inverse's dbl; rows indexed like the
 //    ciphertext's limbs, `ext` rows per digit in the row table's row index);
 //  * CONV_MODDOWN, rows of ROWS_CT: row (polynomial p, limb i) takes
 //      sum_k y_k (P / p_k) mod q_i
@@ -299,8 +300,10 @@ constexpr int MAX_FUSED_CONV = 4;  // conversions of more terms run as separate 
 
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
                  const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr);
+// dbl: the results are stored as the bit patterns of exact doubles, the form the forward transform's fused
+// conversion input (NttConv) reads; only for N = 2^12 and 2^16.
 void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
-                 const NttScale* row_scale = nullptr);
+                 const NttScale* row_scale = nullptr, bool dbl = false);
 
 struct KsItem {
   const u64* key;  // [dnum][2][nprimes][N]

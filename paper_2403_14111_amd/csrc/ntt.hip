@@ -161,8 +161,10 @@ __device__ __forceinline__ void lds_exchange(double (&x)[NTT_R], u32* __restrict
 // in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
 // EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.
 // CONVK / CNT (forward strided pass only): the input words are the basis conversion of NttConv over CNT
-// source rows.  row_scale (inverse strided pass only, may be null): per-row final scaling.
-template <int L, bool INV, bool CONTIG, bool EPI, int CONVK, int CNT>
+// source rows, which hold the bit patterns of doubles (the DBL output of the inverse transform that made them).
+// row_scale (inverse strided pass only, may be null): per-row final scaling.  DBL (inverse strided pass only):
+// the results are stored as the bit patterns of the (integer-valued) doubles, for a conversion input.
+template <int L, bool INV, bool CONTIG, bool EPI, int CONVK, int CNT, bool DBL = false>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const double* __restrict__ tw,
                                                               const FpMod* __restrict__ fpm,
@@ -178,6 +180,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   static_assert(!EPI || (CONTIG && !INV), "the epilogue belongs to the last forward pass");
   static_assert(CONVK == CONV_NONE || (!CONTIG && !INV && CNT >= 1 && CNT <= MAX_FUSED_CONV),
                 "the conversion input belongs to the first forward pass");
+  static_assert(!DBL || (INV && !CONTIG), "double output belongs to the last inverse pass");
   // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
   // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
   // neighbouring slices in lockstep fall on distinct banks.
@@ -244,10 +247,10 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u) {
           const u32 pos = sp_off + sp_step * u;
-          double s = fmul(u2d(yb[0][pos]), cc[0], q, qi);
+          double s = fmul(__longlong_as_double((long long)yb[0][pos]), cc[0], q, qi);
 #pragma unroll
           for (int i = 1; i < CNT; ++i) {
-            s = s + fmul(u2d(yb[i][pos]), cc[i], q, qi);
+            s = s + fmul(__longlong_as_double((long long)yb[i][pos]), cc[i], q, qi);
             if (!LZ && i == 1 && CNT > 2) s = fred(s, q, qi);
           }
           x[u] = LZ ? s : fred(s, q, qi);
@@ -272,7 +275,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
           double s = 0.0;
 #pragma unroll
           for (int k = 0; k < CNT; ++k) {
-            double v = u2d(yb[k][pos]);
+            double v = __longlong_as_double((long long)yb[k][pos]);
             v = v > ph[k] ? v - pk[k] : v;
             s = s + fmul(v, cc[k], q, qi);
             if (!LZ && k == 1 && CNT > 2) s = fred(s, q, qi);
@@ -413,14 +416,15 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
     else
       transform(std::false_type{});
 #pragma unroll
-    for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
+    for (int u = 0; u < NTT_R; ++u)
+      (a + sp_step * u)[sp_off] = DBL ? (u64)__double_as_longlong(x[u]) : d2u(x[u]);
   }
 }
 
 template <bool INV>
 void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0,
                  const NttSrc& src, const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr,
-                 const NttScale* row_scale = nullptr) {
+                 const NttScale* row_scale = nullptr, bool dbl = false) {
   const int sub = 1 << L;
   const int per_wg = NTT_THREADS * NTT_R / sub;  // sub-transforms per workgroup
   const int nsub = c.n / sub;
@@ -446,6 +450,7 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   if (cv && (INV || contiguous || (L != 4 && L != 8) || conv->count < 1 || conv->count > MAX_FUSED_CONV))
     fail(HETAL_E_PARAMS, "NTT conversion input outside the first forward pass");
   if (row_scale && !(INV && !contiguous)) fail(HETAL_E_PARAMS, "NTT row scaling outside the last inverse pass");
+  if (dbl && !(INV && !contiguous)) fail(HETAL_E_PARAMS, "double output outside the last inverse pass");
   const NttEpilogue no_epi{};
   const NttConv no_conv{};
   c.begin_launch();
@@ -469,6 +474,19 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
 #undef HETAL_NTT_CONV
       default:
         fail(HETAL_E_PARAMS, "unsupported NTT conversion input");
+    }
+  } else if (dbl) {
+    switch (L) {
+#define HETAL_NTT_DBL(LL)                                                                                      \
+  case LL:                                                                                                   \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, true, false, false, CONV_NONE, 1, true>), grid, block, 0, c.stream, pa, \
+                       rows.d, tw, c.d_fpm, c.d_pc, c.log_n, s0, no_epi, no_conv, row_scale);                \
+    break;
+      HETAL_NTT_DBL(4)
+      HETAL_NTT_DBL(8)
+#undef HETAL_NTT_DBL
+      default:
+        fail(HETAL_E_PARAMS, "double output needs N = 2^12 or 2^16");
     }
   } else {
     switch (L * 2 + (contiguous ? 1 : 0)) {
@@ -517,11 +535,11 @@ void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef 
 }
 
 void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
-                 const NttScale* row_scale) {
+                 const NttScale* row_scale, bool dbl) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
   launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, src);
-  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{}, nullptr, nullptr, row_scale);
+  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{}, nullptr, nullptr, row_scale, dbl);
   c.counters[6] += (int64_t)rows.count * batch;
 }
 

@@ -382,7 +382,7 @@ void key_switch(Context& c, const KsJob& job) {
   src.p = job.in;
   src.batch_stride = hoisted ? 0 : job.in_stride;
   ntt_inverse(c, coef, poly, m_in, RowsRef{ct_rows.d, l}, src,
-              fuse_up ? c.d_modup_scale + (size_t)level * MAX_PRIMES : nullptr);
+              fuse_up ? c.d_modup_scale + (size_t)level * MAX_PRIMES : nullptr, fuse_up);
 
   // 2. ModUp of every digit, then the NTT of the converted rows
   Tmp dt(c.pool, m_in * dt_words);
@@ -456,7 +456,8 @@ void key_switch(Context& c, const KsJob& job) {
   }
 
   // 4. ModDown: special rows to coefficient form, centred conversion, NTT, combine
-  ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level), NttSrc{}, fuse_down ? c.d_moddown_scale : nullptr);
+  ntt_inverse(c, acc, acc_words, m, c.rows(ROWS_SPECIAL, level), NttSrc{}, fuse_down ? c.d_moddown_scale : nullptr,
+              fuse_down);
   Tmp conv(c.pool, m * conv_words);
   NttConv cv;
   if (fuse_down) {
