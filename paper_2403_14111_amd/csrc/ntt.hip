@@ -78,6 +78,11 @@ __device__ __forceinline__ double fred(double v, double q, double qinv) {
 // [0, q] -> [0, q)
 __device__ __forceinline__ double ffix(double v, double q) { return v >= q ? v - q : v; }
 
+// A transform's first pass hands its results to the second as the bit patterns of the doubles (values in
+// [0, q]): nothing else reads them, so neither side converts.
+__device__ __forceinline__ u64 mid_st(double v) { return (u64)__double_as_longlong(v); }
+__device__ __forceinline__ double mid_ld(u64 w) { return __longlong_as_double((long long)w); }
+
 // Cooley-Tukey butterfly: T = y w, then x + T and x - T.  Reduced (LAZY false): inputs and outputs in
 // [0, q].  LAZY (moduli below 2^42 only): nothing is reduced; with |y| <= 2^47 the product T lies in
 // (-0.05q, 1.05q), so each stage widens the bound by 1.05q and a pass stays far below 2^47.
@@ -153,7 +158,7 @@ __device__ __forceinline__ void lds_exchange(double (&x)[NTT_R], u32* __restrict
 //  * contiguous (pass B, CONTIG true): the 2^(log_n - 8) chunks of 256, stages log_n - 8 .. log_n - 1
 //    (L == 8); element v of chunk c sits at 256 c + v.
 // Forward passes run A then B, inverse passes B then A; the second pass of either is the final one
-// (stored in [0, q); the first pass stores [0, q], read only by the second).  Inputs are in [0, q].
+// (stored in [0, q); the first pass stores [0, q] as doubles, read only by the second).  Inputs are in [0, q].
 //
 // Each thread holds 16 elements of one sub-transform: in stages 0..3 of the pass element
 // v = j + T u ("spread"), in stages 4..L-1 element v = 16 j + u ("block").  The twiddle of stage l
@@ -284,7 +289,10 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         }
       } else {
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
+        for (int u = 0; u < NTT_R; ++u) {
+          const u64 w = (ain + sp_step * u)[sp_off];
+          x[u] = FINAL ? mid_ld(w) : u2d(w);  // the final pass reads the first pass's doubles
+        }
       }
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
@@ -344,10 +352,10 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
     } else if (L > 4) {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) (a + bl_step * u)[bl_off] = d2u(x[u]);
+      for (int u = 0; u < NTT_R; ++u) (a + bl_step * u)[bl_off] = mid_st(x[u]);
     } else {
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
+      for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = mid_st(x[u]);
     }
   } else {
     auto transform = [&](auto lazy) {
@@ -359,10 +367,10 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         lds_exchange<false>(x, ls, spread, block);
       } else if (L > 4) {
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + bl_step * u)[bl_off]);
+        for (int u = 0; u < NTT_R; ++u) x[u] = mid_ld((ain + bl_step * u)[bl_off]);
       } else {
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
+        for (int u = 0; u < NTT_R; ++u) x[u] = mid_ld((ain + sp_step * u)[sp_off]);
       }
       if (L > 4) {
 #pragma unroll
@@ -417,7 +425,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       transform(std::false_type{});
 #pragma unroll
     for (int u = 0; u < NTT_R; ++u)
-      (a + sp_step * u)[sp_off] = DBL ? (u64)__double_as_longlong(x[u]) : d2u(x[u]);
+      (a + sp_step * u)[sp_off] = DBL || !FINAL ? mid_st(x[u]) : d2u(x[u]);
   }
 }
 
