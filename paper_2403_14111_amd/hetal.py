@@ -241,11 +241,13 @@ class Context:
         self.q = self.primes[:self.num_q]
         self.p = self.primes[self.num_q:]
 
-    def __del__(self):
+    # The destroy functions are bound as default arguments: at interpreter shutdown the module's globals
+    # (_lib included) may already be cleared when the last handles are collected.
+    def __del__(self, _destroy=_lib.hetal_ctx_destroy):
         h = getattr(self, "_h", None)
         if h:
-            _lib.hetal_ctx_destroy(h)
             self._h = None
+            _destroy(h)
 
     # -- sizes / buffers --
     def ct_words(self, level):
@@ -626,10 +628,11 @@ class Graph:
     def launch(self):
         _check(_lib.hetal_graph_launch(self._h))
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            _lib.hetal_graph_destroy(self._h)
+    def __del__(self, _destroy=_lib.hetal_graph_destroy):
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _destroy(h)
 
 
 class SecretKey:
@@ -639,10 +642,11 @@ class SecretKey:
         _check(_lib.hetal_sk_create(ctx._h, sp, ctypes.byref(h)))
         self._h = h
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            _lib.hetal_sk_destroy(self._h)
+    def __del__(self, _destroy=_lib.hetal_sk_destroy):
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _destroy(h)
 
 
 class KeySet:
@@ -653,10 +657,11 @@ class KeySet:
         self._h = h
         self.galois = set()
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            _lib.hetal_keys_destroy(self._h)
+    def __del__(self, _destroy=_lib.hetal_keys_destroy):
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _destroy(h)
 
     def gen_relin(self, sk, a, e):
         a, ap = _u64(a)
