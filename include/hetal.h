@@ -182,6 +182,16 @@ int hetal_hrot(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, int r
  * without a step's Galois key. */
 int hetal_hrot_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* in, const int* steps, int count,
                      hetal_ct* out);
+/* hetal_hrot without device allocation, for callers that cannot allocate: code recorded into a HIP graph,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same result as hetal_hrot, word for word.  The key
+ * switch's temporaries live in a fixed 64 MiB static device region (one per GPU, held until the process
+ * ends) instead of the context's pool; a rotation needs (l + beta (l + K) + 2 (l + K) + 2 l) N words for l =
+ * level + 1 limbs, K special primes and beta digits, i.e. 63 MiB at N = 2^16, level 11, K = 3, dnum = 4.
+ * E_INVALID_ARG if that exceeds the region, if out->data == ct->data (in place would need a copy) or while
+ * per-kernel timing is on; other errors as hetal_hrot.  Every call on a GPU shares that GPU's region:
+ * calls that overlap on one GPU (contexts on different streams, several threads) race and must be
+ * serialised by the caller. */
+int hetal_hrot_noalloc(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, int r, hetal_ct* out);
 /* Slot-wise complex conjugation (Galois element 2N-1). */
 int hetal_conj(hetal_ctx* ctx, const hetal_keys* keys, const hetal_ct* ct, hetal_ct* out);
 /* Rescale: c_i <- (c_i - [c_l]_centred) q_l^-1 mod q_i, level - 1, scale / q_l.

@@ -7,76 +7,12 @@
 #include <string>
 #include <vector>
 
-#include "hetal.h"
-#include "matrix.hpp"
+#include "handles.hpp"
 #include "softmax.hpp"
 
 using namespace hetal;
 
-struct hetal_ctx {
-  Context c;
-  MaskCache masks;
-  // A second stream for independent groups of hetal_enc_matmul_batch, sharing c's tables (created on first use;
-  // side_masks is declared after side so that it returns its buffers to side's pool before side goes).
-  std::unique_ptr<Context> side;
-  MaskCache side_masks;
-  hipStream_t side_stream = nullptr;
-  hipEvent_t join[2] = {nullptr, nullptr};
-};
-
-struct hetal_sk {
-  hetal_ctx* ctx;
-  SecretKeyDev key;
-};
-
-struct hetal_keys {
-  hetal_ctx* ctx;
-  KeySet set;
-};
-
 namespace {
-
-thread_local std::string g_last_error;
-
-template <typename F>
-int guarded(F&& f) {
-  try {
-    f();
-    return HETAL_OK;
-  } catch (const Error& e) {
-    g_last_error = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return HETAL_E_OOM;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return HETAL_E_DEVICE;
-  }
-}
-
-void need(bool ok, int code, const char* msg) {
-  if (!ok) fail(code, msg);
-}
-
-void check_ct(const Context& c, const hetal_ct* ct, const char* what) {
-  need(ct && ct->data, HETAL_E_INVALID_ARG, what);
-  need(ct->level >= 0 && ct->level < c.num_q, HETAL_E_LEVEL, "ciphertext level out of range");
-  need(ct->capacity >= c.ct_words(ct->level), HETAL_E_INVALID_ARG, "ciphertext capacity smaller than its level needs");
-}
-
-void check_out(const Context& c, const hetal_ct* out, int level) {
-  need(out && out->data, HETAL_E_INVALID_ARG, "output ciphertext");
-  need(out->capacity >= c.ct_words(level), HETAL_E_INVALID_ARG, "output capacity too small for the result");
-}
-
-void check_pt(const Context& c, const hetal_pt* pt) {
-  need(pt && pt->data, HETAL_E_INVALID_ARG, "plaintext");
-  need(pt->level >= 0 && pt->level < c.num_q, HETAL_E_LEVEL, "plaintext level out of range");
-  need(pt->capacity >= c.poly_words(pt->level), HETAL_E_INVALID_ARG, "plaintext capacity too small");
-}
-
-CtView view_of(const hetal_ct* ct) { return CtView{ct->data, ct->level, ct->scale}; }
 
 // Host -> device upload into a pool buffer.  The stream is drained first, so a
 // pool buffer that queued kernels still read is never overwritten by a copy
@@ -127,6 +63,8 @@ int hetal_ctx_create(const hetal_params* params, void* stream, hetal_ctx** out) 
     need(params && out, HETAL_E_INVALID_ARG, "null argument");
     hetal_ctx* h = new hetal_ctx();
     try {
+      HCHECK(hipGetDevice(&h->device));
+      scratch_setup();
       context_init(h->c, *params, (hipStream_t)stream);
     } catch (...) {
       context_free(h->c);

@@ -95,7 +95,31 @@ T* upload(const T* h, size_t count, hipStream_t s) {
 
 // ---------------------------------------------------------------- Pool
 
+void Pool::arena_begin(u64* base, size_t words) {
+  arena_ = base;
+  arena_words_ = words;
+  arena_top_ = 0;
+  arena_marks_.clear();
+}
+
+void Pool::arena_end() {
+  arena_ = nullptr;
+  arena_words_ = 0;
+  arena_top_ = 0;
+  arena_marks_.clear();
+}
+
 u64* Pool::get(size_t words) {
+  if (arena_) {
+    const size_t need = arena_round(words);
+    if (need > arena_words_ - arena_top_)
+      fail(HETAL_E_INVALID_ARG, "scratch region exhausted: " + std::to_string(need * 8) + " more bytes needed, " +
+                                    std::to_string((arena_words_ - arena_top_) * 8) + " left");
+    u64* p = arena_ + arena_top_;
+    arena_marks_.push_back(arena_top_);
+    arena_top_ += need;
+    return p;
+  }
   auto it = free_.find(words);
   if (it != free_.end()) {
     u64* p = it->second;
@@ -118,6 +142,13 @@ u64* Pool::get(size_t words) {
 }
 
 void Pool::put(u64* p) {
+  if (arena_) {
+    if (!arena_marks_.empty() && p == arena_ + arena_marks_.back()) {
+      arena_top_ = arena_marks_.back();
+      arena_marks_.pop_back();
+    }
+    return;
+  }
   auto it = size_of_.find(p);
   if (it == size_of_.end()) return;
   free_.emplace(it->second, p);

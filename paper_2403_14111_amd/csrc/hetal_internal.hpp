@@ -101,6 +101,11 @@ struct PrimeConsts {
 
 // Size-bucketed cache of device allocations; all work is ordered on one stream,
 // so a buffer returned to the pool may be handed out again immediately.
+//
+// Arena mode (between arena_begin and arena_end): get() carves 256-byte aligned buffers out of one
+// caller-provided device region in order and never allocates (E_INVALID_ARG once the region is used
+// up); put() of the most recent buffer gives its space back, other buffers are held until arena_end.
+// The regular free list is neither used nor changed meanwhile.
 class Pool {
  public:
   u64* get(size_t words);
@@ -109,11 +114,18 @@ class Pool {
   ~Pool();
   size_t bytes_held() const { return held_; }
   bool recording = false;  // while work is recorded into a graph: no allocation (an error instead)
+  void arena_begin(u64* base, size_t words);
+  void arena_end();
+  static size_t arena_round(size_t words) { return (words + 31) / 32 * 32; }  // 256-byte granules
 
  private:
   std::multimap<size_t, u64*> free_;
   std::map<u64*, size_t> size_of_;
   size_t held_ = 0;
+  u64* arena_ = nullptr;
+  size_t arena_words_ = 0;
+  std::vector<size_t> arena_marks_;  // start offset of every buffer handed out, in order
+  size_t arena_top_ = 0;
 };
 
 // RAII lease of a pool buffer.
@@ -335,6 +347,14 @@ struct KsJob {
   size_t addx_stride = 0;
 };
 void key_switch(Context& c, const KsJob& job);
+// Device words of the temporaries key_switch leases from the pool for a job of `count` distinct inputs at
+// `level` (each buffer rounded up to the arena's 256-byte granule).
+size_t key_switch_scratch_words(const Context& c, int level, int count);
+
+// The library's static scratch region of the device that is current (see noalloc.hip): looked up once per
+// device, at context creation; scratch_region returns it for a device already set up.
+void scratch_setup();
+u64* scratch_region(int device, size_t* words);
 
 // Elementwise kernels on [rows][N] arrays whose row i is modulo prime (i mod period).
 void k_add(Context& c, const u64* a, const u64* b, u64* out, int rows, int period);

@@ -355,6 +355,14 @@ __global__ void __launch_bounds__(TPB) keygen_kernel(const u64* __restrict__ a, 
 
 // ---------------------------------------------------------------- launchers
 
+size_t key_switch_scratch_words(const Context& c, int level, int count) {
+  const size_t n = c.n;
+  const size_t l = level + 1, ext = l + c.num_p, beta = c.beta(level);
+  // coefficient form of the inputs, extended digits, accumulators, ModDown conversion rows (as key_switch)
+  return Pool::arena_round(count * l * n) + Pool::arena_round(count * beta * ext * n) +
+         Pool::arena_round(count * 2 * ext * n) + Pool::arena_round(count * 2 * l * n);
+}
+
 void key_switch(Context& c, const KsJob& job) {
   const int level = job.level;
   const int l = level + 1;

@@ -99,6 +99,7 @@ _SIGS = {
     "hetal_hmult": (ctypes.c_int, [_vp, _vp, _ctp, _ctp, _ctp]),
     "hetal_hrot": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_int, _ctp]),
     "hetal_hrot_batch": (ctypes.c_int, [_vp, _vp, _ctp, _intp, ctypes.c_int, _ctp]),
+    "hetal_hrot_noalloc": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_int, _ctp]),
     "hetal_conj": (ctypes.c_int, [_vp, _vp, _ctp, _ctp]),
     "hetal_rescale": (ctypes.c_int, [_vp, _ctp, _ctp]),
     "hetal_mod_drop": (ctypes.c_int, [_vp, _ctp, ctypes.c_int, _ctp]),
@@ -374,6 +375,14 @@ class Context:
         out = self.new_ct(a.level)
         s = out._struct()
         _check(_lib.hetal_hrot(self._h, keys._h, ctypes.byref(a._struct()), int(r), ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def hrot_noalloc(self, keys, a, r, out):
+        """hrot into the caller's `out` (not `a`) with the key switch's temporaries in the library's fixed
+        device scratch region: the call allocates no device memory."""
+        s = out._struct()
+        _check(_lib.hetal_hrot_noalloc(self._h, keys._h, ctypes.byref(a._struct()), int(r), ctypes.byref(s)))
         out.level, out.scale = s.level, s.scale
         return out
 
