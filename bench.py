@@ -211,6 +211,7 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
              "|---|---|---|---|---|---|---|---|"]
     traffic = {}
     scales = {}
+    step_total = {}
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         f = glob.glob(os.path.join(directory, counter, "*counter_collection.csv"))
         if not f:
@@ -219,6 +220,7 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
         scales[counter] = copy_kib / cal[4] if cal[4] > 0 else None
         plo, phi, _ = timed_window([x[1] for x in d], pmc_steps)
         for t, name, dur, grid, v in d[plo:phi]:
+            step_total[counter] = step_total.get(counter, 0.0) + v * 1024.0 * scales[counter] / pmc_steps
             cls = profile_class(name)
             if cls:
                 e = traffic.setdefault(cls, {}).setdefault(counter, [0, 0.0])
@@ -250,14 +252,24 @@ def trace_summary(directory, steps, pmc_steps, bench=None):
     if bench:
         b = json.load(open(bench))
         r = b["roofline"]
-        k = r["kernel"]
-        lines += ["", "bench.py (HIP events on the library stream, %d steps): %.3f matmuls/s, %.3f ms/step; dominant "
-                  "kernel %s: %.2f us per launch (trace above: %.2f us), %.0f algorithmic MB per launch." % (
-                      b["steps"], b["value"], b["ms_per_step"], k, r["avg_launch_us"],
-                      agg[k][1] / agg[k][0] / 1e3 if k in agg else float("nan"), r["avg_bytes_per_launch"] / 1e6)]
+        dk = r["dominant_kernel"]
+        k = dk["kernel"]
+        lines += ["", "bench.py (HIP events on the library stream, %d steps): %.3f matmuls/s, %.3f ms/step; the step's "
+                  "minimum HBM bytes (key switch inputs, outputs and keys, no key reuse) %.2f GB, i.e. %.0f GB/s = "
+                  "%.3f of 8 TB/s (%.3f with key reuse); dominant kernel %s: %.2f us per launch (trace above: "
+                  "%.2f us), %.0f MB per launch." % (
+                      b["steps"], b["value"], b["ms_per_step"], r["alg_bytes_per_step"] / 1e9, r["achieved"],
+                      r["frac"], r["key_reuse"]["frac"], k, dk["avg_launch_us"],
+                      agg[k][1] / agg[k][0] / 1e3 if k in agg else float("nan"), dk["avg_bytes_per_launch"] / 1e6)]
     lines += ["", "Counter scale factors from the closing plain copy of 256 MiB each way: " +
               ", ".join("%s x%.3f" % (k, v) for k, v in scales.items() if v), "",
+              "HBM bytes per step, every kernel of the timed steps (counters, scaled): %.2f GB (FETCH %.2f, WRITE "
+              "%.2f)." % (sum(step_total.values()) / 1e9, step_total.get("FETCH_SIZE", 0) / 1e9,
+                          step_total.get("WRITE_SIZE", 0) / 1e9), "",
               "traffic_json: " + json.dumps({"bytes_per_launch": {k: round(v) for k, v in per_launch.items()},
+                                             "bytes_per_step": round(sum(step_total.values())) if len(step_total) == 2
+                                             else None,
+                                             "sources_sha256_all": kernel_sources_digest(),
                                              "avg_us": {k: round(a[1] / a[0] / 1e3, 2) for k, a in agg.items()
                                                         if k in dict(PROFILE_CLASSES).values()},
                                              "sources_sha256": {k: kernel_sources_digest(k) for k in per_launch}})]
@@ -277,6 +289,38 @@ def recorded_traffic(cls):
     except OSError:
         pass
     return None
+
+
+def recorded_step_traffic():
+    """HBM bytes per step (every kernel of the step, counters) from the committed profile, if taken on these
+    sources."""
+    try:
+        with open(PROFILE_FILE) as fh:
+            for line in fh:
+                if line.startswith("traffic_json: "):
+                    rec = json.loads(line[len("traffic_json: "):])
+                    if rec.get("sources_sha256_all") == kernel_sources_digest() and "bytes_per_step" in rec:
+                        return rec["bytes_per_step"]
+    except OSError:
+        pass
+    return None
+
+
+def step_algorithmic_bytes(ctx, items, key_reads):
+    """The method's minimum HBM bytes for the key switches the step ran: each key switch at level l reads its
+    input and writes its output (2 (l + 1) limbs each) and reads a key of 2 beta (l + 1 + K) limbs (beta digits of
+    alpha primes, K special primes).  Without key reuse every key switch reads its key; with reuse (what the
+    lockstep batches do) a key is read once per batch that shares it.  Returns (no_reuse, with_reuse) bytes."""
+    alpha = -(-ctx.num_q // ctx.dnum)
+    io = key_all = key_once = 0
+    for lv, (m, kr) in enumerate(zip(items, key_reads)):
+        l = lv + 1
+        key = 2 * (-(-l // alpha)) * (l + ctx.num_p)
+        io += m * 4 * l
+        key_all += m * key
+        key_once += kr * key
+    limb = ctx.n * 8
+    return (io + key_all) * limb, (io + key_once) * limb
 
 
 # The paper's Table 4 shapes (a, b, c) with s0 = a, its A40 seconds per call (DiagABT, DiagATB on the level(A) >=
@@ -653,8 +697,9 @@ def train_bench(steps, rows=A_ROWS, classes=CLASSES):
                  % (A_ROWS, CLASSES, C_PAD, S0, ctx.slots // S0), "lr": lr}}), flush=True)
 
 
-def cpu_baseline(X, W, gpu_abt_coeffs):
-    """The oracle (never tuned) on one full DiagABT of the same workload."""
+def cpu_baseline(X, W, PY, gpu_coeffs):
+    """The oracle (never tuned) on one full step of the same workload: one DiagABT and one DiagATB, on all
+    threads; and one rotation at level 11, median of three, on all threads and on one."""
     from oracle import ckks
     from oracle import matrix as mx
     from paper_2403_14111_amd import inputs
@@ -664,12 +709,14 @@ def cpu_baseline(X, W, gpu_abt_coeffs):
     a, e = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(0), prm.dnum, prm.all_primes, prm.n)
     ev.gen_relin_key(a, e)
     s1 = prm.slots // S0
-    steps = mx.rotation_steps("abt", C_PAD, S0, s1)
+    steps = set(mx.rotation_steps("abt", C_PAD, S0, s1)) | set(mx.rotation_steps("atb", C_PAD, S0, s1))
     for g in sorted(set(prm.galois_rot(r) for r in steps) | {prm.galois_conj}):
         a, e = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(1, g), prm.dnum, prm.all_primes, prm.n)
         ev.gen_galois_key(g, a, e)
     Wp = np.zeros((C_PAD, FEAT))
     Wp[:CLASSES] = W
+    PYp = np.zeros((A_ROWS, C_PAD))
+    PYp[:, :CLASSES] = PY
 
     def enc(blocks, first_index):
         out = []
@@ -681,18 +728,28 @@ def cpu_baseline(X, W, gpu_abt_coeffs):
 
     xb = enc(mx.block_encode(X, S0, s1)[0], 0)
     wb = enc(mx.block_encode(mx.tile_vertical(Wp, S0), S0, s1)[0], 100)
+    pb = enc(mx.block_encode(mx.tile_horizontal(PYp, s1), S0, s1)[0], 200)
     threads = ckks.LIB.orc_max_threads()
     t0 = time.perf_counter()
-    out = mx.diag_abt(ev, [xb], wb, C_PAD, S0, s1, 1.0)
-    dt = time.perf_counter() - t0
-    same = gpu_abt_coeffs is not None and np.array_equal(gpu_abt_coeffs, out[0].c)
-    # one rotation at level 11, on all threads and on one
+    out_abt = mx.diag_abt(ev, [xb], wb, C_PAD, S0, s1, 1.0)
+    t_abt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    out_atb = mx.diag_atb(ev, [pb], [xb], C_PAD, S0, s1, 1.0)
+    t_atb = time.perf_counter() - t0
+    same = None
+    if gpu_coeffs is not None:
+        same = bool(np.array_equal(gpu_coeffs[0], out_abt[0].c) and
+                    all(np.array_equal(g, o.c) for g, o in zip(gpu_coeffs[1], out_atb)))
+    # one rotation at level 11, median of three, on all threads and on one
     hrot = {}
     for n in (threads, 1):
         ckks.LIB.orc_set_threads(n)
-        t1 = time.perf_counter()
-        ev.rot(xb[0], 1)
-        hrot[n] = time.perf_counter() - t1
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            ev.rot(xb[0], 1)
+            ts.append(time.perf_counter() - t1)
+        hrot[n] = float(np.median(ts))
     ckks.LIB.orc_set_threads(threads)
     model = "unknown"
     try:
@@ -700,11 +757,12 @@ def cpu_baseline(X, W, gpu_abt_coeffs):
             model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return dict(value=1.0 / dt, unit="matmuls/s", cores=threads, kind="oracle",
-                sample="one full DiagABT of the forward product (128x768x16, N=2^16, level 11): %.1f s on %d "
-                       "OpenMP threads" % (dt, threads),
-                seconds=dt, cpu_model=model, nproc=os.cpu_count(),
-                hrot_level11_s={"threads_%d" % threads: round(hrot[threads], 3), "one_thread": round(hrot[1], 3)}), same
+    return dict(value=2.0 / (t_abt + t_atb), unit="matmuls/s", cores=threads, kind="oracle",
+                sample="one full step of the workload, once: DiagABT (forward, 128x768x16) %.1f s and DiagATB "
+                       "(gradient) %.1f s, N=2^16, level 11, on %d OpenMP threads" % (t_abt, t_atb, threads),
+                seconds={"abt": round(t_abt, 2), "atb": round(t_atb, 2)}, cpu_model=model, nproc=os.cpu_count(),
+                hrot_level11_s={"threads_%d" % threads: round(hrot[threads], 3), "one_thread": round(hrot[1], 3),
+                                "of": "median of 3"}), same
 
 
 def main():
@@ -843,7 +901,8 @@ def main():
     PYp = np.hstack([PY, np.zeros((A_ROWS, C_PAD - CLASSES))])
     ref_g = np.tile(PYp.T @ X, (S0 // C_PAD, 1))
     err_g = float(np.max(np.abs(res_g[:S0, :FEAT] - ref_g)))
-    gpu_abt_coeffs = ctx.ct_to_coeff(ctx.mat_block(y, 0))
+    gpu_coeffs = (ctx.ct_to_coeff(ctx.mat_block(y, 0)), [ctx.ct_to_coeff(ctx.mat_block(g, b))
+                                                         for b in range(g.n_rb * g.n_cb)])
 
     # ---- per-kernel timing (HIP events on the library's stream), same K steps
     log("kernel timing pass")
@@ -860,21 +919,40 @@ def main():
     elapsed_ev = time.perf_counter() - t_ev
     kt = ctx.timing_get()
     ctx.timing_enable(False)
-    counters_step = None
     ctx.reset_counters()
     eager_step()
     torch.cuda.synchronize()
     counters_step = ctx.counters()
+    ks_items, ks_reads = ctx.ks_counts()
+    # the step against the method's minimum traffic: the key switches' inputs, outputs and keys over the step time
+    alg_all, alg_reuse = step_algorithmic_bytes(ctx, ks_items, ks_reads)
+    step_s = ms_per_step * 1e-3
+    achieved = alg_all / step_s / 1e9
+    traffic = recorded_step_traffic()
+    # the busiest kernel class: the bytes its launches move (pipeline, not method) over its HIP-event time
     dom = max(kt, key=lambda k: kt[k]["ms"])
     d = kt[dom]
     avg_ms = d["ms"] / max(d["launches"], 1)
     avg_bytes = d["bytes"] / max(d["launches"], 1)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = recorded_traffic(dom)
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    avg_launch_us=round(avg_ms * 1e3, 2), avg_bytes_per_launch=avg_bytes,
-                    launches_per_step=d["launches"] // args.steps)
+    dom_gbs = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = dict(
+        bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+        achieved=round(achieved, 1), frac=round(achieved / HBM_PEAK_GBS, 4),
+        traffic=traffic,
+        basis="per step: the %d key switches' minimum HBM bytes (input and output ciphertexts, one key read per key "
+              "switch) over ms_per_step; traffic = every kernel's FETCH_SIZE + WRITE_SIZE per step from the "
+              "committed counter profile (null if the sources changed since)" % sum(ks_items),
+        alg_bytes_per_step=alg_all,
+        traffic_over_alg=round(traffic / alg_all, 3) if traffic else None,
+        key_switches_by_level={str(lv): m for lv, m in enumerate(ks_items) if m},
+        key_reuse=dict(alg_bytes_per_step=alg_reuse, achieved=round(alg_reuse / step_s / 1e9, 1),
+                       frac=round(alg_reuse / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                       key_reads_by_level={str(lv): m for lv, m in enumerate(ks_reads) if m}),
+        dominant_kernel=dict(kernel=dom, achieved=round(dom_gbs, 1), frac=round(dom_gbs / HBM_PEAK_GBS, 4),
+                             traffic=recorded_traffic(dom), avg_launch_us=round(avg_ms * 1e3, 2),
+                             avg_bytes_per_launch=avg_bytes, launches_per_step=d["launches"] // args.steps,
+                             note="bytes the kernel's launches read and write (the pipeline's rows) over their "
+                                  "HIP-event time"))
     kernel_share = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3), launches_per_step=v["launches"] // args.steps,
                             gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
                     for k, v in kt.items() if v["launches"]}
@@ -909,12 +987,12 @@ def main():
     hrot_batched["distinct_key_count"] = len(set(distinct))
     del batch, out
 
-    # ---- CPU baseline (the oracle) on one DiagABT of the same workload
+    # ---- CPU baseline (the oracle) on one step of the same workload
     cpu = None
     bitexact = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu, bitexact = cpu_baseline(X, W, gpu_abt_coeffs)
+        cpu, bitexact = cpu_baseline(X, W, PY, gpu_coeffs)
 
     lat_ms = np.array(lat) * 1e3
     line = {
@@ -941,13 +1019,13 @@ def main():
                           "the other kernels in 64-bit integers",
         },
         "roofline": roofline,
-        "cpu_baseline": {k: v for k, v in (cpu or {}).items() if k != "seconds"} if cpu else None,
+        "cpu_baseline": cpu,
         "hrot_per_s": round(hrot_s, 1),
         "hrot_batched_per_s": dict(hrot_batched, batch=HROT_BATCH, level=LEVEL),
         "step_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
         "step_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
         "max_abs_err": {"abt": err_y, "atb": err_g, "bound": 2.0 ** -18},
-        "bitexact_vs_oracle_abt": bitexact,
+        "bitexact_vs_oracle": bitexact,
         "kernels": kernel_share,
         "timing_pass_ms_per_step": round(1e3 * elapsed_ev / args.steps, 3),
         "ops_per_step": counters_step,

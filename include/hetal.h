@@ -365,6 +365,13 @@ int hetal_nag_step(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat* x, c
  * transforms, [7] kernel launches. */
 int hetal_counters_get(const hetal_ctx* ctx, int64_t* out8);
 int hetal_counters_reset(hetal_ctx* ctx);
+/* Key switches since the last hetal_counters_reset, by input level: items[l] key switches of ciphertexts at
+ * level l, and key_reads[l] the key-switching keys they read (once per batch of items that share a key, once
+ * per item otherwise).  They fix the minimum HBM traffic of the work (Sec. 5.1 prices the operations, the
+ * key switch dominating): each item reads its input and writes its output, 2 (l + 1) limbs each, and each key
+ * read moves 2 beta (l + 1 + num_p) limbs, beta = the digits at level l.  Host arrays of `levels` entries
+ * (levels above the chain read 0). */
+int hetal_ks_counts(const hetal_ctx* ctx, int64_t* items, int64_t* key_reads, int levels);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds two event records per launch while enabled).  There are

@@ -806,6 +806,11 @@ struct SideJoin {
       ctx->c.counters[i] += ctx->side->counters[i];
       ctx->side->counters[i] = 0;
     }
+    for (int i = 0; i < MAX_PRIMES; ++i) {
+      ctx->c.ks_items[i] += ctx->side->ks_items[i];
+      ctx->c.ks_key_reads[i] += ctx->side->ks_key_reads[i];
+      ctx->side->ks_items[i] = ctx->side->ks_key_reads[i] = 0;
+    }
   }
 };
 
@@ -1071,6 +1076,18 @@ int hetal_counters_reset(hetal_ctx* ctx) {
   return guarded([&] {
     need(ctx, HETAL_E_INVALID_ARG, "null context");
     std::memset(ctx->c.counters, 0, sizeof(ctx->c.counters));
+    std::memset(ctx->c.ks_items, 0, sizeof(ctx->c.ks_items));
+    std::memset(ctx->c.ks_key_reads, 0, sizeof(ctx->c.ks_key_reads));
+  });
+}
+
+int hetal_ks_counts(const hetal_ctx* ctx, int64_t* items, int64_t* key_reads, int levels) {
+  return guarded([&] {
+    need(ctx && items && key_reads && levels >= 0, HETAL_E_INVALID_ARG, "null argument");
+    for (int i = 0; i < levels; ++i) {
+      items[i] = i < MAX_PRIMES ? ctx->c.ks_items[i] : 0;
+      key_reads[i] = i < MAX_PRIMES ? ctx->c.ks_key_reads[i] : 0;
+    }
   });
 }
 

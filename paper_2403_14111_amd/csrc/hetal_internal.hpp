@@ -204,6 +204,10 @@ struct Context {
 
   Pool pool;
   int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // key switches per input level, and the key-switching keys read for them (one per lockstep batch that shares
+  // a key, one per item otherwise): the inputs of the method's minimum HBM traffic
+  int64_t ks_items[MAX_PRIMES] = {};
+  int64_t ks_key_reads[MAX_PRIMES] = {};
 
   // Optional timing: events recorded on `stream` around every kernel launch.
   bool timing = false;

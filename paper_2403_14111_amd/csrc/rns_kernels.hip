@@ -512,6 +512,8 @@ void key_switch(Context& c, const KsJob& job) {
   for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = i < m ? job.item[i].g : 1;
   ntt_forward(c, conv, conv_words, m, ct_rows, NttSrc{}, &epi, fuse_down ? &cv : nullptr);
   c.counters[5] += m;
+  c.ks_items[level] += m;
+  c.ks_key_reads[level] += shared ? 1 : m;
 }
 
 void k_add(Context& c, const u64* a, const u64* b, u64* out, int rows, int period) {

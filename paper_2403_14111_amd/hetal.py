@@ -131,6 +131,7 @@ _SIGS = {
                                       _intp]),
     "hetal_counters_get": (ctypes.c_int, [_vp, _i64p]),
     "hetal_counters_reset": (ctypes.c_int, [_vp]),
+    "hetal_ks_counts": (ctypes.c_int, [_vp, _i64p, _i64p, ctypes.c_int]),
     "hetal_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hetal_timing_classes": (ctypes.c_int, []),
     "hetal_timing_get": (ctypes.c_int, [_vp, _dblp, _i64p, _dblp]),
@@ -280,6 +281,14 @@ class Context:
         _check(_lib.hetal_counters_get(self._h, out.ctypes.data_as(_i64p)))
         return dict(zip(["rot", "conj", "mult", "cmult", "rescale", "keyswitch", "ntt_limbs", "launches"],
                         [int(x) for x in out]))
+
+    def ks_counts(self):
+        """Key switches by input level since the last reset: (items, key_reads), each a list per level."""
+        items = np.zeros(self.max_level + 1, dtype=np.int64)
+        reads = np.zeros(self.max_level + 1, dtype=np.int64)
+        _check(_lib.hetal_ks_counts(self._h, items.ctypes.data_as(_i64p), reads.ctypes.data_as(_i64p),
+                                    self.max_level + 1))
+        return [int(v) for v in items], [int(v) for v in reads]
 
     def reset_counters(self):
         _check(_lib.hetal_counters_reset(self._h))

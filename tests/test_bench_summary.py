@@ -73,3 +73,36 @@ def test_timed_window_skips_short_accidental_periods():
     assert (lo, hi, p) == (3, len(names), 5)
     lo, hi, p = bench.timed_window(names, 2)
     assert p == 5 and lo == len(names) - 10
+
+
+def test_summary_records_the_whole_step_traffic(tmp_path):
+    """bytes_per_step sums every kernel of the counter runs' timed steps (not only the classified ones), scaled."""
+    d = str(tmp_path)
+    for sub in ("trace", "FETCH_SIZE", "WRITE_SIZE"):
+        os.makedirs(os.path.join(d, sub))
+    write_trace(os.path.join(d, "trace", "t_kernel_trace.csv"), steps=3)
+    epi = STEP[0][0]
+    write_pmc(os.path.join(d, "FETCH_SIZE", "p_counter_collection.csv"), "FETCH_SIZE", 2, {epi: 1000.0}, 131072.0)
+    write_pmc(os.path.join(d, "WRITE_SIZE", "p_counter_collection.csv"), "WRITE_SIZE", 2, {epi: 500.0}, 262144.0)
+    rec = json.loads(bench.trace_summary(d, steps=3, pmc_steps=2).split("traffic_json: ")[1])
+    assert rec["bytes_per_step"] == ((1000 + 4) * 2 + (500 + 4) * 1) * 1024
+    assert rec["sources_sha256_all"] == bench.kernel_sources_digest()
+
+
+class _Ctx:
+    n, num_q, num_p, dnum = 1 << 16, 12, 3, 4
+
+
+def test_step_algorithmic_bytes_follow_the_key_switch_accounting():
+    """One key switch at level 11 (l = 12): ciphertext in and out 4 l limbs, key 2 beta (l + K) = 2 * 4 * 15 limbs
+    (60 MiB), 84 MiB in all; level 8 (l = 9): beta = 3, key 36 MiB, 54 MiB in all.  With key reuse a batch of 8
+    that shares a key reads it once."""
+    items = [0] * 12
+    reads = [0] * 12
+    items[11], reads[11] = 1, 1
+    mib = 1 << 20
+    assert bench.step_algorithmic_bytes(_Ctx, items, reads) == (84 * mib, 84 * mib)
+    items[11], reads[11] = 0, 0
+    items[8], reads[8] = 8, 1
+    no_reuse, reuse = bench.step_algorithmic_bytes(_Ctx, items, reads)
+    assert no_reuse == 8 * 54 * mib and reuse == 8 * 18 * mib + 36 * mib

@@ -27,7 +27,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def deep():
-    steps = sorted(set(sm.rotation_steps(10, S1)) | set(sm.rotation_steps(3, S1)))
+    steps = sorted(set(sm.rotation_steps(10, S1)) | set(sm.rotation_steps(3, S1)) | set(sm.rotation_steps(100, S1)))
     note("n12l12 context + keys (%d rotations)" % len(steps))
     ctx, sk, keys = make_gpu("n12l12", seed=SEED, rot_steps=steps, conj=False)
     ev = make_oracle("n12l12", seed=SEED, rot_steps=steps, conj=False)
@@ -116,9 +116,10 @@ def test_poly_eval_without_levels_needs_a_refresh(deep):
     assert ei.value.name == "E_LEVEL"
 
 
-@pytest.mark.parametrize("c", [10, 3])
+@pytest.mark.parametrize("c", [10, 3, 100])
 def test_softmax_bit_exact(deep, c):
-    """The whole Alg. softmax on a 20 x c matrix (two row blocks), refreshes included, word for word."""
+    """The whole Alg. softmax on a 20 x c matrix (two row blocks), refreshes included, word for word.  c = 100 pads
+    to c' = 128 = s1: seven Amax rounds and rotations up to 64 inside one period."""
     ctx, sk, keys, ev = deep
     note("approx c=%d" % c)
     cp = mx.next_pow2(c)
@@ -174,3 +175,31 @@ def test_softmax_full_ring_bench_shape():
     want[:, :10] = sm.asoftmax_rows(M, prm)
     assert np.abs(res[:128] - np.tile(want, (1, s1 // 16))).max() < 1e-4
     assert np.abs(res[:128, :10] - sm.softmax_rows(M)).max() < 0.03
+
+
+def test_softmax_config3_full_ring_bit_exact():
+    """N = 2^16 at the survey's config 3 shape: 256 x 100 logits in [-64, 64] -> c' = 128, s0 = 256, s1 = 128 (one
+    block, the period filling the row), refreshes included, word for word against the oracle (about a minute of
+    oracle time)."""
+    s0, c, cp = 256, 100, 128
+    s1 = 32768 // s0
+    steps = sm.rotation_steps(c, s1)
+    note("config 3 context + keys (%d rotations), GPU and oracle" % len(steps))
+    ctx, sk, keys = make_gpu("n16l12", seed=2500, rot_steps=steps, conj=False)
+    ev = make_oracle("n16l12", seed=2500, rot_steps=steps, conj=False)
+    M = inputs.logits(85, 256, c, 64.0)
+    gm, oblocks = enc_mat_both(ctx, sk, ev, M, s0, 8, 2, cp, seed=96)
+    assert gm.n_rb * gm.n_cb == 1
+    exp_c = aexp_coeffs()
+    gr = gpu_refresher(ctx, sk, 2501)
+    note("config 3 approx on the GPU")
+    gout, nref = ctx.softmax_approx(keys, gm, c, params=softmax_params_with(exp_c), refresh=gr)
+    note("config 3 approx in the oracle")
+    prm = sm.SoftmaxParams()
+    oout, onref = sm.asoftmax_blocks(ev, [row[0] for row in oblocks], c, s0, s1, prm, exp_c, ev.prm.q,
+                                     ev.prm.max_level, oracle_refresher(ev, 2501))
+    assert nref == onref == gr.calls[0]
+    assert gout.level == oout[0].level and gout.scale == oout[0].scale
+    compare_blocks(ctx, gout, oout)
+    res = ctx.mat_decrypt(sk, gout)[:256, :c]
+    assert np.abs(res - sm.asoftmax_rows(M, prm)).max() < 1e-4

@@ -84,3 +84,35 @@ def test_nag_step_full_ring():
     want_w, want_v = tr.nag_step_plain(X, Y, W, V, lr, gamma, lambda L: sm.asoftmax_rows(L, prm))
     assert np.abs(ctx.mat_decrypt(sk, gW)[:c, :769] - want_w).max() < 1e-4
     assert np.abs(ctx.mat_decrypt(sk, gV)[:c, :769] - want_v).max() < 1e-4
+
+
+def test_nag_step_config3_full_ring():
+    """N = 2^16, the survey's config 3: 256 x 769 features (with the bias column), 100 classes -> c' = 128, s0 = 256
+    (one block row, s1 = 128 = c'), against the plain update with the same softmax approximation."""
+    s0, c, cp = 256, 100, 128
+    s1 = 32768 // s0
+    steps = sorted(set(sm.rotation_steps(c, s1)) | set(mx.rotation_steps("abt", cp, s0, s1)) |
+                   set(mx.rotation_steps("atb", cp, s0, s1)) |
+                   set(mx.rotation_steps("atb", cp, s0, s1, pru=True)))
+    note("config 3 context + keys (%d rotations)" % len(steps))
+    ctx, sk, keys = make_gpu("n16l12", seed=2700, rot_steps=steps)
+    X = np.hstack([inputs.features(1003, 256, 768), np.ones((256, 1))])
+    Y = np.eye(c)[inputs.labels(1003, 256, c)]
+    W = inputs.weights(1003, c, 769)
+    V = inputs.weights(1004, c, 769)
+
+    def enc(M, tiling, seed):
+        nb = int(np.prod(ctx.mat_blocks(M.shape[0], M.shape[1], s0, tiling, cp)))
+        r = [inputs.encryption_randomness(seed, b, ctx.q[:12], ctx.n) for b in range(nb)]
+        return ctx.mat_encrypt(sk, M, s0, 11, 2.0 ** 40, np.stack([x[0] for x in r]), np.stack([x[1] for x in r]),
+                               tiling=tiling, c=cp)
+    gx, gy, gw, gv = enc(X, 0, 301), enc(Y, 2, 302), enc(W, 1, 303), enc(V, 1, 304)
+    lr, gamma = 1.0 / 256, tr.nag_gamma(2)
+    note("config 3 step")
+    gr = ctx.refresher(sk, lambda i: inputs.refresh_randomness(2701, i, ctx.q, ctx.n))
+    gW, gV, nref = ctx.nag_step(keys, gx, gy, gw, gv, c, lr, gamma, refresh=gr)
+    assert nref > 0
+    prm = sm.SoftmaxParams()
+    want_w, want_v = tr.nag_step_plain(X, Y, W, V, lr, gamma, lambda L: sm.asoftmax_rows(L, prm))
+    assert np.abs(ctx.mat_decrypt(sk, gW)[:c, :769] - want_w).max() < 1e-4
+    assert np.abs(ctx.mat_decrypt(sk, gV)[:c, :769] - want_v).max() < 1e-4
