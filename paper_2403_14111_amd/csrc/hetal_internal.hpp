@@ -314,6 +314,9 @@ struct NttConv {
 };
 constexpr int MAX_FUSED_CONV = 4;  // conversions of more terms run as separate kernels
 
+// Between the two passes of a transform (and between the kernels of a key switch) rows hold the bit patterns of
+// exact, integer-valued doubles, not 64-bit residues: only the kernel that reads them as doubles (mid_ld in
+// ntt_device.hpp) may read such a row.  Every row a launcher hands back to its caller holds residues in [0, q).
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
                  const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr);
 // dbl: the results are stored as the bit patterns of exact doubles, the form the forward transform's fused

@@ -35,92 +35,15 @@
 //    fwd_bfly / inv_bfly).  Twiddles are doubles (8 bytes, no Shoup companion).
 #include <type_traits>
 
-#include "hetal_internal.hpp"
+#include "ntt_device.hpp"
 
 namespace hetal {
 
 namespace {
 
-constexpr int NTT_THREADS = 256;
-constexpr int NTT_R = 16;
+using namespace fp64;
 
-__device__ __forceinline__ int pad_idx(int v) { return v + (v >> 4); }
-
-// u64 below 2^53 -> double, exactly.
-__device__ __forceinline__ double u2d(u64 v) {
-#pragma clang fp contract(off)
-  return __builtin_fma((double)hi32(v), 4294967296.0, (double)lo32(v));
-}
-
-// Integer-valued double in [0, 2^53) -> u64.
-__device__ __forceinline__ u64 d2u(double v) {
-#pragma clang fp contract(off)
-  const double h = __builtin_floor(v * (1.0 / 4294967296.0));
-  const double l = __builtin_fma(-h, 4294967296.0, v);
-  return ((u64)(u32)h << 32) | (u64)(u32)l;
-}
-
-// a w mod q, exact, in (-0.75q, 1.75q), for integers |a| <= 2^51 and 0 <= w < q < 2^50.
-__device__ __forceinline__ double fmul(double a, double w, double q, double qinv) {
-#pragma clang fp contract(off)
-  const double p = a * w;
-  const double e = __builtin_fma(a, w, -p);
-  const double f = __builtin_floor(p * qinv);
-  return __builtin_fma(-f, q, p) + e;
-}
-
-// v mod q, exact, in [0, q], for integers |v| < 2^52.
-__device__ __forceinline__ double fred(double v, double q, double qinv) {
-#pragma clang fp contract(off)
-  return __builtin_fma(-__builtin_floor(v * qinv), q, v);
-}
-
-// [0, q] -> [0, q)
-__device__ __forceinline__ double ffix(double v, double q) { return v >= q ? v - q : v; }
-
-// A transform's first pass hands its results to the second as the bit patterns of the doubles (values in
-// [0, q]): nothing else reads them, so neither side converts.
-__device__ __forceinline__ u64 mid_st(double v) { return (u64)__double_as_longlong(v); }
-__device__ __forceinline__ double mid_ld(u64 w) { return __longlong_as_double((long long)w); }
-
-// Cooley-Tukey butterfly: T = y w, then x + T and x - T.  Reduced (LAZY false): inputs and outputs in
-// [0, q].  LAZY (moduli below 2^42 only): nothing is reduced; with |y| <= 2^47 the product T lies in
-// (-0.05q, 1.05q), so each stage widens the bound by 1.05q and a pass stays far below 2^47.
-template <bool LAZY>
-__device__ __forceinline__ void fwd_bfly(double& x, double& y, double w, double q, double qinv) {
-#pragma clang fp contract(off)
-  const double t = fmul(y, w, q, qinv);
-  if (LAZY) {
-    y = x - t;
-    x = x + t;
-  } else {
-    y = fred(x - t, q, qinv);
-    x = fred(x + t, q, qinv);
-  }
-}
-
-// Gentleman-Sande butterfly: x + y, and (x - y) w.  Reduced: [0, q] in and out.  LAZY (moduli below
-// 2^42): nothing is reduced; the sum doubles the bound per stage, so a pass reduces once halfway.
-template <bool LAZY>
-__device__ __forceinline__ void inv_bfly(double& x, double& y, double w, double q, double qinv) {
-#pragma clang fp contract(off)
-  const double s = x + y;
-  const double d = x - y;
-  if (LAZY) {
-    y = fmul(d, w, q, qinv);
-    x = s;
-  } else {
-    y = fred(fmul(d, w, q, qinv), q, qinv);
-    x = fred(s, q, qinv);
-  }
-}
-
-// Moduli below this take the lazy butterflies.
-constexpr double LAZY_MODULUS = 4398046511104.0;  // 2^42
-
-// Workgroups are numbered so that the batch items sharing one (row, chunk) --
-// and so one twiddle range -- run back to back on the same XCD (workgroups
-// are dealt to the 8 XCDs round robin), where the twiddles stay in its L2.
+// Arguments of one pass over `groups` (row, chunk) pairs of `batch` items (numbered as wg_item / wg_group).
 struct PassArgs {
   u64* base;
   size_t batch_stride;
@@ -131,26 +54,6 @@ struct PassArgs {
   int batch;
   int wg_per_poly;
 };
-
-// Transpose through LDS: x[u] is stored at word widx(u) of the workgroup's buffer, then x[u] is
-// loaded from word ridx(u).  The 64-bit values travel as two 32-bit halves through a 32-bit
-// buffer, which halves the LDS a workgroup holds.  LEAD_SYNC: the buffer was read before.
-template <bool LEAD_SYNC, class W, class R>
-__device__ __forceinline__ void lds_exchange(double (&x)[NTT_R], u32* __restrict__ ls, W widx, R ridx) {
-  if (LEAD_SYNC) __syncthreads();
-#pragma unroll
-  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = lo32((u64)__double_as_longlong(x[u]));
-  __syncthreads();
-  u32 lo[NTT_R];
-#pragma unroll
-  for (int u = 0; u < NTT_R; ++u) lo[u] = ls[ridx(u)];
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = hi32((u64)__double_as_longlong(x[u]));
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < NTT_R; ++u) x[u] = __longlong_as_double((long long)(((u64)ls[ridx(u)] << 32) | lo[u]));
-}
 
 // One pass of 2^L-point sub-transforms.  Two shapes occur:
 //  * strided (pass A, CONTIG false): the 256 columns of the limb seen as a 2^L x 256 matrix, stages
@@ -194,9 +97,8 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 
   const int n = 1 << log_n;
   const int wg = blockIdx.x;
-  const int per_block = 8 * pa.batch;
-  const int item = (wg % per_block) >> 3;
-  const int group = (wg / per_block) * 8 + (wg & 7);
+  const int item = wg_item(wg, pa.batch);
+  const int group = wg_group(wg, pa.batch);
   if (group >= pa.groups) return;
   const int rowi = group / pa.wg_per_poly;
   const int chunk = group - rowi * pa.wg_per_poly;
