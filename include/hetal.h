@@ -60,7 +60,7 @@ typedef struct hetal_keys hetal_keys;
  * descending order, and the num_p special primes p_0.. the largest primes
  * below q_0; all are 1 mod 2N (q0_bits, q_bits <= 50).  dnum digits of
  * alpha = ceil(num_q / dnum) consecutive primes are used for hybrid key
- * switching.  Limits: num_q + num_p <= 32, alpha <= 8, num_p <= 8. */
+ * switching.  Limits: num_q + num_p <= 32, alpha <= 4, num_p <= 4, at most 8 digits. */
 typedef struct {
   int log_n;
   int num_q;

@@ -173,7 +173,8 @@ void hetal_keys_destroy(hetal_keys* keys) {
   delete keys;
 }
 
-static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint64_t* a_host, const int64_t* e_host) {
+static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint64_t* a_host, const int64_t* e_host,
+                            u32 g) {
   check_uniform(c, a_host, c.dnum, c.nprimes);
   const size_t rows_words = (size_t)c.nprimes * c.n;
   Tmp a(c.pool, (size_t)c.dnum * rows_words);
@@ -187,7 +188,7 @@ static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint6
   ntt_forward(c, e, rows_words, c.dnum, all);
   u64* key = nullptr;
   if (hipMalloc(&key, c.key_words() * 8) != hipSuccess) fail(HETAL_E_OOM, "key allocation");
-  k_keygen(c, a, e, s, sp, key);
+  k_keygen(c, a, e, s, sp, key, g);
   HCHECK(hipStreamSynchronize(c.stream));
   return key;
 }
@@ -198,7 +199,7 @@ int hetal_keys_gen_relin(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, c
     Context& c = ctx->c;
     Tmp s2(c.pool, (size_t)c.nprimes * c.n);
     k_mul_rows(c, sk->key.s, sk->key.s, s2, c.nprimes, c.nprimes, c.nprimes);
-    u64* key = make_switch_key(c, sk->key.s, s2, a, e);
+    u64* key = make_switch_key(c, sk->key.s, s2, a, e, 1);
     if (keys->set.relin) (void)hipFree(keys->set.relin);
     keys->set.relin = key;
   });
@@ -212,7 +213,7 @@ int hetal_keys_gen_galois(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, 
     need(galois % 2 == 1 && galois < 2ull * c.n, HETAL_E_INVALID_ARG, "Galois element must be odd and below 2N");
     Tmp sg(c.pool, (size_t)c.nprimes * c.n);
     k_galois(c, sk->key.s, sg, c.nprimes, c.nprimes, (u32)galois);
-    u64* key = make_switch_key(c, sk->key.s, sg, a, e);
+    u64* key = make_switch_key(c, sk->key.s, sg, a, e, (u32)galois);
     auto it = keys->set.galois.find((u32)galois);
     if (it != keys->set.galois.end()) (void)hipFree(it->second);
     keys->set.galois[(u32)galois] = key;

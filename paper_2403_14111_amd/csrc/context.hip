@@ -183,7 +183,10 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
   c.num_p = p.num_p;
   c.dnum = p.dnum;
   c.alpha = (p.num_q + p.dnum - 1) / p.dnum;
-  if (c.alpha > MAX_ALPHA) fail(HETAL_E_PARAMS, "too many primes per digit");
+  // the key switch's fused conversions hold one inverse-transformed row per term in registers (keyswitch.hip)
+  if (c.alpha > MAX_FUSED_CONV || c.num_p > MAX_FUSED_CONV)
+    fail(HETAL_E_PARAMS, "more than 4 primes per digit or special primes");
+  if ((c.num_q + c.alpha - 1) / c.alpha > 8) fail(HETAL_E_PARAMS, "more than 8 digits");
   c.nprimes = p.num_q + p.num_p;
   c.stream = stream;
 

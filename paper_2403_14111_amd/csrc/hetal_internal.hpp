@@ -91,6 +91,20 @@ inline int ntt_twiddle_slot(int x, int log_n) {
   return base + (c << l) + (((k & ((1 << m) - 1)) << 4) | (k >> m));
 }
 
+// g^-1 modulo 2N (a power of two; g odd): g^(N - 1), since the odd residues mod 2N form a group of order N.
+inline u32 galois_inverse(u32 g, u32 two_n) {
+  u64 r = 1, b = g % two_n;
+  for (u32 e = two_n / 2 - 1; e; e >>= 1, b = b * b % two_n)
+    if (e & 1) r = r * b % two_n;
+  return (u32)r;
+}
+
+// Device address of a field of a device-resident table (address arithmetic only, nothing is read).
+template <class T, class S>
+const T* device_field(const S* table, size_t offset) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(table) + offset);
+}
+
 struct PrimeConsts {
   u64 ninv, ninv_sh;
   u64 w1ninv, w1ninv_sh;
@@ -269,23 +283,29 @@ struct NttSrc {
 //   out[p][i] = (a[p][i] - x) cst[i] + add0[i](gathered through tau_g, p = 0) + add1[i](p = 1) + addx[p][i]
 // mod q_i, every addend optional.  ModDown ends this way (a = the Q part of the key inner product,
 // cst = P^-1 mod q_i) and so does the rescale (a = the input, cst = q_l^-1 mod q_i).
+//
+// A key switch by tau_g (g != 1 for the item) hands over a and x in the frame before the automorphism (the keys
+// are stored permuted by tau_g^-1): the epilogue then computes (a - x) cst, adds add0 there if `gather` (the
+// input's c0, which the result takes as tau_g(c0)), moves the sum to its place under tau_g, and adds the other
+// addends after that.  Without a permutation `gather` is ignored.
 struct NttEpilogue {
   const u64* a = nullptr;
   size_t a_stride = 0;       // words between items
   int a_poly_rows = 0;       // rows between a[0][i] and a[1][i]
+  int a_dbl = 0;             // a holds doubles (the key inner product's rows), not residues
   int l = 0;                 // limbs per output polynomial
-  const u64* cst = nullptr;  // device arrays indexed by prime
-  const u64* cst_sh = nullptr;
+  const u64* cst = nullptr;  // device array indexed by prime
   u64* out = nullptr;
   size_t out_stride = 0;
   const u64* add0 = nullptr;  // [l][N] per item
   size_t add0_stride = 0;
-  int gather = 0;            // add0 read at the Galois source of each position
+  int gather = 0;            // add0 is tau_g's input (added before the permutation)
   const u64* add1 = nullptr;  // [l][N] per item
   size_t add1_stride = 0;
   const u64* addx = nullptr;  // [2][l][N] per item
   size_t addx_stride = 0;
-  u32 g[MAX_BATCH];
+  u32 g[MAX_BATCH];           // per item: the Galois element (1: no permutation)
+  u32 ginv[MAX_BATCH];        // and its inverse modulo 2N
 };
 
 // Optional basis-conversion input of a forward NTT: the first pass computes its input words instead of
@@ -323,6 +343,12 @@ void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef 
 // conversion input (NttConv) reads; only for N = 2^12 and 2^16.
 void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
                  const NttScale* row_scale = nullptr, bool dbl = false);
+// The two passes one at a time, for the key switch (keyswitch.hip), which fuses the other pass of each transform
+// into its own kernels: the inverse transform's first (contiguous) pass, stored as doubles; and the forward
+// transform's last (contiguous) pass over rows the forward strided pass stored as doubles, with the epilogue.
+void ntt_inverse_first_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src);
+void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
+                           const NttEpilogue& epi);
 
 struct KsItem {
   const u64* key;  // [dnum][2][nprimes][N]
@@ -375,7 +401,9 @@ void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int 
                      size_t out_stride);
 void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level);
 void k_decrypt(Context& c, const u64* ct, const u64* s, u64* m, int level);
-void k_keygen(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* s, const u64* sp, u64* key);
+// A switching key for s' (NTT form) in the layout key_switch reads: g is the Galois element the key serves
+// (1 for relinearisation); see keygen_kernel.
+void k_keygen(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* s, const u64* sp, u64* key, u32 g);
 
 // Encoding (double-double) and decoding.
 void k_encode(Context& c, const double* d_re, const double* d_im, int count, size_t slot_stride, int level,

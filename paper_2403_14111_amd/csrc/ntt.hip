@@ -228,7 +228,8 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       for (int u = 0; u < NTT_R; ++u) x[u] = ffix(x[u], q);
     }
     if (CONTIG && EPI) {
-      // (a - x) c + addends: a - x in [-q, q], its product in (-0.375q, 1.375q), plus two residues
+      // (a - x) c + addends: a - x in [-q, q], its product in (-0.75q, 1.75q), plus two residues: below
+      // 3.75q < 2^52 before the reduction
       lds_exchange<true>(x, ls, block, spread);
       const int p = rj.x >= epi.l ? 1 : 0;
       const int i = rj.y;
@@ -239,12 +240,30 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
                                            : (epi.add1 ? epi.add1 + item * epi.add1_stride + (size_t)i * n : nullptr);
       const u64* __restrict__ both = epi.addx ? epi.addx + item * epi.addx_stride + (size_t)rj.x * n : nullptr;
       const u32 g = epi.g[item];
-      const bool gather = p == 0 && epi.gather && g != 1;
+      const bool perm = g != 1;                           // a key switch by tau_g: x and a precede tau_g
+      const bool own_before = perm && p == 0 && epi.gather;  // tau_g's input c0: added before the permutation
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 k = sp_off + sp_step * u;
-        double v = fmul(u2d(ea[k]) - x[u], cst, q, qi);
-        if (own) v = v + u2d(own[gather ? galois_source(k, g, log_n) : k]);
+        double v = fmul((epi.a_dbl ? mid_ld(ea[k]) : u2d(ea[k])) - x[u], cst, q, qi);
+        if (own_before) v = v + u2d(own[k]);
+        x[u] = v;
+      }
+      // tau_g moves the value at position k to galois_source(k, g^-1): this chunk's 256 words all land in one
+      // chunk, so the move is an exchange through the chunk's LDS slice, and the stores stay coalesced
+      u32 out_chunk = (u32)sub << 8;
+      if (perm) {
+        const u32 gi = epi.ginv[item];
+        out_chunk = galois_source(out_chunk, gi, log_n) & ~255u;
+        auto dest = [&](int u) { return pad_idx((int)(galois_source(sp_off + sp_step * u, gi, log_n) & 255u)); };
+        lds_exchange<true>(x, ls, dest, spread);
+      }
+      const u32 o_off = out_chunk + (u32)j;
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) {
+        const u32 k = o_off + sp_step * u;
+        double v = x[u];
+        if (own && !own_before) v = v + u2d(own[k]);
         if (both) v = v + u2d(both[k]);
         eo[k] = d2u(ffix(fred(v, q, qi), q));
       }
@@ -442,6 +461,17 @@ void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef 
   launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src, nullptr, conv);
   launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, NttSrc{}, epi);
   c.counters[6] += (int64_t)rows.count * batch;
+}
+
+void ntt_inverse_first_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
+  if (rows.count == 0 || batch == 0) return;
+  launch_pass<true>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, src);
+}
+
+void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
+                           const NttEpilogue& epi) {
+  if (rows.count == 0 || batch == 0) return;
+  launch_pass<false>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, NttSrc{}, &epi);
 }
 
 void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
