@@ -293,21 +293,36 @@ __global__ void __launch_bounds__(NTT_THREADS) ks_inner_kernel(InnerArgs a, cons
 #pragma unroll
   for (int u = 0; u < NTT_R; ++u) accb[u] = acca[u] = 0.0;
 
+  // the row of digit jd: the input itself for the digit's own row (residues, NTT form), else the ModUp row
+  // after the strided pass (doubles)
+  auto row_of = [&](int jd) {
+    return jd == own_digit ? a.in + (size_t)item * a.in_stride + (size_t)t * n
+                           : a.dt + (size_t)item * a.dt_stride + ((size_t)jd * a.ext + t) * n;
+  };
+  // software pipelining: the next digit's row is loaded while this one is transformed and multiplied
+  u64 nxt[NTT_R];
+  {
+    const u64* __restrict__ r = row_of(0);
+#pragma unroll
+    for (int u = 0; u < NTT_R; ++u) nxt[u] = (r + 16 * u)[sp_off];
+  }
   for (int jd = 0; jd < a.beta; ++jd) {
     double x[NTT_R];
-    if (jd == own_digit) {
-      // the digit's own row: the input itself, in NTT form
-      const u64* __restrict__ in = a.in + (size_t)item * a.in_stride + (size_t)t * n;
+    const bool own = jd == own_digit;
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) x[u] = u2d((in + 16 * u)[sp_off]);
+    for (int u = 0; u < NTT_R; ++u) x[u] = own ? u2d(nxt[u]) : mid_ld(nxt[u]);
+    if (jd + 1 < a.beta) {
+      asm volatile("" ::: "memory");
+      const u64* __restrict__ r = row_of(jd + 1);
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) nxt[u] = (r + 16 * u)[sp_off];
+      asm volatile("" ::: "memory");
+    }
+    if (own) {
       lds_exchange<true>(x, ls, spread, block);
     } else {
-      const u64* __restrict__ d = a.dt + (size_t)item * a.dt_stride + ((size_t)jd * a.ext + t) * n;
       auto stages = [&](auto lz) {
         constexpr bool LZ = decltype(lz)::value;
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = mid_ld((d + 16 * u)[sp_off]);
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
           const int hu = 8 >> l;
@@ -423,15 +438,14 @@ dim3 ks_grid(int groups, int batch) {
   return dim3((unsigned)(padded * batch));
 }
 
-// Targets per conversion task: enough tasks to give every CU several workgroups, without recomputing the
-// sources' inverse transforms more often than needed.
+// Targets per conversion task.  A task transforms its sources once and then each target, so the fewer tasks per
+// source group the less is recomputed, but the launch needs about two workgroups per CU to fill the chip: the
+// largest count that still gives 512 workgroups, else 2 (measured at N = 2^16, level 11: one task per digit at 8
+// items, 2-3 targets per task at 1 item).
 int targets_per_task(const Context& c, int targets, int sources, int items) {
   const int colgroups = std::max(1, c.n / 4096);
-  const int want = 4 * 256;  // workgroups
-  for (int tpt = targets; tpt > 1; --tpt) {
-    const int tasks = sources * ((targets + tpt - 1) / tpt);
-    if (tasks * colgroups * items >= want && tpt <= 6) return tpt;
-  }
+  for (int tpt = targets; tpt > 2; --tpt)
+    if (sources * ((targets + tpt - 1) / tpt) * colgroups * items >= 512) return tpt;
   return std::min(targets, 2);
 }
 

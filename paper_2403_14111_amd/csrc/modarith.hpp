@@ -136,7 +136,6 @@ __device__ __forceinline__ u32 galois_source(u32 k, u32 g, int log_n) {
   return bit_reverse((e2 - 1u) >> 1, log_n);
 }
 
-// Slot of the word at NTT-domain position pos in a stored switching key: the key inner product's threads own,
-// in each 256-word chunk, block element (j, u) = word 16 j + u of the chunk and read it from slot 16 u + j.
+// Slot of the word at NTT-domain position pos in a stored switching key: the key inner product's 16 threads of a
+// 256-word chunk own element 16 j + u of the chunk (thread j, element u < 16) and read it from slot 16 u + j.
 __device__ __forceinline__ u32 key_slot(u32 pos) { return (pos & ~255u) | ((pos & 15u) << 4) | ((pos >> 4) & 15u); }
-
