@@ -103,27 +103,27 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
   double y[CNT][NTT_R];
   const int nsrc = KIND == KIND_MODUP ? a.nsrc[sg] : CNT;
   const u64* __restrict__ srcb = a.src + (size_t)item * a.src_stride;
+  // every source row's loads first, so that their latencies overlap
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
-    if (i >= nsrc) {  // a short last digit: zero terms (its constants beyond the length are zero too)
+    const u64* __restrict__ in = srcb + (size_t)(a.src_row0[sg] + (i < nsrc ? i : 0)) * n;
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) y[i][u] = 0.0;
-      continue;
-    }
+    for (int u = 0; u < NTT_R; ++u)
+      y[i][u] = i >= nsrc ? 0.0 : mid_ld(L > 4 ? (in + bl_step * u)[bl_off] : (in + sp_step * u)[sp_off]);
+  }
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    if (i >= nsrc) continue;  // a short last digit: zero terms (its constants beyond the length are zero too)
     const int row = a.src_row0[sg] + i;
     const int prime = KIND == KIND_MODUP ? row : a.num_q + i;
     const NttScale sc = a.scale[KIND == KIND_MODUP ? row : sg * CNT + i];
     const FpMod fm = fpm[prime];
     const double q = fm.q, qi = fm.qinv;
     const double* __restrict__ w = tw_inv + (size_t)prime * n;
-    const u64* __restrict__ in = srcb + (size_t)row * n;
-    double x[NTT_R];
+    double (&x)[NTT_R] = y[i];
     auto stages = [&](auto lazy) {
       constexpr bool LZ = decltype(lazy)::value;
-      asm volatile("" ::: "memory");
       if (L > 4) {
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = mid_ld((in + bl_step * u)[bl_off]);
 #pragma unroll
         for (int l = L - 1; l >= 4; --l) {
           const int half = 1 << (L - 1 - l);
@@ -136,9 +136,6 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
           for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
         }
         lds_exchange<true>(x, ls, block, spread);
-      } else {
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = mid_ld((in + sp_step * u)[sp_off]);
       }
       const double k0 = u2d(sc.s0), k1 = u2d(sc.s1);
 #pragma unroll
@@ -166,10 +163,7 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
     if (KIND == KIND_MODDOWN) {
       const double ph = __builtin_floor(q * 0.5);  // (p_k - 1) / 2: values above it are taken as negative
 #pragma unroll
-      for (int u = 0; u < NTT_R; ++u) y[i][u] = x[u] > ph ? x[u] - q : x[u];
-    } else {
-#pragma unroll
-      for (int u = 0; u < NTT_R; ++u) y[i][u] = x[u];
+      for (int u = 0; u < NTT_R; ++u) x[u] = x[u] > ph ? x[u] - q : x[u];
     }
   }
 
