@@ -85,23 +85,22 @@ def encrypt_inputs(ctx, sk, X, W, PY):
 # ---------------------------------------------------------------- profile summaries
 # rocprofv3 kernel names -> the library's timing classes (N = 2^16: every NTT pass has 256-point sub-transforms)
 PROFILE_CLASSES = [
-    ("ntt_pass_kernel<8, false, false, false, 0,", "ntt_fwd_strided"),
-    ("ntt_pass_kernel<8, false, false, false, 1,", "ntt_fwd_modup"),
-    ("ntt_pass_kernel<8, false, false, false, 2,", "ntt_fwd_moddown"),
-    ("ntt_pass_kernel<8, false, true, false,", "ntt_fwd_contig"),
-    ("ntt_pass_kernel<8, false, true, true,", "ntt_fwd_epilogue"),
-    ("ntt_pass_kernel<8, true, true, false,", "ntt_inv_contig"),
-    ("ntt_pass_kernel<8, true, false, false,", "ntt_inv_strided"),
-    ("modup_kernel", "modup"),
-    ("inner_product", "inner_product"),
-    ("moddown_conv_kernel", "moddown_conv"),
+    ("ntt_pass_kernel<8, false, false, false>", "ntt_fwd_strided"),
+    ("modconv_kernel<8, 0,", "ks_modup"),
+    ("modconv_kernel<8, 1,", "ks_moddown"),
+    ("ntt_pass_kernel<8, false, true, false>", "ntt_fwd_contig"),
+    ("ntt_pass_kernel<8, false, true, true>", "ntt_fwd_epilogue"),
+    ("ntt_pass_kernel<8, true, true, false>", "ntt_inv_contig"),
+    ("ntt_pass_kernel<8, true, false, false>", "ntt_inv_strided"),
+    ("ks_inner_kernel", "ks_inner"),
     ("rescale_", "rescale"),
 ]
 PROFILE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "kernels_n16l12_matmul_step.md")
 
 
 # the sources each profiled kernel class is built from
-KERNEL_SOURCES = {"ntt": ("ntt.hip", "modarith.hpp", "hetal_internal.hpp"),
+KERNEL_SOURCES = {"ntt": ("ntt.hip", "ntt_device.hpp", "ntt_fp64.hpp", "modarith.hpp", "hetal_internal.hpp"),
+                  "ks": ("keyswitch.hip", "ntt_device.hpp", "ntt_fp64.hpp", "modarith.hpp", "hetal_internal.hpp"),
                   "rns": ("rns_kernels.hip", "modarith.hpp", "hetal_internal.hpp")}
 
 
@@ -113,7 +112,7 @@ def kernel_sources_digest(cls=None):
     if cls is None:
         files = sorted(f for f in os.listdir(d) if f.endswith((".hip", ".hpp")))
     else:
-        files = KERNEL_SOURCES["ntt" if cls.startswith("ntt_") else "rns"]
+        files = KERNEL_SOURCES["ntt" if cls.startswith("ntt_") else "ks" if cls.startswith("ks_") else "rns"]
     h = hashlib.sha256()
     for f in files:
         h.update(f.encode())

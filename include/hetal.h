@@ -376,18 +376,19 @@ int hetal_ks_counts(const hetal_ctx* ctx, int64_t* items, int64_t* key_reads, in
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds two event records per launch while enabled).  There are
  * hetal_timing_classes() classes: [0] forward NTT, strided first pass,
- * [1] the same pass computing its input as the ModUp basis conversion,
- * [2] the same pass computing its input as the ModDown basis conversion,
- * [3] forward NTT, contiguous final pass, [4] the same pass ending a key
- * switch or rescale (it also subtracts, scales and adds: the ModDown / rescale
- * combine), [5] inverse NTT, contiguous first pass, [6] inverse NTT, strided
- * final pass, [7] ModUp basis conversion as a kernel of its own, [8] key
- * inner product, [9] ModDown basis conversion as a kernel of its own,
- * [10] rescale (the top limb's centred spread), [11] elementwise,
- * [12] encode / decode.  enable(on) clears what
- * was collected; get synchronises and fills, per class, the summed kernel time
- * in ms, the launch count and the summed algorithmic HBM bytes (each operand
- * read once and each result written once) into caller arrays of
+ * [1] the key switch's ModUp kernel (inverse strided pass of the input, the
+ * ModUp basis conversion, forward strided pass of the extended digits),
+ * [2] its ModDown kernel (the same around the ModDown conversion of the
+ * special rows), [3] forward NTT, contiguous final pass, [4] the same pass
+ * ending a key switch or rescale (it also subtracts, scales and adds: the
+ * ModDown / rescale combine), [5] inverse NTT, contiguous first pass,
+ * [6] inverse NTT, strided final pass, [7] the key inner product (with the
+ * forward contiguous pass of the extended digits before it and the inverse
+ * contiguous pass of the special rows after it), [8] rescale (the top limb's
+ * centred spread), [9] elementwise, [10] encode / decode.  enable(on) clears
+ * what was collected; get synchronises and fills, per class, the summed kernel
+ * time in ms, the launch count and the summed algorithmic HBM bytes (each
+ * operand read once and each result written once) into caller arrays of
  * hetal_timing_classes() entries. */
 int hetal_timing_classes(void);
 int hetal_timing_enable(hetal_ctx* ctx, int on);

@@ -156,21 +156,18 @@ struct Tmp {
   operator u64*() const { return p; }
 };
 
-// Kernel classes for the optional per-launch HIP-event timing.
-// NTT passes: forward strided (first; plain, or computing its input by a ModUp / ModDown basis
-// conversion), forward contiguous (final; plain, or with the combine epilogue), inverse contiguous (first),
-// inverse strided (final).
+// Kernel classes for the optional per-launch HIP-event timing: the NTT passes (forward strided = first, forward
+// contiguous = final, plain or with the combine epilogue; inverse contiguous = first, inverse strided = final) and
+// the key switch's own kernels (keyswitch.hip).
 enum KernelClass {
   KC_NTT_FWD_STRIDED = 0,
-  KC_NTT_FWD_MODUP,
-  KC_NTT_FWD_MODDOWN,
+  KC_KS_MODUP,          // inverse strided pass, ModUp conversion, forward strided pass
+  KC_KS_MODDOWN,        // inverse strided pass of the special rows, ModDown conversion, forward strided pass
   KC_NTT_FWD_CONTIG,
   KC_NTT_FWD_EPILOGUE,
   KC_NTT_INV_CONTIG,
   KC_NTT_INV_STRIDED,
-  KC_MODUP,
-  KC_INNER,
-  KC_MODDOWN,
+  KC_KS_INNER,          // forward contiguous pass of the extended digits, key product, special rows' inverse pass
   KC_RESCALE,
   KC_ELEMWISE,
   KC_ENCODE,
@@ -308,41 +305,15 @@ struct NttEpilogue {
   u32 ginv[MAX_BATCH];        // and its inverse modulo 2N
 };
 
-// Optional basis-conversion input of a forward NTT: the first pass computes its input words instead of
-// reading them (the fast basis conversions of hybrid key switching, never stored):
-//  * CONV_MODUP, rows of ROWS_MODUP: row (digit j, extended row r, prime t) takes
-//      sum_i y_i (D_j / d_i) mod t
-//    over the digit's rows y_i = [x_i (D_j/d_i)^-1]_{d_i} of `y` (coefficient form as the bit patterns of exact
-//    doubles, see ntt_inverse's dbl; rows indexed like the
-//    ciphertext's limbs, `ext` rows per digit in the row table's row index);
-//  * CONV_MODDOWN, rows of ROWS_CT: row (polynomial p, limb i) takes
-//      sum_k y_k (P / p_k) mod q_i
-//    over the special rows y_k = [x_k (P/p_k)^-1]_{p_k} of polynomial p of `y` (at row p ext + l + k), each
-//    taken in the centred range (-p_k/2, p_k/2].
-// The sums are reduced to [0, q] (for moduli below 2^42 left below 5.5 q, which the lazy butterflies take).
-enum NttConvKind { CONV_NONE = 0, CONV_MODUP = 1, CONV_MODDOWN = 2 };
-struct NttConv {
-  int kind = CONV_NONE;
-  int count = 0;          // digit length alpha, or the number K of special primes
-  const u64* y = nullptr;
-  size_t y_stride = 0;    // words between items
-  int ext = 0;
-  int l = 0;              // CONV_MODDOWN: limbs per output polynomial
-  int num_q = 0;
-  const ModUpTab* modup = nullptr;  // the level's digit tables
-  const ModDownTab* moddown = nullptr;
-};
-constexpr int MAX_FUSED_CONV = 4;  // conversions of more terms run as separate kernels
+// Terms of a basis conversion the key switch fuses into its NTT passes: alpha and K are at most this.
+constexpr int MAX_FUSED_CONV = 4;
 
 // Between the two passes of a transform (and between the kernels of a key switch) rows hold the bit patterns of
 // exact, integer-valued doubles, not 64-bit residues: only the kernel that reads them as doubles (mid_ld in
 // ntt_device.hpp) may read such a row.  Every row a launcher hands back to its caller holds residues in [0, q).
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
-                 const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr);
-// dbl: the results are stored as the bit patterns of exact doubles, the form the forward transform's fused
-// conversion input (NttConv) reads; only for N = 2^12 and 2^16.
-void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{},
-                 const NttScale* row_scale = nullptr, bool dbl = false);
+                 const NttEpilogue* epi = nullptr);
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src = NttSrc{});
 // The two passes one at a time, for the key switch (keyswitch.hip), which fuses the other pass of each transform
 // into its own kernels: the inverse transform's first (contiguous) pass, stored as doubles; and the forward
 // transform's last (contiguous) pass over rows the forward strided pass stored as doubles, with the epilogue.

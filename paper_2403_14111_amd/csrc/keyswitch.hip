@@ -531,7 +531,7 @@ void key_switch(Context& c, const KsJob& job) {
     a.batch = m_in;
     launch_conv<KIND_MODUP>(c, a, c.alpha, m_in);
     // reads the l coefficient-form limbs, writes the beta ext - l rows outside the digits
-    c.end_launch(KC_NTT_FWD_MODUP, 8.0 * n * m_in * ((double)beta * ext));
+    c.end_launch(KC_KS_MODUP, 8.0 * n * m_in * ((double)beta * ext));
   }
 
   // 3. the inner product with the keys, after the contiguous pass of the extended digits
@@ -561,7 +561,7 @@ void key_switch(Context& c, const KsJob& job) {
                        c.d_twd_fwd, c.d_twd_inv, c.d_fpm, c.log_n);
     // reads the extended digits (beta ext rows per input) and 2 beta ext key rows per item (once for a shared
     // key), writes 2 ext rows per item
-    c.end_launch(KC_INNER, 8.0 * n * ((double)m_in * beta * ext + (shared ? 1.0 : (double)m) * 2.0 * beta * ext +
+    c.end_launch(KC_KS_INNER, 8.0 * n * ((double)m_in * beta * ext + (shared ? 1.0 : (double)m) * 2.0 * beta * ext +
                                       (double)m * 2.0 * ext));
   }
 
@@ -590,7 +590,7 @@ void key_switch(Context& c, const KsJob& job) {
     a.batch = m;
     launch_conv<KIND_MODDOWN>(c, a, c.num_p, m);
     // reads the 2K special rows, writes 2l rows
-    c.end_launch(KC_NTT_FWD_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
+    c.end_launch(KC_KS_MODDOWN, 8.0 * n * m * (2.0 * c.num_p + 2.0 * l));
   }
 
   // 5. the forward contiguous pass of the conversion rows, and the combine (acc_Q - conv) P^-1 + addends

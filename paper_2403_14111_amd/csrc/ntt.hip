@@ -68,17 +68,13 @@ struct PassArgs {
 // for element v is psi_rev[2^(s0 + l) + (c 2^l) + (v >> (L - l))] (c = 0 in the strided pass, where
 // in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
 // EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.
-// CONVK / CNT (forward strided pass only): the input words are the basis conversion of NttConv over CNT
-// source rows, which hold the bit patterns of doubles (the DBL output of the inverse transform that made them).
-// row_scale (inverse strided pass only, may be null): per-row final scaling.  DBL (inverse strided pass only):
-// the results are stored as the bit patterns of the (integer-valued) doubles, for a conversion input.
-template <int L, bool INV, bool CONTIG, bool EPI, int CONVK, int CNT, bool DBL = false>
+// (The key switch's strided passes, which compute their input by a basis conversion, are in keyswitch.hip.)
+template <int L, bool INV, bool CONTIG, bool EPI>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const double* __restrict__ tw,
                                                               const FpMod* __restrict__ fpm,
                                                               const PrimeConsts* __restrict__ pc, int log_n, int s0,
-                                                              NttEpilogue epi, NttConv cv,
-                                                              const NttScale* __restrict__ row_scale) {
+                                                              NttEpilogue epi) {
 #pragma clang fp contract(off)
   constexpr int SUB = 1 << L;
   constexpr int T = SUB / NTT_R;        // threads per sub-transform
@@ -86,9 +82,6 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   constexpr bool FINAL = INV != CONTIG;
   static_assert(!CONTIG || L == 8, "the contiguous pass covers the last 8 stages");
   static_assert(!EPI || (CONTIG && !INV), "the epilogue belongs to the last forward pass");
-  static_assert(CONVK == CONV_NONE || (!CONTIG && !INV && CNT >= 1 && CNT <= MAX_FUSED_CONV),
-                "the conversion input belongs to the first forward pass");
-  static_assert(!DBL || (INV && !CONTIG), "double output belongs to the last inverse pass");
   // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
   // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
   // neighbouring slices in lockstep fall on distinct banks.
@@ -139,57 +132,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       // keeps the two instances' identical loads from being merged above the branch (which would hold every
       // twiddle of the pass in registers at once)
       asm volatile("" ::: "memory");
-      if (CONVK == CONV_MODUP) {
-        // row (digit j, extended row r) at prime t = rj.y: sum_i y_i (D_j/d_i) mod t.  Each product of a
-        // y_i < 2^50 lies in (-0.375 t, 1.375 t); the reducing form reduces the sum after two terms and at the end.
-        const ModUpTab& tb = cv.modup[rj.x / cv.ext];
-        const u64* yb[CNT];
-        double cc[CNT];
-#pragma unroll
-        for (int i = 0; i < CNT; ++i) {
-          // a short last digit has zero constants beyond its length (its row pointer stays in range)
-          yb[i] = cv.y + item * cv.y_stride + (size_t)(tb.first + (i < tb.nsrc ? i : 0)) * n;
-          cc[i] = u2d(tb.dhat[i][rj.y]);
-        }
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u) {
-          const u32 pos = sp_off + sp_step * u;
-          double s = fmul(__longlong_as_double((long long)yb[0][pos]), cc[0], q, qi);
-#pragma unroll
-          for (int i = 1; i < CNT; ++i) {
-            s = s + fmul(__longlong_as_double((long long)yb[i][pos]), cc[i], q, qi);
-            if (!LZ && i == 1 && CNT > 2) s = fred(s, q, qi);
-          }
-          x[u] = LZ ? s : fred(s, q, qi);
-        }
-      } else if (CONVK == CONV_MODDOWN) {
-        // row (polynomial p, limb i) at prime rj.y: sum_k y_k (P/p_k) mod q_i with y_k centred: each
-        // product of a |y_k| < 2^49 lies in (-0.19 q, 1.19 q); the reducing form reduces after two terms
-        // and at the end.
-        const int p = rj.x >= cv.l ? 1 : 0;
-        const u64* yb[CNT];
-        double pk[CNT], ph[CNT], cc[CNT];
-#pragma unroll
-        for (int k = 0; k < CNT; ++k) {
-          yb[k] = cv.y + item * cv.y_stride + (size_t)(p * cv.ext + cv.l + k) * n;
-          pk[k] = fpm[cv.num_q + k].q;
-          ph[k] = __builtin_floor(pk[k] * 0.5);  // (p_k - 1) / 2: values above it are taken as negative
-          cc[k] = u2d(cv.moddown->phat[k][rj.y]);
-        }
-#pragma unroll
-        for (int u = 0; u < NTT_R; ++u) {
-          const u32 pos = sp_off + sp_step * u;
-          double s = 0.0;
-#pragma unroll
-          for (int k = 0; k < CNT; ++k) {
-            double v = __longlong_as_double((long long)yb[k][pos]);
-            v = v > ph[k] ? v - pk[k] : v;
-            s = s + fmul(v, cc[k], q, qi);
-            if (!LZ && k == 1 && CNT > 2) s = fred(s, q, qi);
-          }
-          x[u] = LZ ? s : fred(s, q, qi);
-        }
-      } else {
+      {
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u) {
           const u64 w = (ain + sp_step * u)[sp_off];
@@ -318,14 +261,8 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
           if (u & hu) continue;
           if (l == 0 && FINAL) {
             // last stage of the transform, N^-1 (or the row's replacement) merged into both outputs
-            double k0, k1;
-            if (row_scale) {
-              k0 = u2d(row_scale[rowi].s0);
-              k1 = u2d(row_scale[rowi].s1);
-            } else {
-              k0 = u2d(pc[rj.y].ninv);
-              k1 = u2d(pc[rj.y].w1ninv);
-            }
+            const double k0 = u2d(pc[rj.y].ninv);
+            const double k1 = u2d(pc[rj.y].w1ninv);
             const double s = x[u] + x[u + hu];  // [0, 2q] (lazy: below 16q)
             const double d = x[u] - x[u + hu];
             x[u] = ffix(fred(fmul(s, k0, q, qi), q, qi), q);
@@ -346,14 +283,13 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       transform(std::false_type{});
 #pragma unroll
     for (int u = 0; u < NTT_R; ++u)
-      (a + sp_step * u)[sp_off] = DBL || !FINAL ? mid_st(x[u]) : d2u(x[u]);
+      (a + sp_step * u)[sp_off] = !FINAL ? mid_st(x[u]) : d2u(x[u]);
   }
 }
 
 template <bool INV>
 void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, RowsRef rows, int s0,
-                 const NttSrc& src, const NttEpilogue* epi = nullptr, const NttConv* conv = nullptr,
-                 const NttScale* row_scale = nullptr, bool dbl = false) {
+                 const NttSrc& src, const NttEpilogue* epi = nullptr) {
   const int sub = 1 << L;
   const int per_wg = NTT_THREADS * NTT_R / sub;  // sub-transforms per workgroup
   const int nsub = c.n / sub;
@@ -375,54 +311,17 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
   if (epi && (INV || !contiguous)) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
   if (epi && batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "NTT epilogue batch");
-  const bool cv = conv && conv->kind != CONV_NONE;
-  if (cv && (INV || contiguous || (L != 4 && L != 8) || conv->count < 1 || conv->count > MAX_FUSED_CONV))
-    fail(HETAL_E_PARAMS, "NTT conversion input outside the first forward pass");
-  if (row_scale && !(INV && !contiguous)) fail(HETAL_E_PARAMS, "NTT row scaling outside the last inverse pass");
-  if (dbl && !(INV && !contiguous)) fail(HETAL_E_PARAMS, "double output outside the last inverse pass");
   const NttEpilogue no_epi{};
-  const NttConv no_conv{};
   c.begin_launch();
   if (epi) {
-    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, CONV_NONE, 1>), grid, block, 0, c.stream, pa, rows.d, tw,
-                       c.d_fpm, c.d_pc, c.log_n, s0, *epi, no_conv, nullptr);
-  } else if (cv) {
-    const int key = (L == 8 ? 100 : 0) + conv->kind * 10 + conv->count;
-    switch (key) {
-#define HETAL_NTT_CONV(LL, K, C)                                                                               \
-  case (LL == 8 ? 100 : 0) + K * 10 + C:                                                                     \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, false, false, false, K, C>), grid, block, 0, c.stream, pa, rows.d, tw, \
-                       c.d_fpm, c.d_pc, c.log_n, s0, no_epi, *conv, nullptr);                                \
-    break;
-#define HETAL_NTT_CONV_L(LL) \
-  HETAL_NTT_CONV(LL, 1, 1) HETAL_NTT_CONV(LL, 1, 2) HETAL_NTT_CONV(LL, 1, 3) HETAL_NTT_CONV(LL, 1, 4) \
-  HETAL_NTT_CONV(LL, 2, 1) HETAL_NTT_CONV(LL, 2, 2) HETAL_NTT_CONV(LL, 2, 3) HETAL_NTT_CONV(LL, 2, 4)
-      HETAL_NTT_CONV_L(4)
-      HETAL_NTT_CONV_L(8)
-#undef HETAL_NTT_CONV_L
-#undef HETAL_NTT_CONV
-      default:
-        fail(HETAL_E_PARAMS, "unsupported NTT conversion input");
-    }
-  } else if (dbl) {
-    switch (L) {
-#define HETAL_NTT_DBL(LL)                                                                                      \
-  case LL:                                                                                                   \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, true, false, false, CONV_NONE, 1, true>), grid, block, 0, c.stream, pa, \
-                       rows.d, tw, c.d_fpm, c.d_pc, c.log_n, s0, no_epi, no_conv, row_scale);                \
-    break;
-      HETAL_NTT_DBL(4)
-      HETAL_NTT_DBL(8)
-#undef HETAL_NTT_DBL
-      default:
-        fail(HETAL_E_PARAMS, "double output needs N = 2^12 or 2^16");
-    }
+    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_fpm,
+                       c.d_pc, c.log_n, s0, *epi);
   } else {
     switch (L * 2 + (contiguous ? 1 : 0)) {
 #define HETAL_NTT_CASE(LL, CC)                                                                                 \
   case LL * 2 + CC:                                                                                          \
-    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC, false, CONV_NONE, 1>), grid, block, 0, c.stream, pa, rows.d, \
-                       tw, c.d_fpm, c.d_pc, c.log_n, s0, no_epi, no_conv, row_scale);                        \
+    hipLaunchKernelGGL((ntt_pass_kernel<LL, INV, CC, false>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_fpm, \
+                       c.d_pc, c.log_n, s0, no_epi);                                                         \
     break;
       HETAL_NTT_CASE(4, 0)
       HETAL_NTT_CASE(5, 0)
@@ -440,11 +339,6 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
     // per word: the pass input and a read, out written; addx on every row, add0 / add1 on half of them
     const double per_word = 24.0 + (epi->addx ? 8.0 : 0.0) + (epi->add0 ? 4.0 : 0.0) + (epi->add1 ? 4.0 : 0.0);
     c.end_launch(KC_NTT_FWD_EPILOGUE, per_word * words);
-  } else if (cv) {
-    // the source rows once per item (l limbs for ModUp, 2K special rows for ModDown), every output word written
-    const double src_rows = conv->kind == CONV_MODUP ? (double)(conv->ext - c.num_p) : 2.0 * conv->count;
-    c.end_launch(conv->kind == CONV_MODUP ? KC_NTT_FWD_MODUP : KC_NTT_FWD_MODDOWN,
-                 8.0 * words + 8.0 * (double)c.n * src_rows * batch);
   } else {
     const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
                         : (contiguous ? KC_NTT_FWD_CONTIG : KC_NTT_FWD_STRIDED);
@@ -455,10 +349,10 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
 }  // namespace
 
 void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
-                 const NttEpilogue* epi, const NttConv* conv) {
+                 const NttEpilogue* epi) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
-  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src, nullptr, conv);
+  launch_pass<false>(c, l1, base, batch_stride, batch, rows, 0, src);
   launch_pass<false>(c, 8, base, batch_stride, batch, rows, l1, NttSrc{}, epi);
   c.counters[6] += (int64_t)rows.count * batch;
 }
@@ -474,12 +368,11 @@ void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch
   launch_pass<false>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, NttSrc{}, &epi);
 }
 
-void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
-                 const NttScale* row_scale, bool dbl) {
+void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
   if (rows.count == 0 || batch == 0) return;
   const int l1 = c.log_n - 8;
   launch_pass<true>(c, 8, base, batch_stride, batch, rows, l1, src);
-  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{}, nullptr, nullptr, row_scale, dbl);
+  launch_pass<true>(c, l1, base, batch_stride, batch, rows, 0, NttSrc{});
   c.counters[6] += (int64_t)rows.count * batch;
 }
 

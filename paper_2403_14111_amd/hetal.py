@@ -137,9 +137,8 @@ _SIGS = {
     "hetal_timing_get": (ctypes.c_int, [_vp, _dblp, _i64p, _dblp]),
 }
 
-KERNEL_CLASSES = ["ntt_fwd_strided", "ntt_fwd_modup", "ntt_fwd_moddown", "ntt_fwd_contig", "ntt_fwd_epilogue",
-                  "ntt_inv_contig", "ntt_inv_strided", "modup", "inner_product", "moddown_conv", "rescale", "elementwise",
-                  "encode"]
+KERNEL_CLASSES = ["ntt_fwd_strided", "ks_modup", "ks_moddown", "ntt_fwd_contig", "ntt_fwd_epilogue",
+                  "ntt_inv_contig", "ntt_inv_strided", "ks_inner", "rescale", "elementwise", "encode"]
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res

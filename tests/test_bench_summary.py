@@ -5,9 +5,9 @@ import os
 
 import bench
 
-STEP = [("void hetal::(anonymous namespace)::ntt_pass_kernel<8, false, true, true, 0, 1>(...)", 1000, 4096),
-        ("hetal::(anonymous namespace)::inner_product_shared_kernel<4>(...)", 3000, 65536),
-        ("void hetal::(anonymous namespace)::ntt_pass_kernel<8, true, false, false, 0, 1>(...)", 500, 2048),
+STEP = [("void hetal::(anonymous namespace)::ntt_pass_kernel<8, false, true, true>(...)", 1000, 4096),
+        ("hetal::(anonymous namespace)::ks_inner_kernel(...)", 3000, 65536),
+        ("void hetal::(anonymous namespace)::ntt_pass_kernel<8, true, false, false>(...)", 500, 2048),
         ("hetal::(anonymous namespace)::add_kernel(...)", 100, 65536),
         ("hetal::(anonymous namespace)::add_kernel(...)", 100, 65536)]  # a step ending in two equal kernels
 SETUP = [("hetal::(anonymous namespace)::keygen_kernel(...)", 50, 256),
@@ -57,7 +57,7 @@ def test_summary_window_scaling_and_traffic(tmp_path):
     assert "Timed region: the last 3 steps of the trace (5 kernels per step)" in text
     rec = json.loads(text.split("traffic_json: ")[1])
     assert rec["bytes_per_launch"]["ntt_fwd_epilogue"] == (1000 * 2 + 500) * 1024
-    assert rec["avg_us"]["ntt_fwd_epilogue"] == 1.0 and rec["avg_us"]["inner_product"] == 3.0
+    assert rec["avg_us"]["ntt_fwd_epilogue"] == 1.0 and rec["avg_us"]["ks_inner"] == 3.0
     assert set(rec["sources_sha256"]) == set(rec["bytes_per_launch"])
     row = [l for l in text.splitlines() if l.startswith("| ntt_fwd_epilogue ")][0].split("|")
     assert row[2].strip() == "1"                                  # launches per step
