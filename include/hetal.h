@@ -24,9 +24,11 @@
  *  - All device work is queued on the context's HIP stream (set at creation
  *    or by hetal_ctx_set_stream).  Calls that return host data synchronise
  *    that stream first.  A context is not thread-safe.
- *  - Randomness is an input: the secret key's coefficients, every key
- *    switching key's uniform mask and error, and every encryption's mask and
- *    error are supplied by the caller, so results are deterministic.
+ *  - Randomness: either an input (the secret key's coefficients, every key
+ *    switching key's uniform mask and error, every encryption's mask and
+ *    error supplied by the caller), or drawn by the library from a 64-bit seed
+ *    (the *_seeded calls, hetal_keygen, hetal_gen_evk; see "Seeded sampling"
+ *    below).  Either way results are deterministic.
  */
 #ifndef HETAL_H
 #define HETAL_H
@@ -99,6 +101,29 @@ typedef struct {
   double scale;
 } hetal_mat;
 
+/* ---- Seeded sampling (the client's randomness, Sec. 3.1: the client generates the secret key and the public
+ * operation keys, and encrypts).  The generator is the ChaCha20 block function of RFC 8439 used as a counter-based
+ * stream: stream (seed, purpose, index, sub) has key = the seed (low 32 bits, high 32 bits, then six zero words),
+ * nonce = (purpose, index, sub) and block counter = the block number; its 64-bit word p is the little-endian word
+ * p mod 8 of block p / 8.  Purposes: 1 the secret; 2 a switching key's uniform masks (index = the key id: 0 for the
+ * relinearisation key, else its Galois element; sub = digit * 64 + prime index over all primes); 3 its errors
+ * (sub = digit); 4 an encryption's masks (index = the encryption's number, sub = prime index); 5 its error
+ * (sub = 0).  Distributions, per coefficient k < N:
+ *  - uniform modulo q: the first of the stream's words k, N + k, 2N + k, ... below floor(2^64 / q) q, mod q;
+ *  - error: word k; its top bit is the sign, its low 63 bits u give the magnitude #{j < 19 : T_j <= u}, T_j =
+ *    floor(2^63 P(|x| <= j)) for the rounded Gaussian of standard deviation 3.2 on |x| <= 19
+ *    (hetal_gaussian_table); one value per coefficient, reduced modulo every prime;
+ *  - secret: exactly min(192, N) coefficients +-1: word p names position (word mod N) and sign (top bit), in
+ *    order, positions already set skipped. */
+
+/* The error sampler's 19 thresholds (host, ascending).  *n: in, capacity (>= 19); out, 19.  No context needed. */
+int hetal_gaussian_table(uint64_t* out, int* n);
+/* Samples for tests and for callers that keep their own randomness: the ternary secret of `seed` with h
+ * nonzero coefficients (host int64 [2^log_n]; no context needed); `rows` rows of uniform residues (host uint64
+ * [rows][N], coefficient form; row r is the stream of sub (r / group) * 64 + r % group, modulo prime r % group,
+ * group <= num_q + num_p); `count` rows of errors (host int64 [count][N], row r the stream of sub r). */
+int hetal_sample_ternary(int log_n, uint64_t seed, int h, int64_t* out);
+
 /* The message of the last failed call on the calling thread (a failed call
  * sets it; successful calls leave it).  Owned by the library, valid until
  * the thread's next failing call. */
@@ -126,6 +151,12 @@ uint64_t hetal_galois_conj(const hetal_ctx* ctx);
 int hetal_sk_create(hetal_ctx* ctx, const int64_t* s_coeffs, hetal_sk** out);
 void hetal_sk_destroy(hetal_sk* sk);
 
+/* The client's secret key drawn from `seed`: ternary with min(192, N) nonzero coefficients (seeded sampling). */
+int hetal_keygen(hetal_ctx* ctx, uint64_t seed, hetal_sk** out);
+int hetal_sample_uniform(hetal_ctx* ctx, uint64_t seed, uint32_t purpose, uint32_t index, int rows, int group,
+                         uint64_t* host);
+int hetal_sample_gaussian(hetal_ctx* ctx, uint64_t seed, uint32_t purpose, uint32_t index, int count, int64_t* host);
+
 /* Evaluation keys (public operation keys, Sec. 3.1), held in library-owned
  * device memory: 2 * dnum * (num_q + num_p) * N words per key.
  * Key for s' (s^2 for relinearisation, tau_g(s) for Galois element g):
@@ -139,6 +170,12 @@ void hetal_keys_destroy(hetal_keys* keys);
 int hetal_keys_gen_relin(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, const uint64_t* a, const int64_t* e);
 int hetal_keys_gen_galois(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, uint64_t galois, const uint64_t* a,
                           const int64_t* e);
+/* The evaluation keys an algorithm needs, with the library's own randomness from `seed`: the relinearisation
+ * key (if relin), the Galois key of every rotation step in rot_steps[0 .. n-1] (left rotation by r; steps that
+ * are 0 mod N/2 need none; duplicates are made once), and the conjugation key (if conj).  Existing keys for the
+ * same elements are replaced.  hetal_required_rot_steps lists the steps of DiagABT / DiagATB. */
+int hetal_gen_evk(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, uint64_t seed, const int32_t* rot_steps,
+                  int n, int conj, int relin);
 
 /* Encoding (Sec. 2.2, CKKS): slot k of the message is the value of the
  * plaintext polynomial at zeta^(5^k), zeta = exp(i pi / N).  The
@@ -156,6 +193,9 @@ int hetal_decode(hetal_ctx* ctx, const hetal_pt* pt, double* re, double* im);
  * (E_INVALID_ARG if a word is not below its prime); e: host int64 [N]. */
 int hetal_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, const uint64_t* a, const int64_t* e,
                   hetal_ct* out);
+/* hetal_encrypt with the library's own randomness: the masks and error of encryption number `index` under `seed`. */
+int hetal_encrypt_seeded(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, uint64_t seed, uint32_t index,
+                         hetal_ct* out);
 /* m = c0 + c1 s. */
 int hetal_decrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_ct* ct, hetal_pt* out);
 
@@ -217,6 +257,9 @@ int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double 
  * else), or if c does not divide the tiled dimension. */
 int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int c,
                       const uint64_t* a, const int64_t* e, hetal_mat* out);
+/* hetal_mat_encrypt with the library's own randomness: block b is encryption number first_index + b under seed. */
+int hetal_mat_encrypt_seeded(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling,
+                             int c, uint64_t seed, uint32_t first_index, hetal_mat* out);
 /* Decrypt and decode every block: host double [n_rb*s0][n_cb*s1] (real
  * parts; padding included).  Synchronises. */
 int hetal_mat_decrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_mat* m, double* host);

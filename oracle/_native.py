@@ -14,6 +14,7 @@ _SRC = os.path.join(_HERE, "ckks_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _dblp = ctypes.POINTER(ctypes.c_double)
 
@@ -53,6 +54,16 @@ def _load():
         "orc_encode": (ctypes.c_int, [_dblp, _dblp, ctypes.c_int, ctypes.c_double, _i64p]),
         "orc_reduce_signed": (None, [_i64p, _u64p, ctypes.c_int, ctypes.c_int, _u64p]),
         "orc_crt_centered": (None, [_u64p, ctypes.c_int, ctypes.c_int, _u64p, _dblp]),
+        "orc_chacha20_quarter_round": (None, [_u32p]),
+        "orc_chacha20_block": (None, [_u32p, ctypes.c_uint32, _u32p, _u32p]),
+        "orc_stream_words": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_uint64, _u64p]),
+        "orc_sample_uniform": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_int, _u64p]),
+        "orc_sample_gaussian": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u64p,
+                                       ctypes.c_int, ctypes.c_int, _i64p]),
+        "orc_sample_ternary": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                                ctypes.c_int, ctypes.c_int, _i64p]),
         "orc_set_threads": (None, [ctypes.c_int]),
         "orc_max_threads": (ctypes.c_int, []),
     }
@@ -74,6 +85,11 @@ def u64ptr(a):
 def i64ptr(a):
     assert a.dtype == np.int64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_i64p)
+
+
+def u32ptr(a):
+    assert a.dtype == np.uint32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_u32p)
 
 
 def dblptr(a):

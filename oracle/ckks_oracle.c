@@ -574,3 +574,125 @@ void orc_crt_centered(const u64* limbs, int count, int log_n, const u64* qs, dou
 /* Thread count of the parallel loops above (timing only; results do not depend on it). */
 void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------ */
+/* Seeded sampling: ChaCha20 as the counter-based generator.            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The ChaCha20 block function of RFC 8439 (Sec. 2.1-2.3), written from its
+ * definition: a 4x4 state of 32-bit words (the four constants, the 256-bit
+ * key, a 32-bit block counter, a 96-bit nonce), twenty rounds that alternate
+ * quarter rounds on the columns and on the diagonals, then the input state
+ * added word by word.  out: the 16 words of the block (the keystream is their
+ * little-endian bytes).
+ */
+static uint32_t rotl32(uint32_t v, int c) { return (v << c) | (v >> (32 - c)); }
+
+static void quarter_round(uint32_t* x, int a, int b, int c, int d) {
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 16);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 12);
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = rotl32(x[d], 8);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = rotl32(x[b], 7);
+}
+
+void orc_chacha20_quarter_round(uint32_t* x4) { quarter_round(x4, 0, 1, 2, 3); }
+
+void orc_chacha20_block(const uint32_t* key8, uint32_t counter, const uint32_t* nonce3, uint32_t* out16) {
+    uint32_t s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u};
+    for (int i = 0; i < 8; ++i) s[4 + i] = key8[i];
+    s[12] = counter;
+    for (int i = 0; i < 3; ++i) s[13 + i] = nonce3[i];
+    uint32_t x[16];
+    memcpy(x, s, sizeof(x));
+    for (int r = 0; r < 10; ++r) {
+        quarter_round(x, 0, 4, 8, 12);
+        quarter_round(x, 1, 5, 9, 13);
+        quarter_round(x, 2, 6, 10, 14);
+        quarter_round(x, 3, 7, 11, 15);
+        quarter_round(x, 0, 5, 10, 15);
+        quarter_round(x, 1, 6, 11, 12);
+        quarter_round(x, 2, 7, 8, 13);
+        quarter_round(x, 3, 4, 9, 14);
+    }
+    for (int i = 0; i < 16; ++i) out16[i] = x[i] + s[i];
+}
+
+/*
+ * The stream of (seed, purpose, index, sub): ChaCha20 with the key = the
+ * 64-bit seed (low word first) followed by zeros, the nonce = (purpose, index,
+ * sub), and the block counter = the block number.  Its 64-bit word p is bytes
+ * 8 (p mod 8) .. 8 (p mod 8) + 7 of block floor(p / 8), little-endian.
+ */
+static u64 stream_word(u64 seed, uint32_t purpose, uint32_t index, uint32_t sub, u64 p) {
+    uint32_t key[8] = {(uint32_t)seed, (uint32_t)(seed >> 32), 0, 0, 0, 0, 0, 0};
+    uint32_t nonce[3] = {purpose, index, sub};
+    uint32_t blk[16];
+    orc_chacha20_block(key, (uint32_t)(p / 8), nonce, blk);
+    int w = (int)(p % 8);
+    return (u64)blk[2 * w] | ((u64)blk[2 * w + 1] << 32);
+}
+
+/* Words p0 .. p0 + count - 1 of a stream. */
+void orc_stream_words(u64 seed, uint32_t purpose, uint32_t index, uint32_t sub, u64 p0, u64 count, u64* out) {
+    for (u64 i = 0; i < count; ++i) out[i] = stream_word(seed, purpose, index, sub, p0 + i);
+}
+
+/*
+ * Uniform residues modulo q, one per coefficient k < N: the first of the words
+ * k, N + k, 2N + k, ... of the stream that lies below floor(2^64 / q) q (a
+ * rejected word would bias the result), reduced modulo q.
+ */
+void orc_sample_uniform(u64 seed, uint32_t purpose, uint32_t index, uint32_t sub, u64 q, int log_n, u64* out) {
+    u64 n = 1ull << log_n;
+    u64 bound = (UINT64_MAX / q) * q; /* floor(2^64 / q) q, as 2^64 - (2^64 mod q) */
+    if (UINT64_MAX % q == q - 1) bound = 0; /* q divides 2^64: no word is rejected */
+    for (u64 k = 0; k < n; ++k) {
+        for (u64 layer = 0;; ++layer) {
+            u64 w = stream_word(seed, purpose, index, sub, layer * n + k);
+            if (bound == 0 || w < bound) {
+                out[k] = w % q;
+                break;
+            }
+        }
+    }
+}
+
+/*
+ * Rounded Gaussian errors from a cumulative table: word k of the stream gives
+ * coefficient k; its top bit is the sign and its low 63 bits u select the
+ * magnitude, the number of thresholds table[j] <= u (table ascending, `entries`
+ * of them); magnitude 0 ignores the sign.
+ */
+void orc_sample_gaussian(u64 seed, uint32_t purpose, uint32_t index, uint32_t sub, const u64* table, int entries,
+                         int log_n, i64* out) {
+    u64 n = 1ull << log_n;
+    for (u64 k = 0; k < n; ++k) {
+        u64 w = stream_word(seed, purpose, index, sub, k);
+        u64 u = w & 0x7fffffffffffffffull;
+        i64 mag = 0;
+        for (int j = 0; j < entries; ++j) mag += table[j] <= u;
+        out[k] = (w >> 63) ? -mag : mag;
+    }
+}
+
+/*
+ * A ternary secret with exactly h nonzero coefficients: the words of the
+ * stream are taken in order; word w names position w mod N (N a power of two)
+ * and sign (w >> 63 ? -1 : +1); a position already taken is skipped, until h
+ * positions are set.  Returns the number of words used, or -1 if h > N.
+ */
+i64 orc_sample_ternary(u64 seed, uint32_t purpose, uint32_t index, uint32_t sub, int h, int log_n, i64* out) {
+    u64 n = 1ull << log_n;
+    if ((u64)h > n) return -1;
+    memset(out, 0, n * sizeof(i64));
+    u64 p = 0;
+    for (int set = 0; set < h; ++p) {
+        u64 w = stream_word(seed, purpose, index, sub, p);
+        u64 pos = w & (n - 1);
+        if (out[pos] != 0) continue;
+        out[pos] = (w >> 63) ? -1 : 1;
+        ++set;
+    }
+    return (i64)p;
+}

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "handles.hpp"
+#include "sampler.hpp"
 #include "softmax.hpp"
 
 using namespace hetal;
@@ -37,19 +38,37 @@ static void check_uniform(const Context& c, const uint64_t* host, int count, int
     }
 }
 
+// NTT form of coefficient-form randomness already on the device: a ([count][l][N], residues, transformed in
+// place) and e ([count][N], signed, reduced into en [count][l][N]).
+void randomness_to_ntt(Context& c, u64* a, const i64* ecoef, int level, int count, u64* en) {
+  const size_t poly = c.poly_words(level);
+  RowsRef rows = c.rows(ROWS_CT, level);
+  RowsRef first{rows.d, level + 1};
+  ntt_forward(c, a, poly, count, first);
+  k_reduce_signed(c, ecoef, en, first, count, c.n, poly);
+  ntt_forward(c, en, poly, count, first);
+}
+
 // NTT form of caller-supplied coefficient-form randomness a ([count][l][N]) and e ([count][N]).
 void load_randomness(Context& c, const uint64_t* a_host, const int64_t* e_host, int level, int count, Tmp& a, Tmp& e) {
   check_uniform(c, a_host, count, level + 1);
   const size_t poly = c.poly_words(level);
   HCHECK(hipStreamSynchronize(c.stream));
   HCHECK(hipMemcpyAsync(a.p, a_host, (size_t)count * poly * 8, hipMemcpyHostToDevice, c.stream));
-  RowsRef rows = c.rows(ROWS_CT, level);
-  RowsRef first{rows.d, level + 1};
-  ntt_forward(c, a, poly, count, first);
   Tmp ecoef = upload_words(c, e_host, (size_t)count * c.n * 8);
-  k_reduce_signed(c, reinterpret_cast<const i64*>(ecoef.p), e, first, count, c.n, poly);
-  ntt_forward(c, e, poly, count, first);
+  randomness_to_ntt(c, a, reinterpret_cast<const i64*>(ecoef.p), level, count, e);
   HCHECK(hipStreamSynchronize(c.stream));
+}
+
+// The library's own randomness for encryptions index .. index + count - 1 at `level` (sampler.hip), in NTT form.
+void sample_randomness(Context& c, u64 seed, u32 index, int level, int count, Tmp& a, Tmp& e) {
+  const size_t poly = c.poly_words(level);
+  Tmp ecoef(c.pool, (size_t)count * c.n);
+  for (int b = 0; b < count; ++b) {
+    sample_uniform(c, seed, PURPOSE_ENC_A, index + (u32)b, level + 1, level + 1, a.p + b * poly);
+    sample_gaussian(c, seed, PURPOSE_ENC_E, index + (u32)b, 1, reinterpret_cast<i64*>(ecoef.p) + b * c.n);
+  }
+  randomness_to_ntt(c, a, reinterpret_cast<const i64*>(ecoef.p), level, count, e);
 }
 
 }  // namespace
@@ -134,20 +153,32 @@ int hetal_synchronize(hetal_ctx* ctx) {
 uint64_t hetal_galois_rot(const hetal_ctx* ctx, int r) { return ctx ? galois_rot(ctx->c, r) : 0; }
 uint64_t hetal_galois_conj(const hetal_ctx* ctx) { return ctx ? galois_conj(ctx->c) : 0; }
 
+static hetal_sk* sk_from_coeffs(hetal_ctx* ctx, const int64_t* s_coeffs) {
+  Context& c = ctx->c;
+  for (int k = 0; k < c.n; ++k) need(s_coeffs[k] >= -1 && s_coeffs[k] <= 1, HETAL_E_INVALID_ARG, "secret must be ternary");
+  u64* s = nullptr;
+  if (hipMalloc(&s, (size_t)c.nprimes * c.n * 8) != hipSuccess) fail(HETAL_E_OOM, "secret key allocation");
+  Tmp coef = upload_words(c, s_coeffs, (size_t)c.n * 8);
+  RowsRef all = c.rows(ROWS_ALL, 0);
+  k_reduce_signed(c, reinterpret_cast<const i64*>(coef.p), s, all, 1, 0, 0);
+  ntt_forward(c, s, 0, 1, all);
+  HCHECK(hipStreamSynchronize(c.stream));
+  return new hetal_sk{ctx, SecretKeyDev{s}};
+}
+
 int hetal_sk_create(hetal_ctx* ctx, const int64_t* s_coeffs, hetal_sk** out) {
   return guarded([&] {
     need(ctx && s_coeffs && out, HETAL_E_INVALID_ARG, "null argument");
-    Context& c = ctx->c;
-    for (int k = 0; k < c.n; ++k) need(s_coeffs[k] >= -1 && s_coeffs[k] <= 1, HETAL_E_INVALID_ARG, "secret must be ternary");
-    u64* s = nullptr;
-    if (hipMalloc(&s, (size_t)c.nprimes * c.n * 8) != hipSuccess) fail(HETAL_E_OOM, "secret key allocation");
-    Tmp coef = upload_words(c, s_coeffs, (size_t)c.n * 8);
-    RowsRef all = c.rows(ROWS_ALL, 0);
-    k_reduce_signed(c, reinterpret_cast<const i64*>(coef.p), s, all, 1, 0, 0);
-    ntt_forward(c, s, 0, 1, all);
-    HCHECK(hipStreamSynchronize(c.stream));
-    hetal_sk* h = new hetal_sk{ctx, SecretKeyDev{s}};
-    *out = h;
+    *out = sk_from_coeffs(ctx, s_coeffs);
+  });
+}
+
+int hetal_keygen(hetal_ctx* ctx, uint64_t seed, hetal_sk** out) {
+  return guarded([&] {
+    need(ctx && out, HETAL_E_INVALID_ARG, "null argument");
+    std::vector<int64_t> s(ctx->c.n);
+    sample_ternary(seed, ctx->c.log_n, std::min(SECRET_HAMMING, ctx->c.n), s.data());
+    *out = sk_from_coeffs(ctx, s.data());
   });
 }
 
@@ -173,18 +204,14 @@ void hetal_keys_destroy(hetal_keys* keys) {
   delete keys;
 }
 
-static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint64_t* a_host, const int64_t* e_host,
-                            u32 g) {
-  check_uniform(c, a_host, c.dnum, c.nprimes);
+// A switching key for s' (NTT form) from coefficient-form randomness on the device: a [dnum][nprimes][N]
+// (transformed in place), e [dnum][N] signed.
+static u64* switch_key_from(Context& c, const u64* s, const u64* sp, u64* a, const i64* ecoef, u32 g) {
   const size_t rows_words = (size_t)c.nprimes * c.n;
-  Tmp a(c.pool, (size_t)c.dnum * rows_words);
   Tmp e(c.pool, (size_t)c.dnum * rows_words);
-  HCHECK(hipStreamSynchronize(c.stream));
-  HCHECK(hipMemcpyAsync(a.p, a_host, (size_t)c.dnum * rows_words * 8, hipMemcpyHostToDevice, c.stream));
   RowsRef all = c.rows(ROWS_ALL, 0);
   ntt_forward(c, a, rows_words, c.dnum, all);
-  Tmp ecoef = upload_words(c, e_host, (size_t)c.dnum * c.n * 8);
-  k_reduce_signed(c, reinterpret_cast<const i64*>(ecoef.p), e, all, c.dnum, c.n, rows_words);
+  k_reduce_signed(c, ecoef, e, all, c.dnum, c.n, rows_words);
   ntt_forward(c, e, rows_words, c.dnum, all);
   u64* key = nullptr;
   if (hipMalloc(&key, c.key_words() * 8) != hipSuccess) fail(HETAL_E_OOM, "key allocation");
@@ -193,15 +220,43 @@ static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint6
   return key;
 }
 
+static u64* make_switch_key(Context& c, const u64* s, const u64* sp, const uint64_t* a_host, const int64_t* e_host,
+                            u32 g) {
+  check_uniform(c, a_host, c.dnum, c.nprimes);
+  const size_t rows_words = (size_t)c.nprimes * c.n;
+  Tmp a(c.pool, (size_t)c.dnum * rows_words);
+  HCHECK(hipStreamSynchronize(c.stream));
+  HCHECK(hipMemcpyAsync(a.p, a_host, (size_t)c.dnum * rows_words * 8, hipMemcpyHostToDevice, c.stream));
+  Tmp ecoef = upload_words(c, e_host, (size_t)c.dnum * c.n * 8);
+  return switch_key_from(c, s, sp, a, reinterpret_cast<const i64*>(ecoef.p), g);
+}
+
+// s' of the key for Galois element g (1: s^2, the relinearisation key), NTT form over every prime.
+static void key_target(Context& c, const hetal_sk* sk, u32 g, u64* out) {
+  if (g == 1)
+    k_mul_rows(c, sk->key.s, sk->key.s, out, c.nprimes, c.nprimes, c.nprimes);
+  else
+    k_galois(c, sk->key.s, out, c.nprimes, c.nprimes, g);
+}
+
+static void store_key(KeySet& set, u32 g, u64* key) {
+  if (g == 1) {
+    if (set.relin) (void)hipFree(set.relin);
+    set.relin = key;
+    return;
+  }
+  auto it = set.galois.find(g);
+  if (it != set.galois.end()) (void)hipFree(it->second);
+  set.galois[g] = key;
+}
+
 int hetal_keys_gen_relin(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, const uint64_t* a, const int64_t* e) {
   return guarded([&] {
     need(ctx && keys && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
     Context& c = ctx->c;
-    Tmp s2(c.pool, (size_t)c.nprimes * c.n);
-    k_mul_rows(c, sk->key.s, sk->key.s, s2, c.nprimes, c.nprimes, c.nprimes);
-    u64* key = make_switch_key(c, sk->key.s, s2, a, e, 1);
-    if (keys->set.relin) (void)hipFree(keys->set.relin);
-    keys->set.relin = key;
+    Tmp sp(c.pool, (size_t)c.nprimes * c.n);
+    key_target(c, sk, 1, sp);
+    store_key(keys->set, 1, make_switch_key(c, sk->key.s, sp, a, e, 1));
   });
 }
 
@@ -211,12 +266,39 @@ int hetal_keys_gen_galois(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, 
     need(ctx && keys && sk && a && e, HETAL_E_INVALID_ARG, "null argument");
     Context& c = ctx->c;
     need(galois % 2 == 1 && galois < 2ull * c.n, HETAL_E_INVALID_ARG, "Galois element must be odd and below 2N");
-    Tmp sg(c.pool, (size_t)c.nprimes * c.n);
-    k_galois(c, sk->key.s, sg, c.nprimes, c.nprimes, (u32)galois);
-    u64* key = make_switch_key(c, sk->key.s, sg, a, e, (u32)galois);
-    auto it = keys->set.galois.find((u32)galois);
-    if (it != keys->set.galois.end()) (void)hipFree(it->second);
-    keys->set.galois[(u32)galois] = key;
+    if (galois == 1) return;  // the identity needs no key
+    Tmp sp(c.pool, (size_t)c.nprimes * c.n);
+    key_target(c, sk, (u32)galois, sp);
+    store_key(keys->set, (u32)galois, make_switch_key(c, sk->key.s, sp, a, e, (u32)galois));
+  });
+}
+
+int hetal_gen_evk(hetal_ctx* ctx, hetal_keys* keys, const hetal_sk* sk, uint64_t seed, const int32_t* rot_steps,
+                  int n, int conj, int relin) {
+  return guarded([&] {
+    need(ctx && keys && sk && n >= 0 && (n == 0 || rot_steps), HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    std::vector<u32> gal;
+    if (relin) gal.push_back(1);
+    for (int i = 0; i < n; ++i) {
+      const u32 g = galois_rot(c, rot_steps[i]);
+      if (g != 1 && std::find(gal.begin(), gal.end(), g) == gal.end()) gal.push_back(g);
+    }
+    if (conj) {
+      const u32 g = galois_conj(c);
+      if (std::find(gal.begin(), gal.end(), g) == gal.end()) gal.push_back(g);
+    }
+    const size_t rows_words = (size_t)c.nprimes * c.n;
+    Tmp sp(c.pool, rows_words);
+    Tmp a(c.pool, (size_t)c.dnum * rows_words);
+    Tmp ecoef(c.pool, (size_t)c.dnum * c.n);
+    for (u32 g : gal) {
+      key_target(c, sk, g, sp);
+      const u32 kid = g == 1 ? 0u : g;
+      sample_uniform(c, seed, PURPOSE_KSK_A, kid, c.dnum * c.nprimes, c.nprimes, a);
+      sample_gaussian(c, seed, PURPOSE_KSK_E, kid, c.dnum, reinterpret_cast<i64*>(ecoef.p));
+      store_key(keys->set, g, switch_key_from(c, sk->key.s, sp, a, reinterpret_cast<const i64*>(ecoef.p), g));
+    }
   });
 }
 
@@ -270,6 +352,65 @@ int hetal_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, const 
     k_encrypt(c, an, en, pt->data, sk->key.s, out->data, pt->level);
     out->level = pt->level;
     out->scale = pt->scale;
+  });
+}
+
+int hetal_encrypt_seeded(hetal_ctx* ctx, const hetal_sk* sk, const hetal_pt* pt, uint64_t seed, uint32_t index,
+                         hetal_ct* out) {
+  return guarded([&] {
+    need(ctx && sk, HETAL_E_INVALID_ARG, "null argument");
+    Context& c = ctx->c;
+    check_pt(c, pt);
+    check_out(c, out, pt->level);
+    const size_t poly = c.poly_words(pt->level);
+    Tmp an(c.pool, poly), en(c.pool, poly);
+    sample_randomness(c, seed, index, pt->level, 1, an, en);
+    k_encrypt(c, an, en, pt->data, sk->key.s, out->data, pt->level);
+    HCHECK(hipStreamSynchronize(c.stream));
+    out->level = pt->level;
+    out->scale = pt->scale;
+  });
+}
+
+int hetal_gaussian_table(uint64_t* out, int* n) {
+  return guarded([&] {
+    need(out && n, HETAL_E_INVALID_ARG, "null argument");
+    need(*n >= GAUSS_ENTRIES, HETAL_E_INVALID_ARG, "table needs 19 entries");
+    u64 t[GAUSS_ENTRIES];
+    gaussian_table(t);
+    for (int j = 0; j < GAUSS_ENTRIES; ++j) out[j] = t[j];
+    *n = GAUSS_ENTRIES;
+  });
+}
+
+int hetal_sample_ternary(int log_n, uint64_t seed, int h, int64_t* out) {
+  return guarded([&] {
+    need(out && log_n >= 1 && log_n <= 30 && h >= 0, HETAL_E_INVALID_ARG, "bad argument");
+    sample_ternary(seed, log_n, h, out);
+  });
+}
+
+int hetal_sample_uniform(hetal_ctx* ctx, uint64_t seed, uint32_t purpose, uint32_t index, int rows, int group,
+                         uint64_t* host) {
+  return guarded([&] {
+    need(ctx && host && rows > 0 && group > 0 && group <= ctx->c.nprimes, HETAL_E_INVALID_ARG, "bad argument");
+    Context& c = ctx->c;
+    Tmp d(c.pool, (size_t)rows * c.n);
+    sample_uniform(c, seed, purpose, index, rows, group, d);
+    HCHECK(hipMemcpyAsync(host, d.p, (size_t)rows * c.n * 8, hipMemcpyDeviceToHost, c.stream));
+    HCHECK(hipStreamSynchronize(c.stream));
+  });
+}
+
+int hetal_sample_gaussian(hetal_ctx* ctx, uint64_t seed, uint32_t purpose, uint32_t index, int count,
+                          int64_t* host) {
+  return guarded([&] {
+    need(ctx && host && count > 0, HETAL_E_INVALID_ARG, "bad argument");
+    Context& c = ctx->c;
+    Tmp d(c.pool, (size_t)count * c.n);
+    sample_gaussian(c, seed, purpose, index, count, reinterpret_cast<i64*>(d.p));
+    HCHECK(hipMemcpyAsync(host, d.p, (size_t)count * c.n * 8, hipMemcpyDeviceToHost, c.stream));
+    HCHECK(hipStreamSynchronize(c.stream));
   });
 }
 
@@ -644,49 +785,72 @@ int hetal_ct_from_coeff(hetal_ctx* ctx, const uint64_t* host, int level, double 
   });
 }
 
+}  // extern "C"
+
+// Block-encodes and encrypts a host matrix; `randomness(nb, level, an, en)` fills the NTT-form randomness of the
+// nb blocks.
+template <class R>
+static void mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int cc,
+                        hetal_mat* out, R&& randomness) {
+  need(rows > 0 && cols > 0, HETAL_E_SHAPE, "empty matrix");
+  need(ctx && sk && host && out && out->data, HETAL_E_INVALID_ARG, "null argument");
+  Context& c = ctx->c;
+  need(out->s0 > 0 && c.slots % out->s0 == 0, HETAL_E_SHAPE, "s0 must divide N/2");
+  const int s0 = out->s0, s1 = c.slots / s0;
+  need(out->level >= 0 && out->level < c.num_q, HETAL_E_LEVEL, "level out of range");
+  need(out->scale > 0, HETAL_E_SCALE, "scale must be positive");
+  int n_rb, n_cb;
+  if (tiling == 0) {
+    n_rb = (rows + s0 - 1) / s0;
+    n_cb = (cols + s1 - 1) / s1;
+  } else if (tiling == 1) {
+    need(cc >= rows && cc > 0 && s0 % cc == 0, HETAL_E_SHAPE, "vertical tiling needs rows <= c and c | s0");
+    n_rb = 1;
+    n_cb = (cols + s1 - 1) / s1;
+  } else if (tiling == 2) {
+    need(cc >= cols && cc > 0 && s1 % cc == 0, HETAL_E_SHAPE, "horizontal tiling needs cols <= c and c | s1");
+    n_rb = (rows + s0 - 1) / s0;
+    n_cb = 1;
+  } else {
+    fail(HETAL_E_INVALID_ARG, "tiling must be 0, 1 or 2");
+  }
+  const int nb = n_rb * n_cb;
+  const int lv = out->level;
+  need(out->capacity >= (size_t)nb * c.ct_words(lv), HETAL_E_INVALID_ARG, "matrix capacity too small");
+  Tmp dmat = upload_words(c, host, (size_t)rows * cols * 8);
+  Tmp slots(c.pool, (size_t)nb * c.slots);
+  k_block_layout(c, reinterpret_cast<const double*>(dmat.p), rows, cols, tiling, cc, s0, s1, n_rb, n_cb,
+                 reinterpret_cast<double*>(slots.p));
+  const size_t poly = c.poly_words(lv);
+  Tmp pts(c.pool, (size_t)nb * poly);
+  encode_slots(c, reinterpret_cast<const double*>(slots.p), nullptr, nb, c.slots, lv, out->scale, pts, poly);
+  Tmp an(c.pool, (size_t)nb * poly), en(c.pool, (size_t)nb * poly);
+  randomness(nb, lv, an, en);
+  for (int b = 0; b < nb; ++b)
+    k_encrypt(c, an.p + b * poly, en.p + b * poly, pts.p + b * poly, sk->key.s, out->data + b * c.ct_words(lv), lv);
+  out->n_rb = n_rb;
+  out->n_cb = n_cb;
+  out->s1 = s1;
+  HCHECK(hipStreamSynchronize(c.stream));
+}
+
+extern "C" {
+
 int hetal_mat_encrypt(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling, int cc,
                       const uint64_t* a, const int64_t* e, hetal_mat* out) {
   return guarded([&] {
-    need(rows > 0 && cols > 0, HETAL_E_SHAPE, "empty matrix");
-    need(ctx && sk && host && a && e && out && out->data, HETAL_E_INVALID_ARG, "null argument");
-    Context& c = ctx->c;
-    need(out->s0 > 0 && c.slots % out->s0 == 0, HETAL_E_SHAPE, "s0 must divide N/2");
-    const int s0 = out->s0, s1 = c.slots / s0;
-    need(out->level >= 0 && out->level < c.num_q, HETAL_E_LEVEL, "level out of range");
-    need(out->scale > 0, HETAL_E_SCALE, "scale must be positive");
-    int n_rb, n_cb;
-    if (tiling == 0) {
-      n_rb = (rows + s0 - 1) / s0;
-      n_cb = (cols + s1 - 1) / s1;
-    } else if (tiling == 1) {
-      need(cc >= rows && cc > 0 && s0 % cc == 0, HETAL_E_SHAPE, "vertical tiling needs rows <= c and c | s0");
-      n_rb = 1;
-      n_cb = (cols + s1 - 1) / s1;
-    } else if (tiling == 2) {
-      need(cc >= cols && cc > 0 && s1 % cc == 0, HETAL_E_SHAPE, "horizontal tiling needs cols <= c and c | s1");
-      n_rb = (rows + s0 - 1) / s0;
-      n_cb = 1;
-    } else {
-      fail(HETAL_E_INVALID_ARG, "tiling must be 0, 1 or 2");
-    }
-    const int nb = n_rb * n_cb;
-    const int lv = out->level;
-    need(out->capacity >= (size_t)nb * c.ct_words(lv), HETAL_E_INVALID_ARG, "matrix capacity too small");
-    Tmp dmat = upload_words(c, host, (size_t)rows * cols * 8);
-    Tmp slots(c.pool, (size_t)nb * c.slots);
-    k_block_layout(c, reinterpret_cast<const double*>(dmat.p), rows, cols, tiling, cc, s0, s1, n_rb, n_cb,
-                   reinterpret_cast<double*>(slots.p));
-    const size_t poly = c.poly_words(lv);
-    Tmp pts(c.pool, (size_t)nb * poly);
-    encode_slots(c, reinterpret_cast<const double*>(slots.p), nullptr, nb, c.slots, lv, out->scale, pts, poly);
-    Tmp an(c.pool, (size_t)nb * poly), en(c.pool, (size_t)nb * poly);
-    load_randomness(c, a, e, lv, nb, an, en);
-    for (int b = 0; b < nb; ++b)
-      k_encrypt(c, an.p + b * poly, en.p + b * poly, pts.p + b * poly, sk->key.s, out->data + b * c.ct_words(lv), lv);
-    out->n_rb = n_rb;
-    out->n_cb = n_cb;
-    out->s1 = s1;
-    HCHECK(hipStreamSynchronize(c.stream));
+    need(a && e, HETAL_E_INVALID_ARG, "null argument");
+    mat_encrypt(ctx, sk, host, rows, cols, tiling, cc, out,
+                [&](int nb, int lv, Tmp& an, Tmp& en) { load_randomness(ctx->c, a, e, lv, nb, an, en); });
+  });
+}
+
+int hetal_mat_encrypt_seeded(hetal_ctx* ctx, const hetal_sk* sk, const double* host, int rows, int cols, int tiling,
+                             int cc, uint64_t seed, uint32_t first_index, hetal_mat* out) {
+  return guarded([&] {
+    mat_encrypt(ctx, sk, host, rows, cols, tiling, cc, out, [&](int nb, int lv, Tmp& an, Tmp& en) {
+      sample_randomness(ctx->c, seed, first_index, lv, nb, an, en);
+    });
   });
 }
 

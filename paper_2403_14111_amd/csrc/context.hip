@@ -431,6 +431,8 @@ void context_share(Context& d, const Context& s, hipStream_t stream) {
 void context_free(Context& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   else (void)hipDeviceSynchronize();
+  if (c.d_gauss) (void)hipFree(c.d_gauss);  // each context's own (made on first use)
+  c.d_gauss = nullptr;
   if (!c.owns_tables) return;
   void* ptrs[] = {c.d_mod,     c.d_pc,     c.d_modup,  c.d_moddown,
                   c.d_rescale, c.d_roots,  c.d_pow5,   c.d_rows, c.d_modup_scale, c.d_moddown_scale,

@@ -205,6 +205,7 @@ struct Context {
   RescaleTab* d_rescale = nullptr;   // [num_q]
   double* d_roots = nullptr;         // [2N][4]: exp(2 pi i j / 2N) in double-double (re hi, re lo, im hi, im lo)
   u32* d_pow5 = nullptr;             // [N/2]: 5^k mod 2N
+  u64* d_gauss = nullptr;            // the error sampler's cumulative thresholds (sampler.hip), made on first use
   int2* d_rows = nullptr;            // all row tables, packed
   std::vector<int> row_off[NUM_ROW_TABLES], row_cnt[NUM_ROW_TABLES];
 

@@ -91,6 +91,16 @@ _SIGS = {
     "hetal_encode": (ctypes.c_int, [_vp, _dblp, _dblp, ctypes.c_int, ctypes.c_double, _ctp]),
     "hetal_decode": (ctypes.c_int, [_vp, _ctp, _dblp, _dblp]),
     "hetal_encrypt": (ctypes.c_int, [_vp, _vp, _ctp, _u64p, _i64p, _ctp]),
+    "hetal_encrypt_seeded": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_uint64, ctypes.c_uint32, _ctp]),
+    "hetal_keygen": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "hetal_gen_evk": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int]),
+    "hetal_gaussian_table": (ctypes.c_int, [_u64p, ctypes.POINTER(ctypes.c_int)]),
+    "hetal_sample_ternary": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, _i64p]),
+    "hetal_sample_uniform": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                            ctypes.c_int, _u64p]),
+    "hetal_sample_gaussian": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                             _i64p]),
     "hetal_decrypt": (ctypes.c_int, [_vp, _vp, _ctp, _ctp]),
     "hetal_add": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
     "hetal_sub": (ctypes.c_int, [_vp, _ctp, _ctp, _ctp]),
@@ -108,6 +118,8 @@ _SIGS = {
     "hetal_ct_from_coeff": (ctypes.c_int, [_vp, _u64p, ctypes.c_int, ctypes.c_double, _ctp]),
     "hetal_mat_encrypt": (ctypes.c_int, [_vp, _vp, _dblp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          _u64p, _i64p, _matp]),
+    "hetal_mat_encrypt_seeded": (ctypes.c_int, [_vp, _vp, _dblp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, _matp]),
     "hetal_mat_decrypt": (ctypes.c_int, [_vp, _vp, _matp, _dblp]),
     "hetal_enc_matmul_abt": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
     "hetal_enc_matmul_atb": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
@@ -217,6 +229,20 @@ class Matrix:
         self.n_rb, self.n_cb, self.s0, self.s1, self.level, self.scale = m.n_rb, m.n_cb, m.s0, m.s1, m.level, m.scale
 
 
+def gaussian_table():
+    """The error sampler's 19 cumulative thresholds (hetal_gaussian_table)."""
+    out = np.empty(19, dtype=np.uint64)
+    n = ctypes.c_int(19)
+    _check(_lib.hetal_gaussian_table(out.ctypes.data_as(_u64p), ctypes.byref(n)))
+    return out[:n.value]
+
+
+def sample_ternary(log_n, seed, h):
+    out = np.empty(1 << log_n, dtype=np.int64)
+    _check(_lib.hetal_sample_ternary(int(log_n), int(seed), int(h), out.ctypes.data_as(_i64p)))
+    return out
+
+
 class Context:
     def __init__(self, preset="toy", device="cuda:0", **overrides):
         if not torch.cuda.is_available():
@@ -315,6 +341,23 @@ class Context:
     def keys_create(self):
         return KeySet(self)
 
+    def keygen(self, seed):
+        """The secret key drawn by the library from `seed` (hetal_keygen)."""
+        return SecretKey(self, None, None, seed=seed)
+
+    # -- the library's seeded sampler (for tests and callers that keep their own randomness) --
+    def sample_uniform(self, seed, purpose, index, rows, group):
+        out = np.empty((rows, self.n), dtype=np.uint64)
+        _check(_lib.hetal_sample_uniform(self._h, int(seed), int(purpose), int(index), int(rows), int(group),
+                                         out.ctypes.data_as(_u64p)))
+        return out
+
+    def sample_gaussian(self, seed, purpose, index, count):
+        out = np.empty((count, self.n), dtype=np.int64)
+        _check(_lib.hetal_sample_gaussian(self._h, int(seed), int(purpose), int(index), int(count),
+                                          out.ctypes.data_as(_i64p)))
+        return out
+
     # -- encoding / encryption --
     def encode(self, z, level, scale):
         z = np.asarray(z, dtype=np.complex128)
@@ -341,6 +384,14 @@ class Context:
         out = self.new_ct(pt.level)
         s = out._struct()
         _check(_lib.hetal_encrypt(self._h, sk._h, ctypes.byref(pt._struct()), ap, ep, ctypes.byref(s)))
+        out.level, out.scale = s.level, s.scale
+        return out
+
+    def encrypt_seeded(self, sk, pt, seed, index):
+        out = self.new_ct(pt.level)
+        s = out._struct()
+        _check(_lib.hetal_encrypt_seeded(self._h, sk._h, ctypes.byref(pt._struct()), int(seed), int(index),
+                                         ctypes.byref(s)))
         out.level, out.scale = s.level, s.scale
         return out
 
@@ -464,6 +515,17 @@ class Context:
         m = Matrix(self, n_rb * n_cb * self.ct_words(level), s0, level, scale)
         s = m._struct()
         _check(_lib.hetal_mat_encrypt(self._h, sk._h, mp, rows, cols, int(tiling), int(c), ap, ep, ctypes.byref(s)))
+        m._update(s)
+        return m
+
+    def mat_encrypt_seeded(self, sk, mat, s0, level, scale, seed, first_index, tiling=0, c=1):
+        mat, mp = _dbl(mat)
+        rows, cols = mat.shape
+        n_rb, n_cb = self.mat_blocks(rows, cols, s0, tiling, c)
+        m = Matrix(self, n_rb * n_cb * self.ct_words(level), s0, level, scale)
+        s = m._struct()
+        _check(_lib.hetal_mat_encrypt_seeded(self._h, sk._h, mp, rows, cols, int(tiling), int(c), int(seed),
+                                             int(first_index), ctypes.byref(s)))
         m._update(s)
         return m
 
@@ -653,10 +715,13 @@ class Graph:
 
 
 class SecretKey:
-    def __init__(self, ctx, s, sp):
+    def __init__(self, ctx, s, sp, seed=None):
         self.ctx = ctx
         h = _vp()
-        _check(_lib.hetal_sk_create(ctx._h, sp, ctypes.byref(h)))
+        if seed is None:
+            _check(_lib.hetal_sk_create(ctx._h, sp, ctypes.byref(h)))
+        else:
+            _check(_lib.hetal_keygen(ctx._h, int(seed), ctypes.byref(h)))
         self._h = h
 
     def __del__(self, _destroy=_lib.hetal_sk_destroy):
@@ -694,3 +759,15 @@ class KeySet:
         assert a.shape == (c.dnum, c.num_primes, c.n) and e.shape == (c.dnum, c.n)
         _check(_lib.hetal_keys_gen_galois(c._h, self._h, sk._h, int(g), ap, ep))
         self.galois.add(int(g))
+
+    def gen_evk(self, sk, seed, rot_steps=(), conj=False, relin=False):
+        """The relinearisation, rotation and conjugation keys with the library's randomness from `seed`."""
+        c = self.ctx
+        steps = (ctypes.c_int32 * max(1, len(rot_steps)))(*[int(r) for r in rot_steps])
+        _check(_lib.hetal_gen_evk(c._h, self._h, sk._h, int(seed), steps, len(rot_steps), int(bool(conj)),
+                                  int(bool(relin))))
+        for r in rot_steps:
+            if c.galois_rot(r) != 1:
+                self.galois.add(c.galois_rot(r))
+        if conj:
+            self.galois.add(c.galois_conj())
