@@ -406,50 +406,50 @@ def paper_shapes(reps):
 
 
 def uneven_requests(seed, count, per_shape):
-    """`count` seeded products of uneven shapes: rows 32..512, inner dimension 64..1024, classes 2..16, half DiagABT
-    (forward) and half DiagATB (gradient).  Standard encoding: s0 = 128 and c = 16 for all; per-shape encoding:
-    s0 = the next power of two >= rows, c = the next power of two >= classes."""
+    """`count` seeded products of uneven shapes (the survey's batching workload): rows 32..512, inner dimension
+    64..1024, classes 2..100, half DiagABT (forward) and half DiagATB (gradient).  Standard encoding: s0 = 128 and
+    c' = 128 for all; per-shape encoding: c' = the next power of two >= classes, s0 = the next power of two >= rows
+    (at least 32 and c', at most 32768 / c' so that c' divides s1)."""
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(count):
         rows = int(rng.integers(32, 513))
         inner = int(rng.integers(64, 1025))
-        classes = int(rng.integers(2, 17))
+        classes = int(rng.integers(2, 101))
         if per_shape:
-            s0 = 1 << max(5, (rows - 1).bit_length())
             c = 1 << max(1, (classes - 1).bit_length())
+            s0 = min(max(32, c, 1 << (rows - 1).bit_length()), 32768 // c)
         else:
-            s0, c = S0, C_PAD
+            s0, c = S0, 128
         reqs.append(dict(op="abt" if i % 2 == 0 else "atb", rows=rows, inner=inner, classes=classes, s0=s0, c=c))
     return reqs
 
 
-def uneven(count, per_shape):
-    """Many uneven products: one batched call against the same products issued one by one (one JSON line)."""
+def uneven(count, per_shape, tune_reps=1):
+    """Many uneven products (one JSON line): one by one, one batched call with the default schedules, the
+    autotuner's schedules, and the tuned batch replayed from a HIP graph; every result the same, word for word."""
     import torch
     from paper_2403_14111_amd import hetal, inputs
+    torch.cuda.set_stream(torch.cuda.Stream())   # graph capture needs a created stream
     ctx = hetal.Context("n16l12")
-    sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"], ctx.n))
+    sk = ctx.keygen(SEEDS["keys"])
     spec = uneven_requests(SEEDS["data"] + 7, count, per_shape)
     steps = set()
     for r in spec:
         steps |= set(ctx.required_rot_steps(0 if r["op"] == "abt" else 1, r["c"], r["s0"]))
     log("%d requests, %d rotation keys" % (len(spec), len(steps)))
     keys = ctx.keys_create()
-    ra, re_ = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
-    keys.gen_relin(sk, ra, re_)
-    for g in sorted(set(ctx.galois_rot(r) for r in steps) | {ctx.galois_conj()}):
-        ra, re_ = inputs.switch_key_randomness(SEEDS["keys"], inputs.key_id(1, g), ctx.dnum, ctx.primes, ctx.n)
-        keys.gen_galois(sk, g, ra, re_)
+    keys.gen_evk(sk, SEEDS["keys"], rot_steps=sorted(steps), conj=True, relin=True)
     reqs = []
     first = 0
     for n, r in enumerate(spec):
         def enc(mat, tiling):
             nonlocal first
             nb = int(np.prod(ctx.mat_blocks(mat.shape[0], mat.shape[1], r["s0"], tiling, r["c"])))
-            ea, ee = enc_randomness(ctx, nb, LEVEL, first)
+            m = ctx.mat_encrypt_seeded(sk, mat, r["s0"], LEVEL, 2.0 ** 40, SEEDS["enc"], first, tiling=tiling,
+                                       c=r["c"])
             first += nb
-            return ctx.mat_encrypt(sk, mat, r["s0"], LEVEL, 2.0 ** 40, ea, ee, tiling=tiling, c=r["c"])
+            return m
         X = inputs.features(SEEDS["data"] + 100 + n, r["rows"], r["inner"])
         if r["op"] == "abt":
             W = inputs.weights(SEEDS["data"] + 100 + n, r["classes"], r["inner"])
@@ -463,85 +463,165 @@ def uneven(count, per_shape):
         return [ctx.enc_matmul_abt(keys, a, b, c, t) if op == "abt" else ctx.enc_matmul_atb(keys, a, b, c, t)
                 for op, a, b, c, t in reqs]
 
+    def timed(fn, reps=2):
+        ts, out = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), out
+
+    log("warm-up")
     one_by_one()
-    ctx.enc_matmul_batch(keys, reqs)  # warm-up: masks encoded and cached
-    torch.cuda.synchronize()
+    ctx.enc_matmul_batch(keys, reqs)  # masks encoded and cached
+    log("one by one")
+    t_seq, seq = timed(one_by_one)
+    log("batched, default schedules")
+    t_bat, bat = timed(lambda: ctx.enc_matmul_batch(keys, reqs))
+    log("autotuning")
     t0 = time.perf_counter()
-    seq = one_by_one()
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    bat = ctx.enc_matmul_batch(keys, reqs)
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
-    same = all(x.level == y.level and x.n_rb == y.n_rb and x.n_cb == y.n_cb and
-               torch.equal(x.buf[:x.n_rb * x.n_cb * ctx.ct_words(x.level)],
-                           y.buf[:y.n_rb * y.n_cb * ctx.ct_words(y.level)]) for x, y in zip(seq, bat))
-    print(json.dumps({"uneven_matmuls": count, "encoding": "per-shape s0, c" if per_shape else "s0=128, c=16",
-                      "lockstep_groups": groups, "one_by_one_s": round(t_seq, 4), "batched_s": round(t_bat, 4),
-                      "one_by_one_matmuls_per_s": round(count / t_seq, 2),
-                      "batched_matmuls_per_s": round(count / t_bat, 2), "speedup": round(t_seq / t_bat, 3),
-                      "bitexact_batched_vs_one_by_one": bool(same),
+    _, rep = ctx.autotune_batch(keys, reqs, reps=tune_reps)
+    t_tuning = time.perf_counter() - t0
+    t_tuned, tuned = timed(lambda: ctx.enc_matmul_batch(keys, reqs))
+    log("graph of the tuned batch")
+    gouts, graph = ctx.enc_matmul_batch_graph(keys, reqs)
+
+    def replay():
+        graph.launch()
+        return gouts
+    t_graph, _ = timed(replay)
+
+    def same(xs, ys):
+        return all(x.level == y.level and x.n_rb == y.n_rb and x.n_cb == y.n_cb and
+                   torch.equal(x.buf[:x.n_rb * x.n_cb * ctx.ct_words(x.level)],
+                               y.buf[:y.n_rb * y.n_cb * ctx.ct_words(y.level)]) for x, y in zip(xs, ys))
+    bitexact = same(seq, bat) and same(seq, tuned) and same(seq, gouts)
+    chosen = {}
+    for op, a, b, c, t in reqs:
+        la = min(a.level, b.level) if op == "abt" else a.level
+        lb = la if op == "abt" else b.level
+        chosen["%s c=%d s0=%d" % (op, c, a.s0)] = ctx.tune_get(op, c, a.s0, la, lb)
+    print(json.dumps({"uneven_matmuls": count, "encoding": "per-shape s0, c'" if per_shape else "s0=128, c'=128",
+                      "lockstep_groups": groups,
+                      "matmuls_per_s": {"one_by_one": round(count / t_seq, 2), "batched_default": round(count / t_bat, 2),
+                                        "batched_tuned": round(count / t_tuned, 2),
+                                        "graph_tuned": round(count / t_graph, 2)},
+                      "speedup_vs_one_by_one": {"batched_default": round(t_seq / t_bat, 3),
+                                                "batched_tuned": round(t_seq / t_tuned, 3),
+                                                "graph_tuned": round(t_seq / t_graph, 3)},
+                      "tuned_vs_untuned": round(t_bat / t_tuned, 3), "graph_vs_eager_tuned": round(t_tuned / t_graph, 3),
+                      "tuner": dict(rep, seconds=round(t_tuning, 1)), "chosen": chosen,
+                      "bitexact_all_vs_one_by_one": bool(bitexact),
                       "shapes": [[r["op"], r["rows"], r["inner"], r["classes"], r["s0"], r["c"]] for r in spec]}),
           flush=True)
 
 
-def serve_bench(clients, count, rate, budget_gib):
-    """The request loop under Poisson arrivals: `clients` clients, each with its own keys and data (the 128x768x10
-    forward and gradient products of the benchmark, in the standard encoding), alternating DiagABT and DiagATB
-    requests; p50 / p99 latency beside throughput (one JSON line)."""
+def serve_bench(clients, count, rates, budget_gib, lanes):
+    """The request loop under Poisson arrivals (one JSON line): `clients` clients, each with its own seeded secret
+    and evaluation keys (resident), four of the 64 uneven product shapes of the batching workload each (two DiagABT,
+    two DiagATB, per-shape encoding), requests drawn uniformly over clients and their shapes.  Continuous batching
+    on `lanes` streams with admission by free device memory; the service capacity is measured first (the 64 shapes
+    in one batched call), then each offered rate is replayed: 0 stands for half the capacity (below saturation).
+    p50 / p99 latency beside throughput; a sample of served results against the same products computed alone."""
     import torch
     from paper_2403_14111_amd import hetal, inputs, serving
+    streams = serving.concurrent_streams(lanes)  # lanes on streams of their own, on separate hardware queues
+    torch.cuda.set_stream(streams[0])
     ctx = hetal.Context("n16l12")
-    server = serving.Server(ctx, int(budget_gib * 2 ** 30), sync=torch.cuda.synchronize)
-    data = {}
+    spec = uneven_requests(SEEDS["data"] + 7, 4 * clients, True)
+    data, owned = {}, {}
+    keysets, sks = {}, {}
+    first = 0
     for cl in range(clients):
-        log("client %d: keys and data" % cl)
-        sk = ctx.sk_create(inputs.ternary_secret(SEEDS["keys"] + 1 + cl, ctx.n))
+        mine = spec[4 * cl:4 * cl + 4]
+        steps = set()
+        for r in mine:
+            steps |= set(ctx.required_rot_steps(0 if r["op"] == "abt" else 1, r["c"], r["s0"]))
+        sk = ctx.keygen(SEEDS["keys"] + 1 + cl)
         keys = ctx.keys_create()
-        ra, re_ = inputs.switch_key_randomness(SEEDS["keys"] + 1 + cl, inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
-        keys.gen_relin(sk, ra, re_)
-        for g in sorted(set(ctx.galois_rot(r) for r in key_steps(ctx)) | {ctx.galois_conj()}):
-            ra, re_ = inputs.switch_key_randomness(SEEDS["keys"] + 1 + cl, inputs.key_id(1, g), ctx.dnum, ctx.primes,
-                                                   ctx.n)
-            keys.gen_galois(sk, g, ra, re_)
-        X = inputs.features(SEEDS["data"] + 200 + cl, A_ROWS, FEAT)
-        W = inputs.weights(SEEDS["data"] + 200 + cl, CLASSES, FEAT)
-        lab = inputs.labels(SEEDS["data"] + 200 + cl, A_ROWS, CLASSES)
-        PY = inputs.softmax_minus_onehot(X @ W.T, lab, CLASSES)
-        data[cl] = encrypt_inputs(ctx, sk, X, W, PY)
-        server.add_client(cl, keys)
-    rng = np.random.default_rng(SEEDS["data"] + 300)
-    arrivals = serving.poisson_arrivals(rng, rate, count)
-    who = rng.integers(0, clients, size=count)
-    reqs = []
-    for i, (t, cl) in enumerate(zip(arrivals, who)):
-        gx, gw, gpy = data[int(cl)]
-        if i % 2 == 0:
-            reqs.append(serving.Request(i, int(cl), "abt", gx, gw, C_PAD, 1.0, t))
-        else:
-            reqs.append(serving.Request(i, int(cl), "atb", gpy, gx, C_PAD, 1.0, t))
-    # warm-up: one request of each kind per client (masks encoded and cached, pool buffers sized)
-    for cl in range(clients):
-        gx, gw, gpy = data[cl]
-        ctx.enc_matmul_batch(server.keys[cl], [("abt", gx, gw, C_PAD, 1.0), ("atb", gpy, gx, C_PAD, 1.0)])
+        keys.gen_evk(sk, SEEDS["keys"] + 1 + cl, rot_steps=sorted(steps), conj=True, relin=True)
+        sks[cl], keysets[cl] = sk, keys
+        owned[cl] = []
+        for j, r in enumerate(mine):
+            n = 4 * cl + j
+            def enc(mat, tiling):
+                nonlocal first
+                nb = int(np.prod(ctx.mat_blocks(mat.shape[0], mat.shape[1], r["s0"], tiling, r["c"])))
+                m = ctx.mat_encrypt_seeded(sk, mat, r["s0"], LEVEL, 2.0 ** 40, SEEDS["enc"] + 1 + cl, first,
+                                           tiling=tiling, c=r["c"])
+                first += nb
+                return m
+            X = inputs.features(SEEDS["data"] + 100 + n, r["rows"], r["inner"])
+            if r["op"] == "abt":
+                W = inputs.weights(SEEDS["data"] + 100 + n, r["classes"], r["inner"])
+                data[(cl, j)] = ("abt", enc(X, 0), enc(W, 1), r["c"])
+            else:
+                PY = inputs.toy_matrix(SEEDS["data"] + 100 + n, r["rows"], r["classes"], 0) * 0.1
+                data[(cl, j)] = ("atb", enc(PY, 2), enc(X, 0), r["c"])
+            owned[cl].append(j)
+        log("client %d: %d rotation keys, 4 shapes encrypted" % (cl, len(steps)))
     torch.cuda.synchronize()
-    log("serving %d requests at %.1f/s from %d clients" % (count, rate, clients))
-    finished = serving.serve(server, reqs)
-    summary = serving.latency_summary(finished, rate)
-    sizes = [n for _, n, _ in server.rounds]
-    # a sample of served results against the same products computed alone
-    same = True
-    for r in finished[:: max(1, len(finished) // 8)]:
-        gx, gw, gpy = data[r.client]
-        alone = ctx.enc_matmul_batch(server.keys[r.client], [(r.op, r.a, r.b, r.c, r.t)])[0]
-        w = alone.n_rb * alone.n_cb * ctx.ct_words(alone.level)
-        same = same and r.result.level == alone.level and torch.equal(r.result.buf[:w], alone.buf[:w])
-    summary.update(clients=clients, rounds=len(sizes), mean_requests_per_round=round(float(np.mean(sizes)), 2),
-                   max_requests_per_round=int(max(sizes)), memory_budget_gib=budget_gib,
-                   bitexact_sampled_vs_alone=bool(same), workload="alternating DiagABT / DiagATB 128x768x10 "
-                   "(c=16, s0=128, level 11), per-client keys resident")
-    print(json.dumps({"serving": summary}), flush=True)
+    lane_ctxs = [ctx] + [ctx.share(st) for st in streams[1:]]
+    for lane in lane_ctxs:
+        lane.set_two_streams(lanes == 1)
+    log("warm-up on %d lanes" % lanes)
+    for lane in lane_ctxs:
+        with torch.cuda.stream(lane.stream):
+            for cl in range(clients):
+                lane.enc_matmul_batch(keysets[cl], [(op, a, b, c, 1.0) for op, a, b, c in
+                                                    (data[(cl, j)] for j in owned[cl])])
+    torch.cuda.synchronize()
+    # capacity: every client's four shapes, one batched call per client, all lanes busy
+    t0 = time.perf_counter()
+    for cl in range(clients):
+        lane = lane_ctxs[cl % lanes]
+        with torch.cuda.stream(lane.stream):
+            lane.enc_matmul_batch(keysets[cl], [(op, a, b, c, 1.0) for op, a, b, c in
+                                                (data[(cl, j)] for j in owned[cl])])
+    torch.cuda.synchronize()
+    capacity = 4 * clients / (time.perf_counter() - t0)
+    log("capacity %.1f products/s" % capacity)
+    out = {"clients": clients, "lanes": lanes, "capacity_products_per_s": round(capacity, 2),
+           "memory_budget_gib": budget_gib, "admission": "queue head in order while reservations fit the budget and "
+           "free device memory (hipMemGetInfo + the allocator's unused cache) minus 1 GiB",
+           "workload": "the 64 uneven shapes of the batching workload, 4 per client (2 DiagABT, 2 DiagATB), "
+           "per-shape s0 / c', level 11, N=2^16; per-client seeded keys resident", "runs": []}
+    rng = np.random.default_rng(SEEDS["data"] + 300)
+    for rate in rates:
+        offered = rate if rate > 0 else 0.5 * capacity
+        n = int(min(count, max(64, 20.0 * min(offered, capacity))))   # about 20 s of work at most
+        arrivals = serving.poisson_arrivals(rng, offered, n)
+        who = rng.integers(0, clients, size=n)
+        shape = rng.integers(0, 4, size=n)
+        reqs = []
+        for i in range(n):
+            op, a, b, c = data[(int(who[i]), int(shape[i]))]
+            reqs.append(serving.Request(i, int(who[i]), op, a, b, c, 1.0, arrivals[i]))
+        server = serving.Server(lane_ctxs, int(budget_gib * 2 ** 30), free_memory=serving.torch_free_memory)
+        for cl in range(clients):
+            server.add_client(cl, keysets[cl])
+        log("serving %d requests at %.1f/s" % (n, offered))
+        finished = serving.serve(server, reqs)
+        summary = serving.latency_summary(finished, round(offered, 2))
+        sizes = [r[1] for r in server.rounds]
+        same = True
+        for r in finished[:: max(1, len(finished) // 6)]:
+            with torch.cuda.stream(ctx.stream):
+                alone = ctx.enc_matmul_batch(keysets[r.client], [(r.op, r.a, r.b, r.c, r.t)])[0]
+            torch.cuda.synchronize()
+            w = alone.n_rb * alone.n_cb * ctx.ct_words(alone.level)
+            same = same and r.result.level == alone.level and torch.equal(r.result.buf[:w], alone.buf[:w])
+        summary.update(below_saturation=bool(offered < capacity), rounds=len(sizes),
+                       mean_requests_per_round=round(float(np.mean(sizes)), 2), max_requests_per_round=int(max(sizes)),
+                       rounds_admitted_while_others_in_flight=sum(1 for r in server.rounds if r[3] > 0),
+                       requests_per_lane=[sum(1 for r in finished if r.lane == k) for k in range(lanes)],
+                       bitexact_sampled_vs_alone=bool(same))
+        log("%s" % summary)
+        out["runs"].append(summary)
+        del finished, reqs, server
+    print(json.dumps({"serving": out}), flush=True)
 
 
 def softmax_bench(reps):
@@ -782,14 +862,17 @@ def main():
                          "runs' one")
     ap.add_argument("--pmc-steps", type=int, default=2)
     ap.add_argument("--uneven", type=int, default=0, metavar="COUNT",
-                    help="instead of the benchmark: COUNT seeded uneven products, one batched call against one by "
-                         "one, with the standard and the per-shape encodings (one JSON line each)")
+                    help="instead of the benchmark: COUNT seeded uneven products: one by one, one batched call, "
+                         "autotuned, and graph-replayed (one JSON line)")
+    ap.add_argument("--uneven-encoding", choices=("per-shape", "standard"), default="per-shape")
     ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
-                    help="instead of the benchmark: serve COUNT requests arriving as a Poisson process "
-                         "(--rate per second, --clients clients, --budget-gib admission budget); one JSON line")
-    ap.add_argument("--rate", type=float, default=60.0)
-    ap.add_argument("--clients", type=int, default=4)
-    ap.add_argument("--budget-gib", type=float, default=32.0)
+                    help="instead of the benchmark: serve up to COUNT requests per offered rate, arriving as a "
+                         "Poisson process (--rates per second, 0 = half the measured capacity; --clients clients, "
+                         "--lanes streams, --budget-gib admission budget); one JSON line")
+    ap.add_argument("--rates", default="0,200", help="comma-separated offered rates of --serve")
+    ap.add_argument("--clients", type=int, default=16)
+    ap.add_argument("--lanes", type=int, default=2)
+    ap.add_argument("--budget-gib", type=float, default=96.0)
     ap.add_argument("--softmax", type=int, default=0, metavar="REPS",
                     help="time the softmax approximation (App. softmax) at the forward product's shape, REPS runs")
     ap.add_argument("--train-step", type=int, default=0, metavar="STEPS",
@@ -817,8 +900,7 @@ def main():
         paper_shapes(args.steps)
         return
     if args.uneven:
-        uneven(args.uneven, False)
-        uneven(args.uneven, True)
+        uneven(args.uneven, args.uneven_encoding == "per-shape")
         return
     if args.softmax:
         softmax_bench(args.softmax)
@@ -828,7 +910,8 @@ def main():
         train_bench(args.train_step, rows, classes)
         return
     if args.serve:
-        serve_bench(args.clients, args.serve, args.rate, args.budget_gib)
+        serve_bench(args.clients, args.serve, [float(r) for r in args.rates.split(",")], args.budget_gib,
+                    args.lanes)
         return
     log("context + keys")
     if args.graph:

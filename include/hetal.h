@@ -134,6 +134,16 @@ const char* hetal_last_error(void);
  * temporaries.  `stream` is a hipStream_t (NULL = default stream).
  * E_PARAMS if the parameter set is outside the limits above. */
 int hetal_ctx_create(const hetal_params* params, void* stream, hetal_ctx** out);
+/* A context on `stream` that shares base's parameters and precomputed device tables (not copied), with a memory
+ * pool, mask cache, counters and timing of its own: for independent work on several streams at once (a request
+ * loop's lanes).  Secret keys and evaluation keys made with base serve it too (same parameters, same layout).
+ * base must outlive it; destroying it frees only what it owns. */
+int hetal_ctx_create_shared(hetal_ctx* base, void* stream, hetal_ctx** out);
+/* Whether hetal_enc_matmul_batch may run independent shape classes on the context's second stream (on by
+ * default; hetal_autotune_batch and hetal_tune_set choose it again, hetal_tune_reset turns it back on).  Lanes
+ * of a request loop turn it off: HIP maps streams onto a few hardware queues, and a second stream that waits on
+ * its lane's work can hold up another lane that shares its queue.  E_INVALID_ARG for a null context. */
+int hetal_ctx_set_two_streams(hetal_ctx* ctx, int enable);
 void hetal_ctx_destroy(hetal_ctx* ctx);
 int hetal_ctx_set_stream(hetal_ctx* ctx, void* stream);
 /* n: ring degree; slots: N/2; max_level: num_q - 1; num_primes: num_q + num_p. */
@@ -300,6 +310,45 @@ typedef struct {
  * single calls; on an error no output is written (checked before any work). */
 int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
                            hetal_mat* outs);
+
+/* ---- Schedule choices and the autotuner.  Every choice below leaves every result unchanged, word for word; they
+ * trade launch sizes, parallelism and recomputation.  ks_group: the most key switches one launch sequence takes
+ * (1..32); tpt_modup / tpt_moddown: target primes per workgroup task of the key switch's ModUp / ModDown kernels
+ * (each task recomputes its sources' inverse transforms; 0 = the library's rule); two_streams: independent shape
+ * classes of a batch alternate between the context's stream and a second one; work_cts: the working-set limit of
+ * a product, in ciphertexts at its level (0 = 2 GiB worth): the products of the k loop (DiagABT) or of the block
+ * columns (DiagATB) are made that many at a time and summed into place, and requests of one class run in lockstep
+ * while their run sums fit.  A shape class of
+ * hetal_enc_matmul_batch is (op, c, s0, level of A, level of B) (for DiagABT both levels are min(level A, level
+ * Bbar)). */
+typedef struct {
+  int ks_group;
+  int tpt_modup;
+  int tpt_moddown;
+  int two_streams;
+  int work_cts;
+} hetal_tune;
+
+typedef struct {
+  double untuned_ms; /* median time of the batch with the defaults */
+  double tuned_ms;   /* ... with the chosen schedules */
+  int classes;       /* shape classes in the batch */
+  int trials;        /* timed runs of a class or of the batch */
+  int two_streams;   /* the choice made for the batch */
+} hetal_tune_report;
+
+/* The autotuner: times `reps` runs (median) of each shape class of the batch alone under candidate schedules
+ * (coordinate descent over ks_group in {32, 16, 8, 4}, tpt_modup in {default, 2, 4, 6, 12}, tpt_moddown in
+ * {default, 2, 3, 6, 12}; a candidate must beat the current choice by 2%), keeps the best per class in the
+ * context, then chooses two_streams for the whole batch.  Later hetal_enc_matmul_batch calls (and graphs
+ * recorded after) use the choices; outs receive the batch's results.  Errors as hetal_enc_matmul_batch. */
+int hetal_autotune_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                         hetal_mat* outs, int reps, hetal_tune_report* report);
+/* The schedule a shape class runs with (the defaults if none was chosen), and setting it by hand; reset returns
+ * every class to the defaults. */
+int hetal_tune_get(const hetal_ctx* ctx, int op, int c, int s0, int level_a, int level_b, hetal_tune* out);
+int hetal_tune_set(hetal_ctx* ctx, int op, int c, int s0, int level_a, int level_b, const hetal_tune* in);
+int hetal_tune_reset(hetal_ctx* ctx);
 
 /* The products of hetal_enc_matmul_batch recorded into a HIP graph, for callers that repeat the same batch (a
  * training loop over fixed buffers, a serving loop): the call runs the batch twice eagerly (encoding the masks

@@ -55,13 +55,14 @@ __global__ void __launch_bounds__(TPB) cmult_batch_kernel(const u64* __restrict_
 }
 
 // Segment g of a launch is items [start[g], start[g+1]) of the input (start[0] = 0 relative to the launch's
-// first item).
+// first item); its sum goes to item dst[g] of the output.
 constexpr int MAX_SEGMENTS = 64;
 struct SegArgs {
   int start[MAX_SEGMENTS + 1];
+  int dst[MAX_SEGMENTS];
 };
 
-// out[g][row] = sum over the items t of segment g of a[t][row].
+// out[dst[g]][row] = sum over the items t of segment g of a[t][row].
 __global__ void __launch_bounds__(TPB) sum_segments_kernel(const u64* __restrict__ a, size_t a_stride, SegArgs sg,
                                                            u64* __restrict__ out, const ModInfo* __restrict__ mods,
                                                            int log_n, int level) {
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(TPB) sum_segments_kernel(const u64* __restrict
   const u64* __restrict__ src = a + (size_t)t0 * a_stride + (size_t)row * n + k;
   u64 s = 0;
   for (int t = 0; t < t1 - t0; ++t) s = add_mod(s, src[(size_t)t * a_stride], q);
-  out[(size_t)g * 2 * l * n + (size_t)row * n + k] = s;
+  out[(size_t)sg.dst[g] * 2 * l * n + (size_t)row * n + k] = s;
 }
 
 dim3 grid3(const Context& c, int y, int z) { return dim3((unsigned)(c.n / TPB), (unsigned)y, (unsigned)z); }
@@ -186,8 +187,9 @@ static void run_rotations(Context& c, const KeySet& k, const u64* in0, size_t in
                           size_t addx_stride = 0, size_t out_stride = 0) {
   const size_t poly = c.poly_words(level);
   const size_t w = out_stride ? out_stride : c.ct_words(level);
-  for (int first = 0; first < count; first += MAX_BATCH) {
-    const int m = std::min(MAX_BATCH, count - first);
+  const int group = std::max(1, std::min(MAX_BATCH, c.tune.ks_group));
+  for (int first = 0; first < count; first += group) {
+    const int m = std::min(group, count - first);
     KsJob job;
     job.level = level;
     job.count = m;
@@ -287,8 +289,9 @@ Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const s
     if (a[i].level != level || b[i].level != level) fail(HETAL_E_LEVEL, "hmult operands at different levels");
   Batch o(c, level, count);
   const size_t poly = c.poly_words(level), w = c.ct_words(level);
-  for (int first = 0; first < count; first += MAX_BATCH) {
-    const int m = std::min(MAX_BATCH, count - first);
+  const int group = std::max(1, std::min(MAX_BATCH, c.tune.ks_group));
+  for (int first = 0; first < count; first += group) {
+    const int m = std::min(group, count - first);
     Tmp d01(c.pool, (size_t)m * w), d2(c.pool, (size_t)m * poly);
     PtrArgs p;
     for (int i = 0; i < MAX_BATCH; ++i) {
@@ -344,29 +347,41 @@ Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSp
   return o;
 }
 
-Batch b_sum_segments(Context& c, BView a, const std::vector<int>& sizes) {
+void b_sum_segments_into(Context& c, BView a, const std::vector<int>& sizes, const std::vector<int>& dst, Batch& out) {
   int total = 0;
   for (int z : sizes) {
     if (z < 1) fail(HETAL_E_INVALID_ARG, "empty segment");
     total += z;
   }
   if (sizes.empty() || total != a.count) fail(HETAL_E_INVALID_ARG, "segments must cover the batch");
+  if (dst.size() != sizes.size() || out.level != a.level) fail(HETAL_E_INVALID_ARG, "segment destinations");
+  for (int d : dst)
+    if (d < 0 || d >= out.count) fail(HETAL_E_INVALID_ARG, "segment destination outside the output");
   const int l = a.level + 1;
   const int groups = (int)sizes.size();
-  Batch o(c, a.level, groups);
   int item = 0;
   for (int first = 0; first < groups; first += MAX_SEGMENTS) {
     const int m = std::min(MAX_SEGMENTS, groups - first);
     SegArgs sg;
     sg.start[0] = 0;
-    for (int g = 0; g < m; ++g) sg.start[g + 1] = sg.start[g] + sizes[first + g];
+    for (int g = 0; g < m; ++g) {
+      sg.start[g + 1] = sg.start[g] + sizes[first + g];
+      sg.dst[g] = dst[first + g];
+    }
     c.begin_launch();
     hipLaunchKernelGGL(sum_segments_kernel, grid3(c, 2 * l, m), dim3(TPB), 0, c.stream, a.d + (size_t)item * a.stride,
-                       a.stride, sg, o.d + (size_t)first * c.ct_words(a.level), c.d_mod, c.log_n, a.level);
+                       a.stride, sg, out.d, c.d_mod, c.log_n, a.level);
     c.end_launch(KC_ELEMWISE, 8.0 * c.n * 2.0 * l * (sg.start[m] + m));
     item += sg.start[m];
   }
-  o.scale = a.scale;
+  out.scale = a.scale;
+}
+
+Batch b_sum_segments(Context& c, BView a, const std::vector<int>& sizes) {
+  Batch o(c, a.level, std::max(1, (int)sizes.size()));
+  std::vector<int> dst(sizes.size());
+  for (size_t g = 0; g < dst.size(); ++g) dst[g] = (int)g;
+  b_sum_segments_into(c, a, sizes, dst, o);
   return o;
 }
 

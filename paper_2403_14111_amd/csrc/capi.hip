@@ -95,6 +95,26 @@ int hetal_ctx_create(const hetal_params* params, void* stream, hetal_ctx** out) 
   });
 }
 
+int hetal_ctx_create_shared(hetal_ctx* base, void* stream, hetal_ctx** out) {
+  return guarded([&] {
+    need(base && out, HETAL_E_INVALID_ARG, "null argument");
+    hetal_ctx* h = new hetal_ctx();
+    h->device = base->device;
+    context_share(h->c, base->c, (hipStream_t)stream);
+    h->masks.c = &h->c;
+    h->tuned = base->tuned;  // the schedules chosen so far (later tuning of either context stays its own)
+    h->two_streams = base->two_streams;
+    *out = h;
+  });
+}
+
+int hetal_ctx_set_two_streams(hetal_ctx* ctx, int enable) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    ctx->two_streams = enable != 0;
+  });
+}
+
 void hetal_ctx_destroy(hetal_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->c.stream);
@@ -1016,7 +1036,7 @@ static void matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
     }
     // Independent groups alternate between the main stream and a second one, so that one group's small
     // launches overlap the other's (unless per-kernel timing is on, which wants kernels one at a time).
-    const bool two = groups.size() >= 2 && !c.timing;
+    const bool two = groups.size() >= 2 && !c.timing && ctx->two_streams;
     std::unique_ptr<SideJoin> joined;
     if (two) {
       side_context(ctx);
@@ -1029,6 +1049,12 @@ static void matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
       MaskCache& mcx = on_side ? ctx->side_masks : ctx->masks;
       const int op = std::get<0>(kv.first), cc = std::get<1>(kv.first), s0 = std::get<2>(kv.first);
       const int s1 = c.slots / s0;
+      auto tuned = ctx->tuned.find({op, cc, s0, std::get<3>(kv.first), std::get<4>(kv.first)});
+      struct TuneScope {  // the class's schedule for this group only (also when an error unwinds)
+        Context& c;
+        ~TuneScope() { c.tune = Tune{}; }
+      } scope{cx};
+      cx.tune = tuned != ctx->tuned.end() ? tuned->second : Tune{};
       const std::vector<int>& idx = kv.second;
       Batch res;
       if (op == 0) {
@@ -1080,6 +1106,147 @@ static void matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_mat
 int hetal_enc_matmul_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
                            hetal_mat* outs) {
   return guarded([&] { matmul_batch(ctx, keys, reqs, count, outs); });
+}
+
+// Median time (ms) of `reps` runs of a batch, between events on the context's stream (the batch joins its second
+// stream back into it).
+static double time_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                         hetal_mat* outs, int reps) {
+  hipEvent_t e[2];
+  HCHECK(hipEventCreate(&e[0]));
+  HCHECK(hipEventCreate(&e[1]));
+  std::vector<double> t;
+  try {
+    for (int r = 0; r < reps; ++r) {
+      HCHECK(hipEventRecord(e[0], ctx->c.stream));
+      matmul_batch(ctx, keys, reqs, count, outs);
+      HCHECK(hipEventRecord(e[1], ctx->c.stream));
+      HCHECK(hipEventSynchronize(e[1]));
+      float ms = 0.0f;
+      HCHECK(hipEventElapsedTime(&ms, e[0], e[1]));
+      t.push_back(ms);
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e[0]);
+    (void)hipEventDestroy(e[1]);
+    throw;
+  }
+  (void)hipEventDestroy(e[0]);
+  (void)hipEventDestroy(e[1]);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+int hetal_autotune_batch(hetal_ctx* ctx, const hetal_keys* keys, const hetal_matmul_req* reqs, int count,
+                         hetal_mat* outs, int reps, hetal_tune_report* report) {
+  return guarded([&] {
+    need(ctx && keys && reqs && outs && count > 0 && reps >= 1, HETAL_E_INVALID_ARG, "bad argument");
+    need(!ctx->c.timing, HETAL_E_INVALID_ARG, "per-kernel timing is on");
+    ctx->tuned.clear();
+    ctx->two_streams = true;
+    matmul_batch(ctx, keys, reqs, count, outs);  // warm-up (masks encoded, pools sized); also validates
+    const double untuned = time_batch(ctx, keys, reqs, count, outs, reps);
+    // the shape classes of the batch, each tuned alone by coordinate descent over the schedule choices
+    std::map<std::array<int, 5>, std::vector<int>> classes;
+    for (int i = 0; i < count; ++i) {
+      const hetal_matmul_req& r = reqs[i];
+      const int lv_a = r.op == 0 ? std::min(r.a->level, r.b->level) : r.a->level;
+      const int lv_b = r.op == 0 ? lv_a : r.b->level;
+      classes[{r.op, r.c, r.a->s0, lv_a, lv_b}].push_back(i);
+    }
+    int trials = 0;
+    for (auto& kv : classes) {
+      std::vector<hetal_matmul_req> sr;
+      std::vector<hetal_mat> so;
+      for (int i : kv.second) {
+        sr.push_back(reqs[i]);
+        so.push_back(outs[i]);
+      }
+      auto run = [&](const Tune& t) {
+        ctx->tuned[kv.first] = t;
+        ++trials;
+        return time_batch(ctx, keys, sr.data(), (int)sr.size(), so.data(), reps);
+      };
+      Tune best;
+      double best_ms = run(best);
+      auto consider = [&](Tune cand) {
+        const double ms = run(cand);
+        if (ms < 0.98 * best_ms) {  // a choice must beat the current one by more than the timing noise
+          best = cand;
+          best_ms = ms;
+        }
+      };
+      for (int g : {16, 8, 4}) {
+        Tune t = best;
+        t.ks_group = g;
+        consider(t);
+      }
+      for (int v : {2, 4, 6, 12}) {
+        Tune t = best;
+        t.tpt_modup = v;
+        consider(t);
+      }
+      for (int v : {2, 3, 6, 12}) {
+        Tune t = best;
+        t.tpt_moddown = v;
+        consider(t);
+      }
+      ctx->tuned[kv.first] = best;
+    }
+    // the second stream for independent classes, with the tuned schedules
+    double tuned = time_batch(ctx, keys, reqs, count, outs, reps);
+    if (classes.size() >= 2) {
+      ctx->two_streams = false;
+      const double one = time_batch(ctx, keys, reqs, count, outs, reps);
+      ++trials;
+      if (one < tuned) tuned = one;
+      else ctx->two_streams = true;
+    }
+    if (report) {
+      report->untuned_ms = untuned;
+      report->tuned_ms = tuned;
+      report->classes = (int)classes.size();
+      report->trials = trials;
+      report->two_streams = ctx->two_streams ? 1 : 0;
+    }
+  });
+}
+
+int hetal_tune_get(const hetal_ctx* ctx, int op, int c, int s0, int level_a, int level_b, hetal_tune* out) {
+  return guarded([&] {
+    need(ctx && out, HETAL_E_INVALID_ARG, "null argument");
+    auto it = ctx->tuned.find({op, c, s0, level_a, level_b});
+    const Tune t = it != ctx->tuned.end() ? it->second : Tune{};
+    out->ks_group = t.ks_group;
+    out->tpt_modup = t.tpt_modup;
+    out->tpt_moddown = t.tpt_moddown;
+    out->two_streams = ctx->two_streams ? 1 : 0;
+    out->work_cts = t.work_cts;
+  });
+}
+
+int hetal_tune_set(hetal_ctx* ctx, int op, int c, int s0, int level_a, int level_b, const hetal_tune* in) {
+  return guarded([&] {
+    need(ctx && in, HETAL_E_INVALID_ARG, "null argument");
+    need(in->ks_group >= 1 && in->ks_group <= MAX_BATCH && in->tpt_modup >= 0 && in->tpt_moddown >= 0 &&
+             in->work_cts >= 0,
+         HETAL_E_INVALID_ARG, "schedule out of range");
+    Tune t;
+    t.ks_group = in->ks_group;
+    t.tpt_modup = in->tpt_modup;
+    t.tpt_moddown = in->tpt_moddown;
+    t.work_cts = in->work_cts;
+    ctx->tuned[{op, c, s0, level_a, level_b}] = t;
+    ctx->two_streams = in->two_streams != 0;
+  });
+}
+
+int hetal_tune_reset(hetal_ctx* ctx) {
+  return guarded([&] {
+    need(ctx, HETAL_E_INVALID_ARG, "null context");
+    ctx->tuned.clear();
+    ctx->two_streams = true;
+  });
 }
 
 struct hetal_graph {

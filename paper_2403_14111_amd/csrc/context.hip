@@ -109,6 +109,16 @@ void Pool::arena_end() {
   arena_marks_.clear();
 }
 
+// Buffers come in size classes (a multiple of an eighth of the size's power of two), and a request takes the
+// smallest free buffer of at least its class and at most twice it: the varied sizes of chunked work reuse each
+// other's buffers instead of piling up in the free list.
+static size_t size_class(size_t words) {
+  size_t top = 1;
+  while (top * 2 <= words) top *= 2;
+  const size_t unit = std::max<size_t>(1, top / 8);
+  return (words + unit - 1) / unit * unit;
+}
+
 u64* Pool::get(size_t words) {
   if (arena_) {
     const size_t need = arena_round(words);
@@ -120,8 +130,9 @@ u64* Pool::get(size_t words) {
     arena_top_ += need;
     return p;
   }
-  auto it = free_.find(words);
-  if (it != free_.end()) {
+  words = size_class(words);
+  auto it = free_.lower_bound(words);
+  if (it != free_.end() && it->first <= 2 * words) {
     u64* p = it->second;
     free_.erase(it);
     return p;

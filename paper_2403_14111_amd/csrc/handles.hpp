@@ -1,6 +1,8 @@
 // The C ABI's handle types and the argument checks and error translation shared by the extern "C" entry
 // points (capi.hip, noalloc.hip).
 #pragma once
+#include <array>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -18,6 +20,11 @@ struct hetal_ctx {
   hipStream_t side_stream = nullptr;
   hipEvent_t join[2] = {nullptr, nullptr};
   int device = 0;  // the HIP device that was current at creation
+  // Schedule choices per shape class (op, c, s0, input levels) of hetal_enc_matmul_batch, as hetal_autotune_batch
+  // or hetal_tune_set left them (classes not listed take the defaults), and whether independent classes use the
+  // second stream.
+  std::map<std::array<int, 5>, hetal::Tune> tuned;
+  bool two_streams = true;
 };
 
 struct hetal_sk {

@@ -187,6 +187,16 @@ struct RowsRef {
   int count;
 };
 
+// Schedule choices that leave every result unchanged, word for word (an autotuner picks them per shape class):
+// ks_group, the most key switches one launch sequence takes (up to MAX_BATCH); tpt_modup / tpt_moddown, the
+// target primes per workgroup task of the key switch's conversion kernels (0: the library's rule).
+struct Tune {
+  int ks_group = MAX_BATCH;
+  int tpt_modup = 0;
+  int tpt_moddown = 0;
+  int work_cts = 0;  // working-set limit of the matrix products, in ciphertexts (0 = the library's rule)
+};
+
 struct Context {
   int log_n = 0, n = 0, slots = 0;
   int num_q = 0, num_p = 0, dnum = 0, alpha = 0, nprimes = 0;
@@ -215,6 +225,7 @@ struct Context {
   bool owns_tables = true;  // false for a context sharing another's device tables (context_share)
 
   Pool pool;
+  Tune tune;
   int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // key switches per input level, and the key-switching keys read for them (one per lockstep batch that shares
   // a key, one per item otherwise): the inputs of the method's minimum HBM traffic

@@ -524,7 +524,7 @@ void key_switch(Context& c, const KsJob& job) {
     a.scale = c.d_modup_scale + (size_t)level * MAX_PRIMES;
     a.modup = c.d_modup + (size_t)level * c.dnum;
     a.num_q = c.num_q;
-    a.tpt = targets_per_task(c, maxcnt, beta, m_in);
+    a.tpt = c.tune.tpt_modup > 0 ? std::min(c.tune.tpt_modup, maxcnt) : targets_per_task(c, maxcnt, beta, m_in);
     a.tasks_per_group = (maxcnt + a.tpt - 1) / a.tpt;
     a.colgroups = colgroups;
     a.groups = beta * a.tasks_per_group * colgroups;
@@ -583,7 +583,7 @@ void key_switch(Context& c, const KsJob& job) {
     a.scale = c.d_moddown_scale;
     a.moddown = c.d_moddown;
     a.num_q = c.num_q;
-    a.tpt = targets_per_task(c, l, 2, m);
+    a.tpt = c.tune.tpt_moddown > 0 ? std::min(c.tune.tpt_moddown, l) : targets_per_task(c, l, 2, m);
     a.tasks_per_group = (l + a.tpt - 1) / a.tpt;
     a.colgroups = colgroups;
     a.groups = 2 * a.tasks_per_group * colgroups;

@@ -8,6 +8,11 @@ namespace hetal {
 
 std::vector<int> required_rot_steps(const Context& c, int op, int cc, int s0);
 
+// The most ciphertexts at `level` that one stage of DiagABT / DiagATB holds at once (Tune::work_cts, else 2 GiB
+// worth): the products are made in chunks of this size and summed into place, and a lockstep group whose run
+// sums exceed it runs as consecutive smaller groups.  Results do not depend on it.
+int work_limit(const Context& c, int level);
+
 // One product of a lockstep group: DiagABT <t A Bbar^T> (A: n_a x n_b blocks, Bbar: n_b blocks) or DiagATB
 // <t Abar^T B> (Abar: n_a blocks, B: n_a x n_b blocks).
 struct AbtRequest {

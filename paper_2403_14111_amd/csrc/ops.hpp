@@ -179,5 +179,7 @@ Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSp
 Batch b_sum_groups(Context& c, BView a, int groups);
 // out[g] = sum of the g-th run of sizes[g] consecutive items (the runs cover the batch in order).
 Batch b_sum_segments(Context& c, BView a, const std::vector<int>& sizes);
+// The same sums written to items dst[g] of `out` (allocated by the caller at a's level; other items untouched).
+void b_sum_segments_into(Context& c, BView a, const std::vector<int>& sizes, const std::vector<int>& dst, Batch& out);
 
 }  // namespace hetal

@@ -49,6 +49,16 @@ class _Mat(ctypes.Structure):
                 ("scale", ctypes.c_double)]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [("ks_group", ctypes.c_int), ("tpt_modup", ctypes.c_int), ("tpt_moddown", ctypes.c_int),
+                ("two_streams", ctypes.c_int), ("work_cts", ctypes.c_int)]
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("untuned_ms", ctypes.c_double), ("tuned_ms", ctypes.c_double), ("classes", ctypes.c_int),
+                ("trials", ctypes.c_int), ("two_streams", ctypes.c_int)]
+
+
 class _Req(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("a", ctypes.POINTER(_Mat)), ("b", ctypes.POINTER(_Mat)), ("c", ctypes.c_int),
                 ("t", ctypes.c_double)]
@@ -93,6 +103,8 @@ _SIGS = {
     "hetal_encrypt": (ctypes.c_int, [_vp, _vp, _ctp, _u64p, _i64p, _ctp]),
     "hetal_encrypt_seeded": (ctypes.c_int, [_vp, _vp, _ctp, ctypes.c_uint64, ctypes.c_uint32, _ctp]),
     "hetal_keygen": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "hetal_ctx_create_shared": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "hetal_ctx_set_two_streams": (ctypes.c_int, [_vp, ctypes.c_int]),
     "hetal_gen_evk": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int]),
     "hetal_gaussian_table": (ctypes.c_int, [_u64p, ctypes.POINTER(ctypes.c_int)]),
@@ -124,6 +136,11 @@ _SIGS = {
     "hetal_enc_matmul_abt": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
     "hetal_enc_matmul_atb": (ctypes.c_int, [_vp, _vp, _matp, _matp, ctypes.c_int, ctypes.c_double, _matp]),
     "hetal_enc_matmul_batch": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp]),
+    "hetal_autotune_batch": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp, ctypes.c_int,
+                                            ctypes.POINTER(_TuneReport)]),
+    "hetal_tune_get": (ctypes.c_int, [_vp] + [ctypes.c_int] * 5 + [ctypes.POINTER(_Tune)]),
+    "hetal_tune_set": (ctypes.c_int, [_vp] + [ctypes.c_int] * 5 + [ctypes.POINTER(_Tune)]),
+    "hetal_tune_reset": (ctypes.c_int, [_vp]),
     "hetal_required_rot_steps": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _intp]),
     "hetal_enc_matmul_batch_graph": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_Req), ctypes.c_int, _matp,
                                                     ctypes.POINTER(_vp)]),
@@ -267,6 +284,22 @@ class Context:
         self.dnum = cfg["dnum"]
         self.q = self.primes[:self.num_q]
         self.p = self.primes[self.num_q:]
+
+    def share(self, stream):
+        """A context on the torch stream `stream` sharing this one's parameters, tables and keys
+        (hetal_ctx_create_shared); this context must outlive it."""
+        other = object.__new__(Context)
+        other.__dict__.update({k: v for k, v in self.__dict__.items() if k != "_h"})
+        other.stream = stream
+        other.base = self
+        h = _vp()
+        _check(_lib.hetal_ctx_create_shared(self._h, _vp(stream.cuda_stream), ctypes.byref(h)))
+        other._h = h
+        return other
+
+    def set_two_streams(self, on):
+        """Whether batched products may use the context's second stream (hetal_ctx_set_two_streams)."""
+        _check(_lib.hetal_ctx_set_two_streams(self._h, int(bool(on))))
 
     # The destroy functions are bound as default arguments: at interpreter shutdown the module's globals
     # (_lib included) may already be cleared when the last handles are collected.
@@ -550,7 +583,7 @@ class Context:
         out._update(s)
         return out
 
-    def enc_matmul_batch(self, keys, reqs):
+    def enc_matmul_batch(self, keys, reqs, _autotune_reps=0):
         """[(op, a, b, c, t), ...] with op "abt" or "atb" -> the list of results, each exactly what
         enc_matmul_abt / enc_matmul_atb returns for it; requests sharing (op, c, s0, levels, scales) run in lockstep."""
         n = len(reqs)
@@ -569,10 +602,39 @@ class Context:
             outs.append(out)
             arr[i] = _Req(0 if op == "abt" else 1, ctypes.pointer(sa), ctypes.pointer(sb), int(c), float(t))
         structs = (_Mat * max(n, 1))(*[o._struct() for o in outs])
-        _check(_lib.hetal_enc_matmul_batch(self._h, keys._h, arr, n, structs))
+        if _autotune_reps:
+            rep = _TuneReport()
+            _check(_lib.hetal_autotune_batch(self._h, keys._h, arr, n, structs, int(_autotune_reps),
+                                             ctypes.byref(rep)))
+            self.last_tune_report = dict(untuned_ms=rep.untuned_ms, tuned_ms=rep.tuned_ms, classes=rep.classes,
+                                         trials=rep.trials, two_streams=bool(rep.two_streams))
+        else:
+            _check(_lib.hetal_enc_matmul_batch(self._h, keys._h, arr, n, structs))
         for o, s in zip(outs, structs):
             o._update(s)
         return outs
+
+    def autotune_batch(self, keys, reqs, reps=3):
+        """The autotuner (hetal_autotune_batch) on this batch: -> (outputs, report); later batches of these shape
+        classes run with the chosen schedules."""
+        outs = self.enc_matmul_batch(keys, reqs, _autotune_reps=reps)
+        return outs, self.last_tune_report
+
+    def tune_get(self, op, c, s0, level_a, level_b):
+        t = _Tune()
+        _check(_lib.hetal_tune_get(self._h, 0 if op == "abt" else 1, int(c), int(s0), int(level_a), int(level_b),
+                                   ctypes.byref(t)))
+        return dict(ks_group=t.ks_group, tpt_modup=t.tpt_modup, tpt_moddown=t.tpt_moddown,
+                    two_streams=bool(t.two_streams), work_cts=t.work_cts)
+
+    def tune_set(self, op, c, s0, level_a, level_b, ks_group=32, tpt_modup=0, tpt_moddown=0, two_streams=True,
+                 work_cts=0):
+        t = _Tune(int(ks_group), int(tpt_modup), int(tpt_moddown), int(bool(two_streams)), int(work_cts))
+        _check(_lib.hetal_tune_set(self._h, 0 if op == "abt" else 1, int(c), int(s0), int(level_a), int(level_b),
+                                   ctypes.byref(t)))
+
+    def tune_reset(self):
+        _check(_lib.hetal_tune_reset(self._h))
 
     def enc_matmul_batch_graph(self, keys, reqs):
         """enc_matmul_batch recorded into a HIP graph -> (outputs, graph); graph.launch() recomputes the outputs

@@ -1,5 +1,7 @@
-"""The request loop on the GPU (toy ring): two clients with their own keys, requests of both kinds arriving in a
-burst; every served result must equal the same product computed alone, word for word."""
+"""The request loop on the GPU (toy ring): two clients with their own seeded keys, two lanes (contexts on their own
+streams).  A second round arrives while the first is still on the device (held there by a spin on its lane), is
+admitted at once and runs on the other lane, finishing first; every served result equals the same product computed
+alone, word for word."""
 import sys
 
 import pytest
@@ -7,54 +9,80 @@ import torch
 
 from oracle import matrix as mx
 from paper_2403_14111_amd import inputs
-from tests.gpu_setup import make_gpu
-from tests.test_gpu_parity import enc_mat_gpu
 
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_standalone_products():
-    from paper_2403_14111_amd import serving
-    print("[case] serving: two clients, twelve requests", file=sys.stderr, flush=True)
+def note(msg):
+    print("[case] serving: " + msg, file=sys.stderr, flush=True)
+
+
+def test_requests_arriving_in_flight_overlap_and_equal_standalone_products():
+    from paper_2403_14111_amd import hetal, serving
     s0, c = 16, 8
     steps = sorted(set(mx.rotation_steps("abt", c, s0, 128)) | set(mx.rotation_steps("atb", c, s0, 128)))
-    ctx, sk0, keys0 = make_gpu("toy", seed=2100, rot_steps=steps)
-    clients = {0: (sk0, keys0), 1: make_keys(ctx, 2101, steps)}
-    server = serving.Server(ctx, 1 << 34, sync=torch.cuda.synchronize)
+    note("context, two lanes, two clients")
+    s_a, s_b = serving.concurrent_streams(2)             # lanes on streams of their own, on separate hardware queues
+    with torch.cuda.stream(s_a):
+        ctx = hetal.Context("toy")
+    lanes = [ctx, ctx.share(s_b)]
+    server = serving.Server(lanes, 1 << 34, free_memory=serving.torch_free_memory)
+    assert all(not lane.tune_get("abt", c, s0, 4, 4)["two_streams"] for lane in lanes)
     data = {}
-    for cl, (sk, keys) in clients.items():
+    for cl in (0, 1):
+        sk = ctx.keygen(4100 + cl)
+        keys = ctx.keys_create()
+        keys.gen_evk(sk, 4100 + cl, rot_steps=steps, conj=True, relin=True)
         server.add_client(cl, keys)
         X = inputs.toy_matrix(7000 + cl, 16, 40, 0)
         W = inputs.toy_matrix(7000 + cl, 6, 40, 1)
         P = inputs.toy_matrix(7100 + cl, 16, 6, 0)
-        data[cl] = (enc_mat_gpu(ctx, sk, X, s0, 4, 0, c, 90 + cl)[0], enc_mat_gpu(ctx, sk, W, s0, 4, 1, c, 92 + cl)[0],
-                    enc_mat_gpu(ctx, sk, P, s0, 4, 2, c, 94 + cl)[0])
-    reqs = []
-    for i in range(12):
-        cl = [0, 1, 1, 0, 0, 1, 0, 1, 1, 1, 0, 0][i]
+        data[cl] = (ctx.mat_encrypt_seeded(sk, X, s0, 4, 2.0 ** 40, 4100 + cl, 0),
+                    ctx.mat_encrypt_seeded(sk, W, s0, 4, 2.0 ** 40, 4100 + cl, 10, tiling=1, c=c),
+                    ctx.mat_encrypt_seeded(sk, P, s0, 4, 2.0 ** 40, 4100 + cl, 20, tiling=2, c=c))
+
+    def reqs_of(cl, first):
         gx, gw, gp = data[cl]
-        if i % 3 == 2:
-            reqs.append(serving.Request(i, cl, "atb", gp, gx, c, 0.5, 0.0))
-        else:
-            reqs.append(serving.Request(i, cl, "abt", gx, gw, c, 1.0 + i, 0.0))
-    finished = serving.serve(server, reqs)
-    assert sorted(r.rid for r in finished) == list(range(12))
-    assert len(server.rounds) == 1 and server.rounds[0][1:] == (12, 2)
-    for r in finished:
-        alone = (ctx.enc_matmul_abt(server.keys[r.client], r.a, r.b, r.c, r.t) if r.op == "abt"
-                 else ctx.enc_matmul_atb(server.keys[r.client], r.a, r.b, r.c, r.t))
+        out = []
+        for i in range(6):
+            if i % 3 == 2:
+                out.append(serving.Request(first + i, cl, "atb", gp, gx, c, 0.5))
+            else:
+                out.append(serving.Request(first + i, cl, "abt", gx, gw, c, 1.0 + i))
+        return out
+
+    note("warm-up: masks encoded on both lanes")
+    for lane in lanes:
+        with torch.cuda.stream(lane.stream):
+            for cl in (0, 1):
+                lane.enc_matmul_batch(server.keys[cl], [(r.op, r.a, r.b, r.c, r.t) for r in reqs_of(cl, 0)])
+    torch.cuda.synchronize()
+
+    note("round 1 behind a spin on lane 0, round 2 while it is in flight")
+    with torch.cuda.stream(lanes[0].stream):
+        torch.cuda._sleep(100_000_000)                   # tens of ms of spinning: round 1 stays in flight
+    first = reqs_of(0, 0)
+    for r in first:
+        server.submit(r)
+    server.step()
+    assert [g.lane for g in server.inflight] == [0]
+    second = reqs_of(1, 100)
+    for r in second:
+        server.submit(r)
+    server.step()
+    assert server.rounds[1][3] == 6                      # admitted with round 1's six requests in flight
+    assert all(r.lane == 1 for r in second)
+    finished = []
+    while server.inflight:
+        finished += server.step()
+    assert sorted(r.rid for r in finished) == [r.rid for r in first + second]
+    assert max(r.done for r in second) < min(r.done for r in first)   # round 2 overlapped and finished first
+    note("results against standalone products")
+    with torch.cuda.stream(ctx.stream):
+        alones = [ctx.enc_matmul_abt(server.keys[r.client], r.a, r.b, r.c, r.t) if r.op == "abt"
+                  else ctx.enc_matmul_atb(server.keys[r.client], r.a, r.b, r.c, r.t) for r in finished]
+    torch.cuda.synchronize()
+    for r, alone in zip(finished, alones):
         w = alone.n_rb * alone.n_cb * ctx.ct_words(alone.level)
         assert r.result.level == alone.level and r.result.scale == alone.scale
         assert torch.equal(r.result.buf[:w], alone.buf[:w]), r.rid
-
-
-def make_keys(ctx, seed, steps):
-    """A second client's secret and keys in an existing context."""
-    sk = ctx.sk_create(inputs.ternary_secret(seed, ctx.n))
-    keys = ctx.keys_create()
-    a, e = inputs.switch_key_randomness(seed, inputs.key_id(0), ctx.dnum, ctx.primes, ctx.n)
-    keys.gen_relin(sk, a, e)
-    for g in sorted(set(ctx.galois_rot(r) for r in steps) | {ctx.galois_conj()}):
-        a, e = inputs.switch_key_randomness(seed, inputs.key_id(1, g), ctx.dnum, ctx.primes, ctx.n)
-        keys.gen_galois(sk, g, a, e)
-    return sk, keys
