@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ks_inner_kernel(InnerArgs a, cons
       asm volatile("" ::: "memory");
     }
     if (own) {
-      lds_exchange<true>(x, ls, spread, block);
+      lds_exchange<true, true>(x, ls, spread, block);
     } else {
       auto stages = [&](auto lz) {
         constexpr bool LZ = decltype(lz)::value;
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ks_inner_kernel(InnerArgs a, cons
           for (int u = 0; u < NTT_R; ++u)
             if (!(u & hu)) fwd_bfly<LZ>(x[u], x[u + hu], twf_spread(l, u), q, qi);
         }
-        lds_exchange<true>(x, ls, spread, block);
+        lds_exchange<true, true>(x, ls, spread, block);
 #pragma unroll
         for (int l = 4; l < 8; ++l) {
           const int half = 1 << (7 - l);
@@ -374,10 +374,10 @@ __global__ void __launch_bounds__(NTT_THREADS) ks_inner_kernel(InnerArgs a, cons
     }
     u64* __restrict__ ob = accp + (size_t)t * n;
     u64* __restrict__ oa = accp + (size_t)(a.ext + t) * n;
-    lds_exchange<true>(accb, ls, block, spread);
+    lds_exchange<true, true>(accb, ls, block, spread);
 #pragma unroll
     for (int u = 0; u < NTT_R; ++u) (ob + 16 * u)[sp_off] = mid_st(accb[u]);
-    lds_exchange<true>(acca, ls, block, spread);
+    lds_exchange<true, true>(acca, ls, block, spread);
 #pragma unroll
     for (int u = 0; u < NTT_R; ++u) (oa + 16 * u)[sp_off] = mid_st(acca[u]);
     return;
@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ks_inner_kernel(InnerArgs a, cons
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
       }
-      lds_exchange<true>(x, ls, block, spread);
+      lds_exchange<true, true>(x, ls, block, spread);
 #pragma unroll
       for (int l = 3; l >= 0; --l) {
         const int hu = 8 >> l;

@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
           if (!(u & hu)) fwd_bfly<LZ>(x[u], x[u + hu], tw_spread(l, u), q, qi);
       }
       if (L > 4) {
-        lds_exchange<false>(x, ls, spread, block);
+        lds_exchange<false, CONTIG>(x, ls, spread, block);
 #pragma unroll
         for (int l = 4; l < L; ++l) {
           const int half = 1 << (L - 1 - l);
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
     if (CONTIG && EPI) {
       // (a - x) c + addends: a - x in [-q, q], its product in (-0.75q, 1.75q), plus two residues: below
       // 3.75q < 2^52 before the reduction
-      lds_exchange<true>(x, ls, block, spread);
+      lds_exchange<true, true>(x, ls, block, spread);
       const int p = rj.x >= epi.l ? 1 : 0;
       const int i = rj.y;
       const double cst = u2d(epi.cst[i]);
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         const u32 gi = epi.ginv[item];
         out_chunk = galois_source(out_chunk, gi, log_n) & ~255u;
         auto dest = [&](int u) { return pad_idx((int)(galois_source(sp_off + sp_step * u, gi, log_n) & 255u)); };
-        lds_exchange<true>(x, ls, dest, spread);
+        lds_exchange<true, true>(x, ls, dest, spread);
       }
       const u32 o_off = out_chunk + (u32)j;
 #pragma unroll
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         eo[k] = d2u(ffix(fred(v, q, qi), q));
       }
     } else if (CONTIG) {
-      lds_exchange<true>(x, ls, block, spread);
+      lds_exchange<true, true>(x, ls, block, spread);
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) (a + sp_step * u)[sp_off] = d2u(x[u]);
     } else if (L > 4) {
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       if (CONTIG) {
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
-        lds_exchange<false>(x, ls, spread, block);
+        lds_exchange<false, true>(x, ls, spread, block);
       } else if (L > 4) {
 #pragma unroll
         for (int u = 0; u < NTT_R; ++u) x[u] = mid_ld((ain + bl_step * u)[bl_off]);
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
           for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
         }
         if (CONTIG)
-          lds_exchange<true>(x, ls, block, spread);
+          lds_exchange<true, true>(x, ls, block, spread);
         else
           lds_exchange<false>(x, ls, block, spread);
       }

@@ -32,22 +32,35 @@ __device__ __forceinline__ u64 d2u(double v) {
 __device__ __forceinline__ u64 mid_st(double v) { return (u64)__double_as_longlong(v); }
 __device__ __forceinline__ double mid_ld(u64 w) { return __longlong_as_double((long long)w); }
 
+// Waits until the calling wavefront's LDS accesses so far have completed; the compiler moves no memory access
+// across it.
+__device__ __forceinline__ void wave_lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // Transpose through LDS: x[u] is stored at word widx(u) of the workgroup's buffer, then x[u] is
 // loaded from word ridx(u).  The 64-bit values travel as two 32-bit halves through a 32-bit
-// buffer, which halves the LDS a workgroup holds.  LEAD_SYNC: the buffer was read before.
-template <bool LEAD_SYNC, class W, class R>
+// buffer, which halves the LDS a workgroup holds.  LEAD_SYNC: the buffer was read before.  WAVE: every
+// lane that reads a word written here belongs to the writer's wavefront (the 16 threads of a contiguous
+// sub-transform are consecutive lanes, with a slice of the buffer of their own), so waiting for the wavefront's
+// own LDS accesses is enough and no workgroup barrier is taken.
+template <bool LEAD_SYNC, bool WAVE = false, class W, class R>
 __device__ __forceinline__ void lds_exchange(double (&x)[NTT_R], u32* __restrict__ ls, W widx, R ridx) {
-  if (LEAD_SYNC) __syncthreads();
+  auto sync = [] {
+    if (WAVE)
+      wave_lds_wait();
+    else
+      __syncthreads();
+  };
+  if (LEAD_SYNC) sync();
 #pragma unroll
   for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = lo32((u64)__double_as_longlong(x[u]));
-  __syncthreads();
+  sync();
   u32 lo[NTT_R];
 #pragma unroll
   for (int u = 0; u < NTT_R; ++u) lo[u] = ls[ridx(u)];
-  __syncthreads();
+  sync();
 #pragma unroll
   for (int u = 0; u < NTT_R; ++u) ls[widx(u)] = hi32((u64)__double_as_longlong(x[u]));
-  __syncthreads();
+  sync();
 #pragma unroll
   for (int u = 0; u < NTT_R; ++u) x[u] = __longlong_as_double((long long)(((u64)ls[ridx(u)] << 32) | lo[u]));
 }
