@@ -93,7 +93,7 @@ PROFILE_CLASSES = [
     ("ntt_pass_kernel<8, true, true, false>", "ntt_inv_contig"),
     ("ntt_pass_kernel<8, true, false, false>", "ntt_inv_strided"),
     ("ks_inner_kernel", "ks_inner"),
-    ("rescale_", "rescale"),
+    ("modconv_kernel<8, 2,", "rescale"),
 ]
 PROFILE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "kernels_n16l12_matmul_step.md")
 
@@ -112,7 +112,7 @@ def kernel_sources_digest(cls=None):
     if cls is None:
         files = sorted(f for f in os.listdir(d) if f.endswith((".hip", ".hpp")))
     else:
-        files = KERNEL_SOURCES["ntt" if cls.startswith("ntt_") else "ks" if cls.startswith("ks_") else "rns"]
+        files = KERNEL_SOURCES["ntt" if cls.startswith("ntt_") else "ks" if cls.startswith(("ks_", "rescale")) else "rns"]
     h = hashlib.sha256()
     for f in files:
         h.update(f.encode())

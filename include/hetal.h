@@ -476,8 +476,9 @@ int hetal_ks_counts(const hetal_ctx* ctx, int64_t* items, int64_t* key_reads, in
  * ModDown / rescale combine), [5] inverse NTT, contiguous first pass,
  * [6] inverse NTT, strided final pass, [7] the key inner product (with the
  * forward contiguous pass of the extended digits before it and the inverse
- * contiguous pass of the special rows after it), [8] rescale (the top limb's
- * centred spread), [9] elementwise, [10] encode / decode.  enable(on) clears
+ * contiguous pass of the special rows after it), [8] the rescale's conversion
+ * kernel (inverse strided pass of the top limbs, their centred lift to every
+ * q_i, forward strided pass), [9] elementwise, [10] encode / decode.  enable(on) clears
  * what was collected; get synchronises and fills, per class, the summed kernel
  * time in ms, the launch count and the summed algorithmic HBM bytes (each
  * operand read once and each result written once) into caller arrays of

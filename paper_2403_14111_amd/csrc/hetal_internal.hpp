@@ -68,8 +68,9 @@ struct FpMod {
 
 // q_l^-1 mod q_i (i < l) for the rescale at level l.
 struct RescaleTab {
-  u64 inv[MAX_PRIMES];
+  u64 inv[MAX_PRIMES];  // q_level^-1 mod q_i
   u64 inv_sh[MAX_PRIMES];
+  NttScale top;         // the plain N^-1 scaling of the inverse transform's last stage, modulo q_level
 };
 
 // Per prime: N^-1, and psi^-brev(1) N^-1 (the last inverse butterfly with N^-1 merged);
@@ -379,6 +380,7 @@ void k_mul_rows(Context& c, const u64* a, const u64* b, u64* out, int rows, int 
 void k_mul_i(Context& c, const u64* a, u64* out, int rows, int period);
 void k_galois(Context& c, const u64* a, u64* out, int rows, int period, u32 g);
 void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int level);
+// Rescale of `batch` ciphertexts (keyswitch.hip: ModDown's three-launch pipeline from the single prime q_level).
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride);
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
                      size_t out_stride);

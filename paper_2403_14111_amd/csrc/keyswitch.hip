@@ -43,6 +43,7 @@ using namespace fp64;
 
 constexpr int KIND_MODUP = 0;
 constexpr int KIND_MODDOWN = 1;
+constexpr int KIND_RESCALE = 2;  // one source, the top prime q_level of each polynomial; conversion factor 1
 constexpr int MAX_CONV = 4;  // terms of a fused conversion: alpha and K are at most this
 
 // ------------------------------------------------------------------ basis conversion passes (launches 2 and 4)
@@ -55,8 +56,10 @@ struct ConvArgs {
   int first[2 * MAX_CONV];  // per source group: its first entry in `targets`, and its count (MODUP: digits,
   int count[2 * MAX_CONV];  // MODDOWN: the two polynomials)
   int nsrc[2 * MAX_CONV];   // MODUP: rows of each digit (a short last digit has fewer)
-  int src_row0[2 * MAX_CONV];  // first source row of each group (MODUP: the digit's first limb; MODDOWN: p ext + l)
-  const NttScale* scale;   // per source row (MODUP: indexed by limb; MODDOWN: by p K + k)
+  int src_row0[2 * MAX_CONV];  // first source row of each group (MODUP: the digit's first limb; MODDOWN: p ext + l;
+                               // RESCALE: p)
+  const NttScale* scale;   // per source row (MODUP: indexed by limb; MODDOWN: by p K + k; RESCALE: one)
+  int src_prime;           // RESCALE: the source prime's index (the level)
   const ModUpTab* modup;   // MODUP: the level's digit tables
   const ModDownTab* moddown;
   int num_q;
@@ -115,8 +118,8 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
   for (int i = 0; i < CNT; ++i) {
     if (i >= nsrc) continue;  // a short last digit: zero terms (its constants beyond the length are zero too)
     const int row = a.src_row0[sg] + i;
-    const int prime = KIND == KIND_MODUP ? row : a.num_q + i;
-    const NttScale sc = a.scale[KIND == KIND_MODUP ? row : sg * CNT + i];
+    const int prime = KIND == KIND_MODUP ? row : KIND == KIND_MODDOWN ? a.num_q + i : a.src_prime;
+    const NttScale sc = a.scale[KIND == KIND_MODUP ? row : KIND == KIND_MODDOWN ? sg * CNT + i : 0];
     const FpMod fm = fpm[prime];
     const double q = fm.q, qi = fm.qinv;
     const double* __restrict__ w = tw_inv + (size_t)prime * n;
@@ -160,8 +163,8 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
       stages(std::true_type{});
     else
       stages(std::false_type{});
-    if (KIND == KIND_MODDOWN) {
-      const double ph = __builtin_floor(q * 0.5);  // (p_k - 1) / 2: values above it are taken as negative
+    if (KIND != KIND_MODUP) {
+      const double ph = __builtin_floor(q * 0.5);  // (p - 1) / 2: values above it are taken as negative
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) x[u] = x[u] > ph ? x[u] - q : x[u];
     }
@@ -177,12 +180,14 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
     double cc[CNT];
 #pragma unroll
     for (int i = 0; i < CNT; ++i)
-      cc[i] = u2d(KIND == KIND_MODUP ? a.modup[sg].dhat[i][rt.y] : a.moddown->phat[i][rt.y]);
+      cc[i] = KIND == KIND_RESCALE ? 1.0
+                                   : u2d(KIND == KIND_MODUP ? a.modup[sg].dhat[i][rt.y] : a.moddown->phat[i][rt.y]);
     double x[NTT_R];
     auto stages = [&](auto lazy) {
       constexpr bool LZ = decltype(lazy)::value;
       asm volatile("" ::: "memory");
-      // MODUP: y_i < 2^50, each product in (-0.375 t, 1.375 t); MODDOWN: |y_k| < 2^49, in (-0.19 q, 1.19 q).
+      // MODUP: y_i < 2^50, each product in (-0.375 t, 1.375 t); MODDOWN and RESCALE: |y_k| < 2^49, in
+      // (-0.19 q, 1.19 q).
       // The reducing form reduces after two terms and at the end (below 3.75 q < 2^52 in between); the lazy
       // one leaves the sum of at most four terms below 5.5 q, which the lazy butterflies take.
 #pragma unroll
@@ -448,6 +453,23 @@ void launch_conv(Context& c, ConvArgs& a, int cnt, int items) {
   const int L = c.log_n - 8;
   dim3 grid = ks_grid(a.groups, items), block(NTT_THREADS);
   c.begin_launch();
+  if constexpr (KIND == KIND_RESCALE) {
+    if (cnt != 1 || L < 4 || L > 8) fail(HETAL_E_PARAMS, "unsupported rescale shape");
+    switch (L) {
+#define HETAL_RESCALE_CASE(LL)                                                                                   \
+  case LL:                                                                                                     \
+    hipLaunchKernelGGL((modconv_kernel<LL, KIND, 1>), grid, block, 0, c.stream, a, c.d_twd_fwd, c.d_twd_inv,    \
+                       c.d_fpm, c.log_n);                                                                      \
+    break;
+      HETAL_RESCALE_CASE(4)
+      HETAL_RESCALE_CASE(5)
+      HETAL_RESCALE_CASE(6)
+      HETAL_RESCALE_CASE(7)
+      HETAL_RESCALE_CASE(8)
+#undef HETAL_RESCALE_CASE
+    }
+    return;
+  }
   switch (L * 10 + cnt) {
 #define HETAL_CONV_CASE(LL, C)                                                                                  \
   case LL * 10 + C:                                                                                           \
@@ -622,6 +644,66 @@ void key_switch(Context& c, const KsJob& job) {
   c.counters[5] += m;
   c.ks_items[level] += m;
   c.ks_key_reads[level] += shared ? 1 : m;
+}
+
+// A rescale (Sec. 2.2) of `batch` ciphertexts at `level`: out = (in - [in_level]_centred) q_level^-1 over
+// q_0 .. q_{level-1}, in three launches -- ModDown's pipeline with the single source prime q_level: the inverse
+// NTT's contiguous pass over the two top rows; one conversion launch (the inverse strided pass, the centred lift
+// to every q_i, the forward strided pass); the forward contiguous pass with the combine epilogue.
+void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
+  const size_t n = c.n;
+  const int colgroups = std::max(1, c.n / 4096);
+  for (int first = 0; first < batch; first += MAX_BATCH) {
+    const int m = std::min(MAX_BATCH, batch - first);
+    const u64* in_m = in + (size_t)first * in_stride;
+    u64* out_m = out + (size_t)first * out_stride;
+    Tmp top(c.pool, (size_t)m * 2 * n);
+    NttSrc src;
+    src.p = in_m;
+    src.batch_stride = in_stride;
+    src.row_mul = level + 1;  // top row of poly p: p (level + 1) + level
+    src.row_add = level;
+    ntt_inverse_first_pass(c, top, 2 * n, m, c.rows(ROWS_TOP, level), src);
+    const size_t conv_words = 2 * (size_t)level * n;
+    Tmp conv(c.pool, (size_t)m * conv_words);
+    RowsRef out_rows = c.rows(ROWS_CT, level - 1);
+    {
+      ConvArgs a{};
+      a.src = top.p;
+      a.src_stride = 2 * n;
+      a.dst = conv.p;
+      a.dst_stride = conv_words;
+      a.targets = out_rows.d;
+      for (int p = 0; p < 2; ++p) {
+        a.first[p] = p * level;
+        a.count[p] = level;
+        a.nsrc[p] = 1;
+        a.src_row0[p] = p;
+      }
+      a.scale = device_field<NttScale>(c.d_rescale + level, offsetof(RescaleTab, top));
+      a.src_prime = level;
+      a.num_q = c.num_q;
+      a.tpt = c.tune.tpt_moddown > 0 ? std::min(c.tune.tpt_moddown, level) : targets_per_task(c, level, 2, m);
+      a.tasks_per_group = (level + a.tpt - 1) / a.tpt;
+      a.colgroups = colgroups;
+      a.groups = 2 * a.tasks_per_group * colgroups;
+      a.batch = m;
+      launch_conv<KIND_RESCALE>(c, a, 1, m);
+      // reads the two top rows, writes 2 level rows
+      c.end_launch(KC_RESCALE, 8.0 * n * m * (2.0 + 2.0 * level));
+    }
+    NttEpilogue epi;
+    epi.a = in_m;
+    epi.a_stride = in_stride;
+    epi.a_poly_rows = level + 1;
+    epi.l = level;
+    epi.cst = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv));
+    epi.out = out_m;
+    epi.out_stride = out_stride;
+    for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = epi.ginv[i] = 1;
+    ntt_forward_last_pass(c, conv, conv_words, m, out_rows, epi);
+  }
+  c.counters[4] += batch;
 }
 
 }  // namespace hetal

@@ -1,4 +1,4 @@
-// RNS kernels for gfx950: elementwise operations, encryption and key generation, and the rescale schedule.
+// RNS kernels for gfx950: elementwise operations, encryption and key generation.
 // (The key switch lives in keyswitch.hip.)
 //
 // The kernels stream limbs through HBM once; each thread handles one
@@ -12,26 +12,6 @@ namespace {
 constexpr int TPB = 256;
 
 inline dim3 grid_for(const Context& c, int y, int z) { return dim3((unsigned)(c.n / TPB), (unsigned)y, (unsigned)z); }
-
-// ---------------------------------------------------------------- rescale
-// top[p][k] = coefficient-form limb `level` of poly p; spread[p][i][k] = [top]_centred mod q_i.
-__global__ void __launch_bounds__(TPB) rescale_spread_kernel(const u64* __restrict__ top, size_t top_stride,
-                                                             u64* __restrict__ spread, size_t spread_stride,
-                                                             const ModInfo* __restrict__ mods, int log_n, int level) {
-  const int n = 1 << log_n;
-  const int k = blockIdx.x * TPB + threadIdx.x;
-  const int poly = blockIdx.y;
-  const u64 qt = mods[level].q;
-  const u64 x = top[blockIdx.z * top_stride + (size_t)poly * n + k];
-  const bool negative = x > (qt >> 1);
-  const u64 mag = negative ? qt - x : x;
-  u64* __restrict__ o = spread + blockIdx.z * spread_stride + (size_t)poly * level * n;
-  for (int i = 0; i < level; ++i) {
-    const ModInfo m = mods[i];
-    const u64 r = reduce64(mag, m);
-    o[(size_t)i * n + k] = negative ? neg_mod(r, m.q) : r;
-  }
-}
 
 // ---------------------------------------------------------------- elementwise
 __global__ void __launch_bounds__(TPB) add_kernel(const u64* __restrict__ a, const u64* __restrict__ b,
@@ -205,40 +185,6 @@ void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int lev
   hipLaunchKernelGGL(tensor_kernel, grid_for(c, level + 1, 1), dim3(TPB), 0, c.stream, a, b, d01, d2, c.d_mod, c.log_n,
                      level);
   c.end_launch(KC_ELEMWISE, 8.0 * c.n * (level + 1) * 7);
-}
-
-void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
-  const size_t n = c.n;
-  // groups of at most MAX_BATCH items (the NTT epilogue's per-launch limit)
-  for (int first = 0; first < batch; first += MAX_BATCH) {
-    const int m = std::min(MAX_BATCH, batch - first);
-    const u64* in_m = in + (size_t)first * in_stride;
-    u64* out_m = out + (size_t)first * out_stride;
-    Tmp top(c.pool, (size_t)m * 2 * n);
-    NttSrc src;
-    src.p = in_m;
-    src.batch_stride = in_stride;
-    src.row_mul = level + 1;  // top row of poly p: p (level + 1) + level
-    src.row_add = level;
-    ntt_inverse(c, top, 2 * n, m, c.rows(ROWS_TOP, level), src);
-    Tmp spread(c.pool, (size_t)m * 2 * level * n);
-    c.begin_launch();
-    hipLaunchKernelGGL(rescale_spread_kernel, grid_for(c, 2, m), dim3(TPB), 0, c.stream, top.p, 2 * n, spread.p,
-                       2 * (size_t)level * n, c.d_mod, c.log_n, level);
-    c.end_launch(KC_RESCALE, 8.0 * n * m * (2.0 + 2.0 * level));
-    // out = (in - spread) q_level^-1, as the epilogue of the spread rows' NTT
-    NttEpilogue epi;
-    epi.a = in_m;
-    epi.a_stride = in_stride;
-    epi.a_poly_rows = level + 1;
-    epi.l = level;
-    epi.cst = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv));
-    epi.out = out_m;
-    epi.out_stride = out_stride;
-    for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = 1;
-    ntt_forward(c, spread, 2 * (size_t)level * n, m, c.rows(ROWS_CT, level - 1), NttSrc{}, &epi);
-  }
-  c.counters[4] += batch;
 }
 
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
