@@ -1262,7 +1262,19 @@ int hetal_enc_matmul_batch_graph(hetal_ctx* ctx, const hetal_keys* keys, const h
     need(ctx->c.stream != nullptr, HETAL_E_INVALID_ARG, "graph capture needs the context on a created stream");
     need(!ctx->c.timing, HETAL_E_INVALID_ARG, "per-kernel timing is on");
     // two eager runs: the first encodes the masks (each keeps a pool buffer), the second leaves the pools
-    // holding the buffers of every size the recorded run asks for (no allocation is allowed while recording)
+    // holding the buffers of every size the recorded run asks for (no allocation is allowed while recording);
+    // the pools reuse exact size classes until the recording ends, so that the recorded run finds the buffers
+    // the second run used
+    if (ctx->two_streams) side_context(ctx);
+    struct ExactFit {
+      hetal_ctx* ctx;
+      void set(bool on) {
+        ctx->c.pool.exact_fit = on;
+        if (ctx->side) ctx->side->pool.exact_fit = on;
+      }
+      ~ExactFit() { set(false); }
+    } exact{ctx};
+    exact.set(true);
     matmul_batch(ctx, keys, reqs, count, outs);
     matmul_batch(ctx, keys, reqs, count, outs);
     HCHECK(hipStreamSynchronize(ctx->c.stream));

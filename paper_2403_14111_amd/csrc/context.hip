@@ -110,8 +110,8 @@ void Pool::arena_end() {
 }
 
 // Buffers come in size classes (a multiple of an eighth of the size's power of two), and a request takes the
-// smallest free buffer of at least its class and at most twice it: the varied sizes of chunked work reuse each
-// other's buffers instead of piling up in the free list.
+// smallest free buffer of at least its class and at most twice it (only its own class with exact_fit): the varied
+// sizes of chunked work reuse each other's buffers instead of piling up in the free list.
 static size_t size_class(size_t words) {
   size_t top = 1;
   while (top * 2 <= words) top *= 2;
@@ -131,8 +131,8 @@ u64* Pool::get(size_t words) {
     return p;
   }
   words = size_class(words);
-  auto it = free_.lower_bound(words);
-  if (it != free_.end() && it->first <= 2 * words) {
+  auto it = exact_fit ? free_.find(words) : free_.lower_bound(words);
+  if (it != free_.end() && (exact_fit || it->first <= 2 * words)) {
     u64* p = it->second;
     free_.erase(it);
     return p;

@@ -129,6 +129,9 @@ class Pool {
   ~Pool();
   size_t bytes_held() const { return held_; }
   bool recording = false;  // while work is recorded into a graph: no allocation (an error instead)
+  // Reuse only buffers of the request's exact size class: the same sequence of requests then finds the same
+  // buffers again, so a run that allocated nothing is followed by runs that allocate nothing (graph recording).
+  bool exact_fit = false;
   void arena_begin(u64* base, size_t words);
   void arena_end();
   static size_t arena_round(size_t words) { return (words + 31) / 32 * 32; }  // 256-byte granules
