@@ -336,7 +336,6 @@ void context_init(Context& c, const hetal_params& p, hipStream_t stream) {
       resc[lv].inv[i] = invm(c.primes[lv] % qi, qi);
       resc[lv].inv_sh[i] = shoup(resc[lv].inv[i], qi);
     }
-    resc[lv].top = scaled(lv, 1);
   }
   // 5^k mod 2N
   std::vector<u32> pow5(c.slots);

@@ -70,7 +70,6 @@ struct FpMod {
 struct RescaleTab {
   u64 inv[MAX_PRIMES];  // q_level^-1 mod q_i
   u64 inv_sh[MAX_PRIMES];
-  NttScale top;         // the plain N^-1 scaling of the inverse transform's last stage, modulo q_level
 };
 
 // Per prime: N^-1, and psi^-brev(1) N^-1 (the last inverse butterfly with N^-1 merged);
@@ -317,6 +316,8 @@ struct NttEpilogue {
   size_t add1_stride = 0;
   const u64* addx = nullptr;  // [2][l][N] per item
   size_t addx_stride = 0;
+  int a_mul = 0;              // a is first multiplied by a_k[prime] (a residue of a constant, per prime)
+  u64 a_k[MAX_PRIMES];
   u32 g[MAX_BATCH];           // per item: the Galois element (1: no permutation)
   u32 ginv[MAX_BATCH];        // and its inverse modulo 2N
 };
@@ -384,7 +385,11 @@ void k_mul_i(Context& c, const u64* a, u64* out, int rows, int period);
 void k_galois(Context& c, const u64* a, u64* out, int rows, int period, u32 g);
 void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int level);
 // Rescale of `batch` ciphertexts (keyswitch.hip: ModDown's three-launch pipeline from the single prime q_level).
-void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride);
+// kconst (host, level + 1 residues, or null): rescale the ciphertexts times the constant with these residues
+// instead, in the same three launches.  in_poly_rows (0: level + 1): rows between the input's two polynomials,
+// more for an input at a higher level, whose first level + 1 limbs are used (a mod-drop on the fly).
+void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
+               const u64* kconst = nullptr, int in_poly_rows = 0);
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
                      size_t out_stride);
 void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level);

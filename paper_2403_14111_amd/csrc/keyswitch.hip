@@ -60,6 +60,7 @@ struct ConvArgs {
                                // RESCALE: p)
   const NttScale* scale;   // per source row (MODUP: indexed by limb; MODDOWN: by p K + k; RESCALE: one)
   int src_prime;           // RESCALE: the source prime's index (the level)
+  NttScale scale_v;        // RESCALE: the scaling of the inverse transform's last stage (by value)
   const ModUpTab* modup;   // MODUP: the level's digit tables
   const ModDownTab* moddown;
   int num_q;
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
     if (i >= nsrc) continue;  // a short last digit: zero terms (its constants beyond the length are zero too)
     const int row = a.src_row0[sg] + i;
     const int prime = KIND == KIND_MODUP ? row : KIND == KIND_MODDOWN ? a.num_q + i : a.src_prime;
-    const NttScale sc = a.scale[KIND == KIND_MODUP ? row : KIND == KIND_MODDOWN ? sg * CNT + i : 0];
+    const NttScale sc = KIND == KIND_RESCALE ? a.scale_v : a.scale[KIND == KIND_MODUP ? row : sg * CNT + i];
     const FpMod fm = fpm[prime];
     const double q = fm.q, qi = fm.qinv;
     const double* __restrict__ w = tw_inv + (size_t)prime * n;
@@ -647,11 +648,23 @@ void key_switch(Context& c, const KsJob& job) {
 }
 
 // A rescale (Sec. 2.2) of `batch` ciphertexts at `level`: out = (in - [in_level]_centred) q_level^-1 over
-// q_0 .. q_{level-1}, in three launches -- ModDown's pipeline with the single source prime q_level: the inverse
+// q_0 .. q_{level-1} (with kconst: the same of in times the constant K, K in = [K_i in_i]_i; an input at a higher
+// level is taken at `level`), in three launches -- ModDown's pipeline with the single source prime q_level: the inverse
 // NTT's contiguous pass over the two top rows; one conversion launch (the inverse strided pass, the centred lift
 // to every q_i, the forward strided pass); the forward contiguous pass with the combine epilogue.
-void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride) {
+void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
+               const u64* kconst, int in_poly_rows) {
   const size_t n = c.n;
+  const int prow = in_poly_rows > 0 ? in_poly_rows : level + 1;
+  // the top row's inverse transform ends with N^-1 (times the constant's residue mod q_level)
+  NttScale top_scale;
+  {
+    const u64 qt = c.primes[level];
+    const u64 kt = kconst ? kconst[level] : 1;
+    top_scale.s0 = (u64)((unsigned __int128)c.h_pc[level].ninv * kt % qt);
+    top_scale.s1 = (u64)((unsigned __int128)c.h_pc[level].w1ninv * kt % qt);
+    top_scale.s0_sh = top_scale.s1_sh = 0;  // the FP64 passes use no Shoup companions
+  }
   const int colgroups = std::max(1, c.n / 4096);
   for (int first = 0; first < batch; first += MAX_BATCH) {
     const int m = std::min(MAX_BATCH, batch - first);
@@ -661,7 +674,7 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
     NttSrc src;
     src.p = in_m;
     src.batch_stride = in_stride;
-    src.row_mul = level + 1;  // top row of poly p: p (level + 1) + level
+    src.row_mul = prow;  // top row of poly p: p prow + level
     src.row_add = level;
     ntt_inverse_first_pass(c, top, 2 * n, m, c.rows(ROWS_TOP, level), src);
     const size_t conv_words = 2 * (size_t)level * n;
@@ -680,7 +693,7 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
         a.nsrc[p] = 1;
         a.src_row0[p] = p;
       }
-      a.scale = device_field<NttScale>(c.d_rescale + level, offsetof(RescaleTab, top));
+      a.scale_v = top_scale;
       a.src_prime = level;
       a.num_q = c.num_q;
       a.tpt = c.tune.tpt_moddown > 0 ? std::min(c.tune.tpt_moddown, level) : targets_per_task(c, level, 2, m);
@@ -695,11 +708,15 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
     NttEpilogue epi;
     epi.a = in_m;
     epi.a_stride = in_stride;
-    epi.a_poly_rows = level + 1;
+    epi.a_poly_rows = prow;
     epi.l = level;
     epi.cst = device_field<u64>(c.d_rescale + level, offsetof(RescaleTab, inv));
     epi.out = out_m;
     epi.out_stride = out_stride;
+    if (kconst) {
+      epi.a_mul = 1;
+      for (int i = 0; i < level; ++i) epi.a_k[i] = kconst[i];
+    }
     for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = epi.ginv[i] = 1;
     ntt_forward_last_pass(c, conv, conv_words, m, out_rows, epi);
   }

@@ -171,8 +171,8 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       for (int u = 0; u < NTT_R; ++u) x[u] = ffix(x[u], q);
     }
     if (CONTIG && EPI) {
-      // (a - x) c + addends: a - x in [-q, q], its product in (-0.75q, 1.75q), plus two residues: below
-      // 3.75q < 2^52 before the reduction
+      // (a - x) c + addends: a - x in [-q, q] (with a_mul in (-1.75 q, 1.75 q)), its product in (-0.75q, 1.75q),
+      // plus two residues: below 3.75q < 2^52 before the reduction
       lds_exchange<true, true>(x, ls, block, spread);
       const int p = rj.x >= epi.l ? 1 : 0;
       const int i = rj.y;
@@ -188,7 +188,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 k = sp_off + sp_step * u;
-        double v = fmul((epi.a_dbl ? mid_ld(ea[k]) : u2d(ea[k])) - x[u], cst, q, qi);
+        double av = epi.a_dbl ? mid_ld(ea[k]) : u2d(ea[k]);
+        if (epi.a_mul) av = fmul(av, u2d(epi.a_k[i]), q, qi);  // in (-0.75 q, 1.75 q)
+        double v = fmul(av - x[u], cst, q, qi);
         if (own_before) v = v + u2d(own[k]);
         x[u] = v;
       }

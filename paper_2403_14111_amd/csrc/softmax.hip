@@ -144,6 +144,16 @@ Batch b_mul_const(Context& c, BView a, double value, double sigma) {
   return o;
 }
 
+Batch b_mul_const_rescale(Context& c, BView a, int level, double value, double sigma) {
+  if (level < 1 || level > a.level) fail(HETAL_E_LEVEL, "constant product and rescale: level out of range");
+  const i64 K = round_const(value * sigma);
+  const LimbConsts kc = limb_consts(c, K, level);
+  Batch o(c, level - 1, a.count);
+  k_rescale(c, a.d, o.d, level, a.count, a.stride, c.ct_words(level - 1), kc.k, a.level + 1);
+  o.scale = a.scale * sigma / (double)c.primes[level];
+  return o;
+}
+
 Batch b_add_const(Context& c, BView a, double value) {
   const i64 K = round_const(value * a.scale);
   Batch o(c, a.level, a.count);
@@ -273,7 +283,7 @@ struct Steps {
   Val cconst(Val x, double v) {
     x = need(std::move(x), 1);
     const double q = (double)c.primes[x.level()];
-    return rescale(Val(b_mul_const(c, x.v, v, q)));
+    return Val(b_mul_const_rescale(c, x.v, x.level(), v, q));
   }
 
   Val mulint(const Val& x, i64 kk) { return Val(b_mul_const(c, x.v, (double)kk, 1.0)); }
@@ -358,7 +368,7 @@ struct Steps {
       b = need(std::move(b), 1);
       const double q = (double)c.primes[b.level()];
       const double sigma = sa * q / sb;
-      b = rescale(Val(b_mul_const(c, b.v, 1.0, sigma)));
+      b = Val(b_mul_const_rescale(c, b.v, b.level(), 1.0, sigma));
     }
     const int lv = std::min(a.level(), b.level());
     a = drop(std::move(a), lv);
@@ -415,9 +425,8 @@ struct Steps {
     Val acc;
     bool first = true;
     for (int kk : ks) {
-      Val t = drop(Val(pw[kk].v), lt + 1);
-      const double sigma = target * q / t.scale();
-      t = rescale(Val(b_mul_const(c, t.v, coeffs[kk], sigma)));
+      const double sigma = target * q / pw[kk].scale();
+      Val t(b_mul_const_rescale(c, pw[kk].v, lt + 1, coeffs[kk], sigma));
       if (first) {
         acc = std::move(t);
         first = false;
