@@ -388,8 +388,9 @@ void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int lev
 // kconst (host, level + 1 residues, or null): rescale the ciphertexts times the constant with these residues
 // instead, in the same three launches.  in_poly_rows (0: level + 1): rows between the input's two polynomials,
 // more for an input at a higher level, whose first level + 1 limbs are used (a mod-drop on the fly).
+// addx (or null): a ciphertext at level - 1 per item, addx_stride words apart, added to each result.
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
-               const u64* kconst = nullptr, int in_poly_rows = 0);
+               const u64* kconst = nullptr, int in_poly_rows = 0, const u64* addx = nullptr, size_t addx_stride = 0);
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
                      size_t out_stride);
 void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level);

@@ -649,11 +649,11 @@ void key_switch(Context& c, const KsJob& job) {
 
 // A rescale (Sec. 2.2) of `batch` ciphertexts at `level`: out = (in - [in_level]_centred) q_level^-1 over
 // q_0 .. q_{level-1} (with kconst: the same of in times the constant K, K in = [K_i in_i]_i; an input at a higher
-// level is taken at `level`), in three launches -- ModDown's pipeline with the single source prime q_level: the inverse
+// level is taken at `level`; with addx, plus that addend), in three launches -- ModDown's pipeline with the single source prime q_level: the inverse
 // NTT's contiguous pass over the two top rows; one conversion launch (the inverse strided pass, the centred lift
 // to every q_i, the forward strided pass); the forward contiguous pass with the combine epilogue.
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
-               const u64* kconst, int in_poly_rows) {
+               const u64* kconst, int in_poly_rows, const u64* addx, size_t addx_stride) {
   const size_t n = c.n;
   const int prow = in_poly_rows > 0 ? in_poly_rows : level + 1;
   // the top row's inverse transform ends with N^-1 (times the constant's residue mod q_level)
@@ -716,6 +716,10 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
     if (kconst) {
       epi.a_mul = 1;
       for (int i = 0; i < level; ++i) epi.a_k[i] = kconst[i];
+    }
+    if (addx) {
+      epi.addx = addx + (size_t)first * addx_stride;
+      epi.addx_stride = addx_stride;
     }
     for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = epi.ginv[i] = 1;
     ntt_forward_last_pass(c, conv, conv_words, m, out_rows, epi);

@@ -144,13 +144,22 @@ Batch b_mul_const(Context& c, BView a, double value, double sigma) {
   return o;
 }
 
-Batch b_mul_const_rescale(Context& c, BView a, int level, double value, double sigma) {
+Batch b_mul_const_rescale(Context& c, BView a, int level, double value, double sigma, const BView* addend) {
   if (level < 1 || level > a.level) fail(HETAL_E_LEVEL, "constant product and rescale: level out of range");
   const i64 K = round_const(value * sigma);
   const LimbConsts kc = limb_consts(c, K, level);
+  double scale = a.scale * sigma / (double)c.primes[level];
+  if (addend) {  // the checks of b_add(addend, result), whose scale is the addend's
+    if (addend->level != level - 1 || addend->count != a.count)
+      fail(HETAL_E_LEVEL, "batch operands differ in level or count");
+    if (std::abs(addend->scale - scale) > 1e-9 * std::max(std::abs(addend->scale), std::abs(scale)))
+      fail(HETAL_E_SCALE, "batch operands with different scales");
+    scale = addend->scale;
+  }
   Batch o(c, level - 1, a.count);
-  k_rescale(c, a.d, o.d, level, a.count, a.stride, c.ct_words(level - 1), kc.k, a.level + 1);
-  o.scale = a.scale * sigma / (double)c.primes[level];
+  k_rescale(c, a.d, o.d, level, a.count, a.stride, c.ct_words(level - 1), kc.k, a.level + 1,
+            addend ? addend->d : nullptr, addend ? addend->stride : 0);
+  o.scale = scale;
   return o;
 }
 
@@ -426,12 +435,11 @@ struct Steps {
     bool first = true;
     for (int kk : ks) {
       const double sigma = target * q / pw[kk].scale();
-      Val t(b_mul_const_rescale(c, pw[kk].v, lt + 1, coeffs[kk], sigma));
       if (first) {
-        acc = std::move(t);
+        acc = Val(b_mul_const_rescale(c, pw[kk].v, lt + 1, coeffs[kk], sigma));
         first = false;
-      } else {
-        acc = Val(b_add(c, acc.v, t.v));
+      } else {  // the running sum is the rescale's addend
+        acc = Val(b_mul_const_rescale(c, pw[kk].v, lt + 1, coeffs[kk], sigma, &acc.v));
       }
     }
     if (coeffs[0] != 0.0) acc = add_const(acc, coeffs[0]);

@@ -13,8 +13,9 @@ i64 round_const(double v);
 // x * K for the integer K = round(value * sigma) (both polynomials, every limb); scale * sigma.
 Batch b_mul_const(Context& c, BView a, double value, double sigma);
 // rescale(x taken at `level` (mod-dropped) times round(value sigma)), in the rescale's three launches: the same
-// words as b_mod_drop, b_mul_const and b_rescale one after the other.
-Batch b_mul_const_rescale(Context& c, BView a, int level, double value, double sigma);
+// words as b_mod_drop, b_mul_const and b_rescale one after the other (and, with an addend, b_add(addend, that)).
+Batch b_mul_const_rescale(Context& c, BView a, int level, double value, double sigma,
+                          const BView* addend = nullptr);
 // x + value in every slot: K = round(value * scale) added to c0's constant term (every NTT-domain word).
 Batch b_add_const(Context& c, BView a, double value);
 // x + pt (c0 + pt), pt at the batch's level in the NTT domain.
