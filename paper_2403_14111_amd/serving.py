@@ -26,7 +26,7 @@ import time
 class Request:
     """One product: op "abt" (t A Bbar^T) or "atb" (t Abar^T B) on the client's matrices."""
 
-    __slots__ = ("rid", "client", "op", "a", "b", "c", "t", "arrival", "start", "done", "result", "lane")
+    __slots__ = ("rid", "client", "op", "a", "b", "c", "t", "arrival", "start", "done", "result", "lane", "error")
 
     def __init__(self, rid, client, op, a, b, c, t=1.0, arrival=0.0):
         if op not in ("abt", "atb"):
@@ -36,6 +36,7 @@ class Request:
         self.start = self.done = None
         self.result = None
         self.lane = None
+        self.error = None  # the exception of a batched call that failed (then result stays None)
 
     @property
     def latency(self):
@@ -117,6 +118,7 @@ class Server:
         self.lane_bytes = [0] * len(self.lanes)
         self.lane_cost = [0] * len(self.lanes)   # estimated device time queued on each lane and not yet finished
         self.rounds = []  # (round start, number of requests, clients, requests in flight before the round)
+        self.failed = []  # requests whose batched call failed, handed back by the next poll
 
     def add_client(self, client, keys):
         self.keys[client] = keys
@@ -144,7 +146,9 @@ class Server:
         return taken
 
     def poll(self):
-        """Finished groups (their events complete): stamp their requests and release their memory."""
+        """Finished groups (their events complete): stamp their requests and release their memory.  Requests whose
+        call failed come back at once, with .error set."""
+        failed, self.failed = self.failed, []
         done, still = [], []
         for g in self.inflight:
             if g.event.query():
@@ -152,7 +156,7 @@ class Server:
             else:
                 still.append(g)
         if not done:
-            return []
+            return failed
         self.inflight = still
         now = self.clock()
         out = []
@@ -163,7 +167,7 @@ class Server:
             for r in g.reqs:
                 r.done = now
             out += g.reqs
-        return out
+        return failed + out
 
     def launch(self, batch):
         """One round: the admitted requests grouped by client (clients in order of their first request), each group
@@ -180,8 +184,16 @@ class Server:
             cost = sum(request_cost(r) for r in reqs)
             lane = min(range(len(self.lanes)), key=lambda i: (self.lane_cost[i], i))
             ctx = self.lanes[lane]
-            outs = self.run(ctx, lambda: ctx.enc_matmul_batch(self.keys[client],
-                                                              [(r.op, r.a, r.b, r.c, r.t) for r in reqs]))
+            try:
+                outs = self.run(ctx, lambda: ctx.enc_matmul_batch(self.keys[client],
+                                                                  [(r.op, r.a, r.b, r.c, r.t) for r in reqs]))
+            except Exception as e:  # the library checks every request before any work: none of them ran
+                for r in reqs:
+                    r.error = e
+                    r.lane = lane
+                    r.done = self.clock()
+                self.failed += reqs
+                continue
             for r, o in zip(reqs, outs):
                 r.result = o
                 r.lane = lane
@@ -192,12 +204,17 @@ class Server:
         self.rounds.append((t0, len(batch), len(by_client), inflight_before))
 
     def step(self):
-        """Poll completions, then admit and launch what fits.  Returns the requests finished since the last step."""
+        """Poll completions, then admit and launch what fits.  Returns the requests finished (or failed) since the
+        last step."""
         finished = self.poll()
         batch = self.admit()
         if batch:
             self.launch(batch)
-        return finished
+        return finished + self.poll_failed()
+
+    def poll_failed(self):
+        failed, self.failed = self.failed, []
+        return failed
 
     def wait_one(self):
         """Block until the oldest group in flight is done (when there is nothing else to do)."""
@@ -279,7 +296,7 @@ def serve(server, requests, clock=time.perf_counter, sleep=time.sleep, idle=2e-4
     for r in pending:
         r.arrival += t_begin
     finished = []
-    while pending or server.queue or server.inflight:
+    while pending or server.queue or server.inflight or server.failed:
         now = clock()
         while pending and pending[0].arrival <= now:
             server.submit(pending.popleft())
@@ -297,12 +314,16 @@ def serve(server, requests, clock=time.perf_counter, sleep=time.sleep, idle=2e-4
 
 
 def latency_summary(finished, offered_rate):
+    """p50 / p99 / max latency and the served rate of the requests that succeeded; failures are counted apart."""
+    errors = sum(1 for r in finished if r.error is not None)
+    finished = [r for r in finished if r.error is None]
     lat = sorted(r.latency for r in finished)
     span = max(r.done for r in finished) - min(r.arrival for r in finished)
 
     def pct(p):
         return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
 
-    return dict(requests=len(finished), offered_per_s=offered_rate, served_per_s=round(len(finished) / span, 2),
+    return dict(requests=len(finished), errors=errors, offered_per_s=offered_rate,
+                served_per_s=round(len(finished) / span, 2),
                 latency_ms_p50=round(1e3 * pct(50), 2), latency_ms_p99=round(1e3 * pct(99), 2),
                 latency_ms_max=round(1e3 * lat[-1], 2))

@@ -213,3 +213,27 @@ def test_several_lanes_keep_to_their_own_streams():
     ls = [Lane("a", clock), Lane("b", clock)]
     serving.Server(ls, 1 << 40, clock=clock)
     assert not any(lane.two for lane in ls)
+
+
+def test_a_failing_batched_call_hands_its_requests_back_with_the_error():
+    class Boom(FakeLane):
+        def enc_matmul_batch(self, keys, reqs):
+            if keys == "kbad":
+                raise RuntimeError("E_SHAPE: bad request")
+            return super().enc_matmul_batch(keys, reqs)
+    clock = FakeClock()
+    lane = Boom("L0", clock)
+    srv = serving.Server([lane], 1 << 60, clock=clock, record=lambda ln: FakeEvent(clock, ln.busy_until),
+                         run=lambda ln, fn: fn(), margin=0)
+    srv.add_client("good", "kgood")
+    srv.add_client("bad", "kbad")
+    srv.submit(req(0, "bad"))
+    srv.submit(req(1, "good"))
+    first = srv.step()
+    assert [r.rid for r in first] == [0] and isinstance(first[0].error, RuntimeError) and first[0].result is None
+    assert srv.reserved == size(req(1, "good"))      # only the good group holds memory
+    clock.t += 1.0
+    done = srv.step()
+    assert [r.rid for r in done] == [1] and done[0].error is None and srv.reserved == 0
+    s = serving.latency_summary(first + done, 1.0)
+    assert s["requests"] == 1 and s["errors"] == 1
