@@ -85,13 +85,13 @@ def encrypt_inputs(ctx, sk, X, W, PY):
 # ---------------------------------------------------------------- profile summaries
 # rocprofv3 kernel names -> the library's timing classes (N = 2^16: every NTT pass has 256-point sub-transforms)
 PROFILE_CLASSES = [
-    ("ntt_pass_kernel<8, false, false, false>", "ntt_fwd_strided"),
+    ("ntt_pass_kernel<8, false, false, false", "ntt_fwd_strided"),
     ("modconv_kernel<8, 0,", "ks_modup"),
     ("modconv_kernel<8, 1,", "ks_moddown"),
-    ("ntt_pass_kernel<8, false, true, false>", "ntt_fwd_contig"),
-    ("ntt_pass_kernel<8, false, true, true>", "ntt_fwd_epilogue"),
-    ("ntt_pass_kernel<8, true, true, false>", "ntt_inv_contig"),
-    ("ntt_pass_kernel<8, true, false, false>", "ntt_inv_strided"),
+    ("ntt_pass_kernel<8, false, true, false", "ntt_fwd_contig"),
+    ("ntt_pass_kernel<8, false, true, true", "ntt_fwd_epilogue"),   # with or without the rescale's first pass
+    ("ntt_pass_kernel<8, true, true, false", "ntt_inv_contig"),
+    ("ntt_pass_kernel<8, true, false, false", "ntt_inv_strided"),
     ("ks_inner_kernel", "ks_inner"),
     ("modconv_kernel<8, 2,", "rescale"),
 ]

@@ -318,6 +318,13 @@ struct NttEpilogue {
   size_t addx_stride = 0;
   int a_mul = 0;              // a is first multiplied by a_k[prime] (a residue of a constant, per prime)
   u64 a_k[MAX_PRIMES];
+  // When set (a key switch followed by a rescale, no permutation): the rows of prime top_prime also go through
+  // the inverse NTT's contiguous pass after the combine, stored as doubles at top_out + item top_out_stride +
+  // p N -- the rescale's first launch, done while the rows are in registers.
+  u64* top_out = nullptr;
+  size_t top_out_stride = 0;
+  int top_prime = -1;
+  const double* tw_inv = nullptr;
   u32 g[MAX_BATCH];           // per item: the Galois element (1: no permutation)
   u32 ginv[MAX_BATCH];        // and its inverse modulo 2N
 };
@@ -366,6 +373,8 @@ struct KsJob {
   size_t add1_stride = 0;
   const u64* addx = nullptr;  // optional: a ciphertext added to the result (x + Lrot(x))
   size_t addx_stride = 0;
+  u64* top_out = nullptr;  // optional ([count][2][N] doubles): the result's top rows through the inverse
+                           // contiguous pass, for the rescale that follows (items without a permutation only)
 };
 void key_switch(Context& c, const KsJob& job);
 // Device words of the temporaries key_switch leases from the pool for a job of `count` distinct inputs at
@@ -389,8 +398,11 @@ void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int lev
 // instead, in the same three launches.  in_poly_rows (0: level + 1): rows between the input's two polynomials,
 // more for an input at a higher level, whose first level + 1 limbs are used (a mod-drop on the fly).
 // addx (or null): a ciphertext at level - 1 per item, addx_stride words apart, added to each result.
+// top_ready (or null): the two top rows of every item already through the inverse contiguous pass ([batch][2][N]
+// doubles, from a key switch's epilogue): the first launch is skipped.
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
-               const u64* kconst = nullptr, int in_poly_rows = 0, const u64* addx = nullptr, size_t addx_stride = 0);
+               const u64* kconst = nullptr, int in_poly_rows = 0, const u64* addx = nullptr, size_t addx_stride = 0,
+               const u64* top_ready = nullptr);
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
                      size_t out_stride);
 void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level);

@@ -31,6 +31,7 @@
 // 256 words in the order the inner product's threads own them (key_slot): the 16 threads of a sub-transform
 // then read 128 contiguous bytes per load.
 #include <algorithm>
+#include <memory>
 #include <type_traits>
 
 #include "ntt_device.hpp"
@@ -638,6 +639,13 @@ void key_switch(Context& c, const KsJob& job) {
     const u32 g = i < m ? job.item[i].g : 1;
     epi.g[i] = g;
     epi.ginv[i] = galois_inverse(g, two_n);
+    if (job.top_out && g != 1) fail(HETAL_E_INVALID_ARG, "the rescale's first pass needs items without a permutation");
+  }
+  if (job.top_out) {
+    epi.top_out = job.top_out;
+    epi.top_out_stride = 2 * n;
+    epi.top_prime = level;
+    epi.tw_inv = c.d_twd_inv;
   }
   ntt_forward_last_pass(c, conv, conv_words, m, ct_rows, epi);
   // limb transforms: c1 and the ModUp rows, the special rows and the ModDown rows
@@ -649,11 +657,12 @@ void key_switch(Context& c, const KsJob& job) {
 
 // A rescale (Sec. 2.2) of `batch` ciphertexts at `level`: out = (in - [in_level]_centred) q_level^-1 over
 // q_0 .. q_{level-1} (with kconst: the same of in times the constant K, K in = [K_i in_i]_i; an input at a higher
-// level is taken at `level`; with addx, plus that addend), in three launches -- ModDown's pipeline with the single source prime q_level: the inverse
+// level is taken at `level`; with addx, plus that addend), in three launches (two when a key switch's epilogue
+// has run the first) -- ModDown's pipeline with the single source prime q_level: the inverse
 // NTT's contiguous pass over the two top rows; one conversion launch (the inverse strided pass, the centred lift
 // to every q_i, the forward strided pass); the forward contiguous pass with the combine epilogue.
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
-               const u64* kconst, int in_poly_rows, const u64* addx, size_t addx_stride) {
+               const u64* kconst, int in_poly_rows, const u64* addx, size_t addx_stride, const u64* top_ready) {
   const size_t n = c.n;
   const int prow = in_poly_rows > 0 ? in_poly_rows : level + 1;
   // the top row's inverse transform ends with N^-1 (times the constant's residue mod q_level)
@@ -670,19 +679,22 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
     const int m = std::min(MAX_BATCH, batch - first);
     const u64* in_m = in + (size_t)first * in_stride;
     u64* out_m = out + (size_t)first * out_stride;
-    Tmp top(c.pool, (size_t)m * 2 * n);
-    NttSrc src;
-    src.p = in_m;
-    src.batch_stride = in_stride;
-    src.row_mul = prow;  // top row of poly p: p prow + level
-    src.row_add = level;
-    ntt_inverse_first_pass(c, top, 2 * n, m, c.rows(ROWS_TOP, level), src);
+    std::unique_ptr<Tmp> top;
+    if (!top_ready) {
+      top.reset(new Tmp(c.pool, (size_t)m * 2 * n));
+      NttSrc src;
+      src.p = in_m;
+      src.batch_stride = in_stride;
+      src.row_mul = prow;  // top row of poly p: p prow + level
+      src.row_add = level;
+      ntt_inverse_first_pass(c, top->p, 2 * n, m, c.rows(ROWS_TOP, level), src);
+    }
     const size_t conv_words = 2 * (size_t)level * n;
     Tmp conv(c.pool, (size_t)m * conv_words);
     RowsRef out_rows = c.rows(ROWS_CT, level - 1);
     {
       ConvArgs a{};
-      a.src = top.p;
+      a.src = top_ready ? top_ready + (size_t)first * 2 * n : top->p;
       a.src_stride = 2 * n;
       a.dst = conv.p;
       a.dst_stride = conv_words;

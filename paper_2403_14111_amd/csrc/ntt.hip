@@ -67,9 +67,10 @@ struct PassArgs {
 // v = j + T u ("spread"), in stages 4..L-1 element v = 16 j + u ("block").  The twiddle of stage l
 // for element v is psi_rev[2^(s0 + l) + (c 2^l) + (v >> (L - l))] (c = 0 in the strided pass, where
 // in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
-// EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.
+// EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.  TOP (with
+// EPI): the rows of NttEpilogue::top_prime then also run the inverse contiguous pass (a rescale's first launch).
 // (The key switch's strided passes, which compute their input by a basis conversion, are in keyswitch.hip.)
-template <int L, bool INV, bool CONTIG, bool EPI>
+template <int L, bool INV, bool CONTIG, bool EPI, bool TOP = false>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const double* __restrict__ tw,
                                                               const FpMod* __restrict__ fpm,
@@ -210,7 +211,49 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         double v = x[u];
         if (own && !own_before) v = v + u2d(own[k]);
         if (both) v = v + u2d(both[k]);
-        eo[k] = d2u(ffix(fred(v, q, qi), q));
+        x[u] = ffix(fred(v, q, qi), q);
+        eo[k] = d2u(x[u]);
+      }
+      if (TOP && i == epi.top_prime) {
+        // the inverse transform's contiguous pass on the result, as ntt_inverse_first_pass would run it on the
+        // stored row (the host asks for this only without a permutation, so the chunk is the workgroup's own)
+        const double* __restrict__ wi = epi.tw_inv + (size_t)i * n;
+        auto twi_spread = [&](int l, int u) { return wi[(1 << (s0 + l)) + (sub << l) + (u >> (4 - l))]; };
+        auto twi_block = [&](int l, int u) { return wi[(1 << (s0 + l)) + (sub << l) + (((u >> (8 - l)) << 4) | j)]; };
+        auto inverse = [&](auto lazy) {
+          constexpr bool LZ = decltype(lazy)::value;
+          lds_exchange<true, true>(x, ls, spread, block);
+#pragma unroll
+          for (int l = 7; l >= 4; --l) {
+            const int half = 1 << (7 - l);
+#pragma unroll
+            for (int u = 0; u < NTT_R; ++u)
+              if (!(u & half)) inv_bfly<LZ>(x[u], x[u + half], twi_block(l, u), q, qi);
+          }
+          if (LZ) {
+#pragma unroll
+            for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
+          }
+          lds_exchange<true, true>(x, ls, block, spread);
+#pragma unroll
+          for (int l = 3; l >= 0; --l) {
+            const int hu = 8 >> l;
+#pragma unroll
+            for (int u = 0; u < NTT_R; ++u)
+              if (!(u & hu)) inv_bfly<LZ>(x[u], x[u + hu], twi_spread(l, u), q, qi);
+          }
+          if (LZ) {
+#pragma unroll
+            for (int u = 0; u < NTT_R; ++u) x[u] = fred(x[u], q, qi);
+          }
+        };
+        if (q < LAZY_MODULUS)
+          inverse(std::true_type{});
+        else
+          inverse(std::false_type{});
+        u64* __restrict__ to = epi.top_out + item * epi.top_out_stride + (size_t)p * n;
+#pragma unroll
+        for (int u = 0; u < NTT_R; ++u) (to + sp_step * u)[sp_off] = mid_st(x[u]);
       }
     } else if (CONTIG) {
       lds_exchange<true, true>(x, ls, block, spread);
@@ -315,7 +358,10 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   if (epi && batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "NTT epilogue batch");
   const NttEpilogue no_epi{};
   c.begin_launch();
-  if (epi) {
+  if (epi && epi->top_out) {
+    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, true>), grid, block, 0, c.stream, pa, rows.d, tw,
+                       c.d_fpm, c.d_pc, c.log_n, s0, *epi);
+  } else if (epi) {
     hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_fpm,
                        c.d_pc, c.log_n, s0, *epi);
   } else {

@@ -173,6 +173,8 @@ Batch b_rotate_hoisted(Context& c, const KeySet& k, CtView a, const std::vector<
 Batch b_conj(Context& c, const KeySet& k, BView a);
 // Mult (tensor + relinearisation) of the pairs (a[i], b[i]), all at one level.
 Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
+// b_hmult then b_rescale, with the rescale's first launch run by the key switch's epilogue: the same words.
+Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
 // CMult of item i by mask masks[i] (or masks[0] for all), each encoded at the batch level with scale q_level.
 Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks);
 // out[g] = sum over t < per of a[g * per + t], per = a.count / groups.

@@ -329,8 +329,7 @@ struct Steps {
       va.push_back(av.item(i));
       vb.push_back(bv.item(i));
     }
-    Batch p = b_hmult(c, k, va, vb);
-    return Val(b_rescale(c, p.v()));
+    return Val(b_hmult_rescale(c, k, va, vb));
   }
 
   // Independent products as one lockstep Mult + rescale: every item goes through the operations it would get
@@ -356,8 +355,7 @@ struct Steps {
         vb.push_back(b.item(i));
       }
     }
-    Batch p = b_hmult(c, k, va, vb);
-    auto r = std::make_shared<Batch>(b_rescale(c, p.v()));
+    auto r = std::make_shared<Batch>(b_hmult_rescale(c, k, va, vb));
     const size_t w = c.ct_words(lv - 1);
     size_t off = 0;
     out.clear();
