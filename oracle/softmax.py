@@ -51,9 +51,13 @@ Readings (the paper is silent or garbled here; each is also listed with the desi
     constants of a following training step.  Sums of ciphertexts whose scales differ bring the second operand to
     the first's scale with a constant 1 encoded at the matching scale (one level).
 
-Parity status: the plain form is pinned by the closed form of f, the DEP lemmas, the
-theorem's bound and Table softmaxerr (tests/test_oracle_softmax.py); the coefficients of p and
-the AInv parameters are not printed in the paper, so beyond that table they are parity unpinned.
+Parity status: pinned.  The plain form is pinned by the closed form of f, the DEP lemmas, the
+theorem's bound and Table softmaxerr (tests/test_oracle_softmax.py).  The coefficients of p and
+the AInv parameters are not printed in the paper: p is pinned to its closed form (the truncated
+Legendre series of e^t, coefficients (2n + 1) i_n(1) from the modified spherical Bessel functions)
+and AInv to the closed form of Goldschmidt's iteration, (1 - (1 - x / R)^(2^17)) / x; the
+parameter choices themselves (degree 12, B = 8, R = 100, 16 steps) are readings, checked only
+through Table softmaxerr.
 """
 import math
 

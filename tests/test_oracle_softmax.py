@@ -111,6 +111,37 @@ def test_aexp_and_ainv_accuracy():
 
 
 
+def test_aexp_polynomial_equals_the_closed_form_legendre_series():
+    """The L^2 projection of e^t onto degree <= 12 on [-1, 1] is the truncated Legendre series, whose coefficients have
+    a closed form: int_{-1}^{1} e^t P_n(t) dt = 2 i_n(1), i_n the modified spherical Bessel function of the first kind,
+    so p = sum_n (2n + 1) i_n(1) P_n.  Computed here with scipy's Bessel function, independently of the oracle's
+    quadrature, and compared monomial by monomial after the oracle's 1/B scaling."""
+    from scipy.special import spherical_in
+    prm = sm.SoftmaxParams()
+    leg = [(2 * n + 1) * spherical_in(n, 1.0) for n in range(prm.exp_degree + 1)]
+    mono = np.polynomial.legendre.leg2poly(leg)
+    want = [float(mono[k]) / float(prm.exp_B) ** k for k in range(prm.exp_degree + 1)]
+    got = sm.exp_coeffs(prm.exp_degree, prm.exp_B)
+    scale = max(abs(v) for v in want)
+    for k in range(prm.exp_degree + 1):
+        assert abs(got[k] - want[k]) <= 1e-13 * scale, k
+    assert abs(leg[0] - np.sinh(1.0)) < 1e-15           # the mean of e^t on [-1, 1]
+
+
+def test_ainv_equals_the_closed_form_of_goldschmidts_iteration():
+    """Goldschmidt's iteration from y = x / R (a = 2 - y = 1 + b, b = 1 - y; b <- b^2, a <- a (1 + b)) keeps
+    y a_k = 1 - b_0^(2^(k+1)) exactly, so after the 16 steps AInv(x) = (1 - (1 - x / R)^(2^17)) / x.  Near 0 the
+    remainder is large and fixes the step count and the update order (one step fewer doubles b_0's exponent's
+    distance from the truth); on [1, 150] it is 1/x."""
+    prm = sm.SoftmaxParams()
+    x = np.array([1e-3, 3e-3, 1e-2, 0.05, 0.5, 1.0, 7.0, 64.0, 150.0, 199.0])
+    want = (1.0 - np.exp(2.0 ** (prm.inv_iters + 1) * np.log(np.abs(1.0 - x / prm.inv_R)))) / x  # even power
+    got = sm.ainv_plain(x, prm)
+    assert np.abs(got / want - 1.0).max() < 1e-10
+    fewer = sm.ainv_plain(x[:2], sm.SoftmaxParams(inv_iters=prm.inv_iters - 1))
+    assert np.abs(fewer / want[:2] - 1.0).min() > 0.1     # a dropped step would be caught
+
+
 def test_stored_aexp_polynomial_is_the_oracles_projection():
     """tests/golden/aexp_coeffs.json, which both sides of the GPU parity tests take as input, holds the
     oracle's L^2 projection exactly (the file is regenerated by tests/golden/make_aexp_coeffs.py)."""
