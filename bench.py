@@ -1039,6 +1039,20 @@ def main():
                             gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
                     for k, v in kt.items() if v["launches"]}
 
+    # ---- the client's side of a step with fresh inputs, outside the timed region: the three matrices uploaded from
+    # host memory, encoded and encrypted with the library's seeded sampler (PCIe included; never the `value`)
+    log("client upload + encrypt")
+    up_ms = []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.mat_encrypt_seeded(sk, X, S0, LEVEL, 2.0 ** 40, SEEDS["enc"] + 9, 0)
+        ctx.mat_encrypt_seeded(sk, W, S0, LEVEL, 2.0 ** 40, SEEDS["enc"] + 9, 100, tiling=1, c=C_PAD)
+        ctx.mat_encrypt_seeded(sk, PY, S0, LEVEL, 2.0 ** 40, SEEDS["enc"] + 9, 200, tiling=2, c=C_PAD)
+        torch.cuda.synchronize()
+        up_ms.append(1e3 * (time.perf_counter() - t0))
+    upload_ms = float(np.median(up_ms))
+
     # ---- HRot/s (single rotations at level 11)
     log("hrot")
     ct = ctx.mat_block(gx, 0)
@@ -1102,6 +1116,8 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "client_upload_encrypt_ms": round(upload_ms, 3),
+        "pcie_inclusive_matmuls_per_s": round(2.0 * 1e3 / (ms_per_step + upload_ms), 2),
         "hrot_per_s": round(hrot_s, 1),
         "hrot_batched_per_s": dict(hrot_batched, batch=HROT_BATCH, level=LEVEL),
         "step_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
