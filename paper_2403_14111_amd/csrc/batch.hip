@@ -281,40 +281,63 @@ Batch b_conj(Context& c, const KeySet& k, BView a) {
   return o;
 }
 
+// The key switch of one launch group of Mults (items first .. first + m - 1) into out.  Groups of at least
+// FUSED_TENSOR_ITEMS compute the tensor product where the key switch reads it (one launch and three limb rows per
+// item fewer); smaller ones, whose launches are latency-bound, store it first with its own kernel, which is faster
+// there.  The words are the same either way.
+constexpr int FUSED_TENSOR_ITEMS = 8;
+
+static void hmult_group(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b,
+                        int first, int m, u64* out, size_t out_stride, u64* top_out) {
+  const int level = a[first].level, l = level + 1;
+  const size_t poly = c.poly_words(level), w = c.ct_words(level);
+  KsJob job;
+  job.level = level;
+  job.count = m;
+  for (int i = 0; i < m; ++i) job.item[i] = KsItem{k.relin, 1};
+  job.out = out;
+  job.out_stride = out_stride;
+  job.top_out = top_out;
+  if (m >= FUSED_TENSOR_ITEMS) {
+    job.tensor = true;
+    for (int i = 0; i < m; ++i) {
+      job.ta[i] = a[first + i].d;
+      job.tb[i] = b[first + i].d;
+    }
+    key_switch(c, job);
+    return;
+  }
+  Tmp d01(c.pool, (size_t)m * w), d2(c.pool, (size_t)m * poly);
+  PtrArgs p;
+  for (int i = 0; i < MAX_BATCH; ++i) {
+    p.a[i] = i < m ? a[first + i].d : nullptr;
+    p.b[i] = i < m ? b[first + i].d : nullptr;
+  }
+  c.begin_launch();
+  hipLaunchKernelGGL(tensor_batch_kernel, grid3(c, l, m), dim3(TPB), 0, c.stream, p, d01.p, d2.p, c.d_mod, c.log_n,
+                     level);
+  c.end_launch(KC_ELEMWISE, 8.0 * c.n * l * 7.0 * m);
+  job.in = d2;
+  job.in_stride = poly;
+  job.add0 = d01;
+  job.add0_stride = w;
+  job.add1 = d01.p + poly;
+  job.add1_stride = w;
+  key_switch(c, job);
+}
+
 Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b) {
   if (a.size() != b.size() || a.empty()) fail(HETAL_E_INVALID_ARG, "hmult batch operand counts differ");
   if (!k.relin) fail(HETAL_E_NO_KEY, "relinearisation key missing");
-  const int level = a[0].level, count = (int)a.size(), l = level + 1;
+  const int level = a[0].level, count = (int)a.size();
   for (int i = 0; i < count; ++i)
     if (a[i].level != level || b[i].level != level) fail(HETAL_E_LEVEL, "hmult operands at different levels");
   Batch o(c, level, count);
-  const size_t poly = c.poly_words(level), w = c.ct_words(level);
+  const size_t w = c.ct_words(level);
   const int group = std::max(1, std::min(MAX_BATCH, c.tune.ks_group));
   for (int first = 0; first < count; first += group) {
     const int m = std::min(group, count - first);
-    Tmp d01(c.pool, (size_t)m * w), d2(c.pool, (size_t)m * poly);
-    PtrArgs p;
-    for (int i = 0; i < MAX_BATCH; ++i) {
-      p.a[i] = i < m ? a[first + i].d : nullptr;
-      p.b[i] = i < m ? b[first + i].d : nullptr;
-    }
-    c.begin_launch();
-    hipLaunchKernelGGL(tensor_batch_kernel, grid3(c, l, m), dim3(TPB), 0, c.stream, p, d01.p, d2.p, c.d_mod, c.log_n,
-                       level);
-    c.end_launch(KC_ELEMWISE, 8.0 * c.n * l * 7.0 * m);
-    KsJob job;
-    job.level = level;
-    job.count = m;
-    job.in = d2;
-    job.in_stride = poly;
-    for (int i = 0; i < m; ++i) job.item[i] = KsItem{k.relin, 1};
-    job.out = o.d + (size_t)first * w;
-    job.out_stride = w;
-    job.add0 = d01;
-    job.add0_stride = w;
-    job.add1 = d01.p + poly;
-    job.add1_stride = w;
-    key_switch(c, job);
+    hmult_group(c, k, a, b, first, m, o.d + (size_t)first * w, w, nullptr);
   }
   o.scale = a[0].scale * b[0].scale;
   c.counters[2] += count;
@@ -324,40 +347,17 @@ Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const s
 Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b) {
   if (a.size() != b.size() || a.empty()) fail(HETAL_E_INVALID_ARG, "hmult batch operand counts differ");
   if (!k.relin) fail(HETAL_E_NO_KEY, "relinearisation key missing");
-  const int level = a[0].level, count = (int)a.size(), l = level + 1;
+  const int level = a[0].level, count = (int)a.size();
   if (level < 1) fail(HETAL_E_LEVEL, "no level left to rescale");
   for (int i = 0; i < count; ++i)
     if (a[i].level != level || b[i].level != level) fail(HETAL_E_LEVEL, "hmult operands at different levels");
   Batch o(c, level - 1, count);
-  const size_t poly = c.poly_words(level), w = c.ct_words(level), wo = c.ct_words(level - 1);
+  const size_t w = c.ct_words(level), wo = c.ct_words(level - 1);
   const int group = std::max(1, std::min(MAX_BATCH, c.tune.ks_group));
   for (int first = 0; first < count; first += group) {
     const int m = std::min(group, count - first);
-    Tmp d01(c.pool, (size_t)m * w), d2(c.pool, (size_t)m * poly), prod(c.pool, (size_t)m * w),
-        top(c.pool, (size_t)m * 2 * c.n);
-    PtrArgs p;
-    for (int i = 0; i < MAX_BATCH; ++i) {
-      p.a[i] = i < m ? a[first + i].d : nullptr;
-      p.b[i] = i < m ? b[first + i].d : nullptr;
-    }
-    c.begin_launch();
-    hipLaunchKernelGGL(tensor_batch_kernel, grid3(c, l, m), dim3(TPB), 0, c.stream, p, d01.p, d2.p, c.d_mod, c.log_n,
-                       level);
-    c.end_launch(KC_ELEMWISE, 8.0 * c.n * l * 7.0 * m);
-    KsJob job;
-    job.level = level;
-    job.count = m;
-    job.in = d2;
-    job.in_stride = poly;
-    for (int i = 0; i < m; ++i) job.item[i] = KsItem{k.relin, 1};
-    job.out = prod;
-    job.out_stride = w;
-    job.add0 = d01;
-    job.add0_stride = w;
-    job.add1 = d01.p + poly;
-    job.add1_stride = w;
-    job.top_out = top;
-    key_switch(c, job);
+    Tmp prod(c.pool, (size_t)m * w), top(c.pool, (size_t)m * 2 * c.n);
+    hmult_group(c, k, a, b, first, m, prod, w, top);
     k_rescale(c, prod, o.d + (size_t)first * wo, level, m, w, wo, nullptr, 0, nullptr, 0, top);
   }
   o.scale = (a[0].scale * b[0].scale) / (double)c.primes[level];

@@ -325,6 +325,15 @@ struct NttEpilogue {
   size_t top_out_stride = 0;
   int top_prime = -1;
   const double* tw_inv = nullptr;
+  // When set (a Mult's key switch): the tensor product of the ciphertext pairs (ta[item], tb[item]), both at the
+  // output's level, is computed where it is read instead of being stored -- the epilogue adds a0 b0 (rows of c0)
+  // or a0 b1 + a1 b0 (rows of c1) as its addend, and the key switch's first launch (ntt_inverse_first_pass_tensor)
+  // transforms a1 b1, storing it in NTT form at t_out + item t_out_stride for the inner product's own rows.
+  int tensor = 0;
+  const u64* ta[MAX_BATCH];
+  const u64* tb[MAX_BATCH];
+  u64* t_out = nullptr;
+  size_t t_out_stride = 0;
   u32 g[MAX_BATCH];           // per item: the Galois element (1: no permutation)
   u32 ginv[MAX_BATCH];        // and its inverse modulo 2N
 };
@@ -342,6 +351,10 @@ void ntt_inverse(Context& c, u64* base, size_t batch_stride, int batch, RowsRef 
 // into its own kernels: the inverse transform's first (contiguous) pass, stored as doubles; and the forward
 // transform's last (contiguous) pass over rows the forward strided pass stored as doubles, with the epilogue.
 void ntt_inverse_first_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src);
+// The same pass on the products a1 b1 of the pairs in t (t.tensor set, rows: the l rows of c1), also storing the
+// products themselves (see NttEpilogue).
+void ntt_inverse_first_pass_tensor(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
+                                   const NttEpilogue& t);
 void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
                            const NttEpilogue& epi);
 
@@ -375,6 +388,11 @@ struct KsJob {
   size_t addx_stride = 0;
   u64* top_out = nullptr;  // optional ([count][2][N] doubles): the result's top rows through the inverse
                            // contiguous pass, for the rescale that follows (items without a permutation only)
+  // A Mult's relinearisation: the input is the tensor product of the pairs (ta[i], tb[i]) at `level`, computed
+  // on the fly (`in`, add0 and add1 unused; the result is (d0, d1) + the switched d2)
+  bool tensor = false;
+  const u64* ta[MAX_BATCH];
+  const u64* tb[MAX_BATCH];
 };
 void key_switch(Context& c, const KsJob& job);
 // Device words of the temporaries key_switch leases from the pool for a job of `count` distinct inputs at

@@ -509,7 +509,7 @@ void key_switch(Context& c, const KsJob& job) {
   const int m = job.count;
   if (m < 1 || m > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "key switch batch size");
   if (c.alpha > MAX_CONV || c.num_p > MAX_CONV || beta > 2 * MAX_CONV) fail(HETAL_E_PARAMS, "key switch shape");
-  const bool hoisted = job.in_stride == 0;
+  const bool hoisted = !job.tensor && job.in_stride == 0;
   const int m_in = hoisted ? 1 : m;
   const size_t n = c.n;
   const size_t poly = (size_t)l * n;
@@ -518,13 +518,34 @@ void key_switch(Context& c, const KsJob& job) {
   const size_t conv_words = 2 * poly;
   const int colgroups = std::max(1, c.n / 4096);
 
-  // 1. the inverse NTT's contiguous pass over the input (its strided pass runs inside launch 2)
+  // 1. the inverse NTT's contiguous pass over the input (its strided pass runs inside launch 2); for a Mult the
+  // input a1 b1 is computed here, and stored for the inner product's own rows
   Tmp coef(c.pool, m_in * poly);
   RowsRef ct_rows = c.rows(ROWS_CT, level);
-  NttSrc src;
-  src.p = job.in;
-  src.batch_stride = hoisted ? 0 : job.in_stride;
-  ntt_inverse_first_pass(c, coef, poly, m_in, RowsRef{ct_rows.d, l}, src);
+  if (job.tensor && hoisted) fail(HETAL_E_INVALID_ARG, "a Mult's key switch has one input per item");
+  std::unique_ptr<Tmp> d2;
+  const u64* in = job.in;
+  size_t in_stride = job.in_stride;
+  if (job.tensor) {
+    d2.reset(new Tmp(c.pool, (size_t)m * poly));
+    NttEpilogue t;
+    t.tensor = 1;
+    t.l = l;
+    for (int i = 0; i < MAX_BATCH; ++i) {
+      t.ta[i] = i < m ? job.ta[i] : nullptr;
+      t.tb[i] = i < m ? job.tb[i] : nullptr;
+    }
+    t.t_out = d2->p;
+    t.t_out_stride = poly;
+    ntt_inverse_first_pass_tensor(c, coef, poly, m, RowsRef{ct_rows.d, l}, t);
+    in = d2->p;
+    in_stride = poly;
+  } else {
+    NttSrc src;
+    src.p = job.in;
+    src.batch_stride = hoisted ? 0 : job.in_stride;
+    ntt_inverse_first_pass(c, coef, poly, m_in, RowsRef{ct_rows.d, l}, src);
+  }
 
   // 2. ModUp: the strided passes around the conversion, one launch
   Tmp dt(c.pool, m_in * dt_words);
@@ -566,8 +587,8 @@ void key_switch(Context& c, const KsJob& job) {
     InnerArgs a{};
     a.dt = dt.p;
     a.dt_stride = hoisted ? 0 : dt_words;
-    a.in = job.in;
-    a.in_stride = hoisted ? 0 : job.in_stride;
+    a.in = in;
+    a.in_stride = hoisted ? 0 : in_stride;
     a.acc = acc.p;
     a.acc_stride = acc_words;
     for (int i = 0; i < MAX_BATCH; ++i) a.key[i] = reinterpret_cast<const double*>(i < m ? job.item[i].key : nullptr);
@@ -634,6 +655,13 @@ void key_switch(Context& c, const KsJob& job) {
   epi.add1_stride = job.add1_stride;
   epi.addx = job.addx;
   epi.addx_stride = job.addx_stride;
+  if (job.tensor) {
+    epi.tensor = 1;
+    for (int i = 0; i < MAX_BATCH; ++i) {
+      epi.ta[i] = i < m ? job.ta[i] : nullptr;
+      epi.tb[i] = i < m ? job.tb[i] : nullptr;
+    }
+  }
   const u32 two_n = 2u * (u32)c.n;
   for (int i = 0; i < MAX_BATCH; ++i) {
     const u32 g = i < m ? job.item[i].g : 1;

@@ -67,10 +67,14 @@ struct PassArgs {
 // v = j + T u ("spread"), in stages 4..L-1 element v = 16 j + u ("block").  The twiddle of stage l
 // for element v is psi_rev[2^(s0 + l) + (c 2^l) + (v >> (L - l))] (c = 0 in the strided pass, where
 // in the spread stages it does not depend on the lane at all), stored at ntt_twiddle_slot of that.
-// EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.  TOP (with
-// EPI): the rows of NttEpilogue::top_prime then also run the inverse contiguous pass (a rescale's first launch).
+// EPI (forward contiguous pass only): the combine epilogue of NttEpilogue replaces the plain store.  X & NTT_TOP
+// (with EPI): the rows of NttEpilogue::top_prime then also run the inverse contiguous pass (a rescale's first
+// launch).  X & NTT_TENSOR: a Mult's tensor product is read where it is needed (NttEpilogue::tensor).
 // (The key switch's strided passes, which compute their input by a basis conversion, are in keyswitch.hip.)
-template <int L, bool INV, bool CONTIG, bool EPI, bool TOP = false>
+constexpr int NTT_TOP = 1;     // (with EPI) the top rows also run the inverse contiguous pass
+constexpr int NTT_TENSOR = 2;  // a Mult's tensor product computed where it is read (NttEpilogue::tensor)
+
+template <int L, bool INV, bool CONTIG, bool EPI, int X = 0>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
                                                               const double* __restrict__ tw,
                                                               const FpMod* __restrict__ fpm,
@@ -83,6 +87,9 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   constexpr bool FINAL = INV != CONTIG;
   static_assert(!CONTIG || L == 8, "the contiguous pass covers the last 8 stages");
   static_assert(!EPI || (CONTIG && !INV), "the epilogue belongs to the last forward pass");
+  constexpr bool TOP = (X & NTT_TOP) != 0;
+  constexpr bool TENSOR = (X & NTT_TENSOR) != 0;
+  static_assert(!TENSOR || CONTIG, "the tensor product is read by the contiguous passes");
   // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
   // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
   // neighbouring slices in lockstep fall on distinct banks.
@@ -205,11 +212,22 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         lds_exchange<true, true>(x, ls, dest, spread);
       }
       const u32 o_off = out_chunk + (u32)j;
+      // the tensor product's row i of c_p: a0 b0 (p = 0), a0 b1 + a1 b0 (p = 1), reduced to [0, q]
+      const u64* __restrict__ ta0 = TENSOR ? epi.ta[item] + (size_t)i * n : nullptr;
+      const u64* __restrict__ tb0 = TENSOR ? epi.tb[item] + (size_t)i * n : nullptr;
+      const u64* __restrict__ ta1 = TENSOR ? ta0 + (size_t)epi.l * n : nullptr;
+      const u64* __restrict__ tb1 = TENSOR ? tb0 + (size_t)epi.l * n : nullptr;
 #pragma unroll
       for (int u = 0; u < NTT_R; ++u) {
         const u32 k = o_off + sp_step * u;
         double v = x[u];
-        if (own && !own_before) v = v + u2d(own[k]);
+        if (TENSOR) {
+          const double d = p == 0 ? fmul(u2d(ta0[k]), u2d(tb0[k]), q, qi)
+                                  : fmul(u2d(ta0[k]), u2d(tb1[k]), q, qi) + fmul(u2d(ta1[k]), u2d(tb0[k]), q, qi);
+          v = v + fred(d, q, qi);
+        } else if (own && !own_before) {
+          v = v + u2d(own[k]);
+        }
         if (both) v = v + u2d(both[k]);
         x[u] = ffix(fred(v, q, qi), q);
         eo[k] = d2u(x[u]);
@@ -271,8 +289,22 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
       constexpr bool LZ = decltype(lazy)::value;
       asm volatile("" ::: "memory");  // as in the forward branch
       if (CONTIG) {
+        if (TENSOR) {
+          // row i of a Mult's a1 b1: computed from the pair, stored in NTT form, and transformed
+          const int i = rj.y;
+          const u64* __restrict__ a1 = epi.ta[item] + (size_t)(epi.l + i) * n;
+          const u64* __restrict__ b1 = epi.tb[item] + (size_t)(epi.l + i) * n;
+          u64* __restrict__ d2 = epi.t_out + item * epi.t_out_stride + (size_t)i * n;
 #pragma unroll
-        for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
+          for (int u = 0; u < NTT_R; ++u) {
+            const u32 k = sp_off + sp_step * u;
+            x[u] = ffix(fred(fmul(u2d(a1[k]), u2d(b1[k]), q, qi), q, qi), q);
+            d2[k] = d2u(x[u]);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
+        }
         lds_exchange<false, true>(x, ls, spread, block);
       } else if (L > 4) {
 #pragma unroll
@@ -354,16 +386,27 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   // the strided pass is the 2^L x 256 column view (s0 == 0), the contiguous one the last 8 stages
   const bool contiguous = s0 + L == c.log_n;
   if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
-  if (epi && (INV || !contiguous)) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
+  if (epi && !contiguous) fail(HETAL_E_PARAMS, "NTT epilogue outside the contiguous pass");
+  if (epi && INV && !epi->tensor) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
   if (epi && batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "NTT epilogue batch");
   const NttEpilogue no_epi{};
   c.begin_launch();
-  if (epi && epi->top_out) {
-    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, true>), grid, block, 0, c.stream, pa, rows.d, tw,
+  if (epi && INV) {
+    hipLaunchKernelGGL((ntt_pass_kernel<8, true, true, false, NTT_TENSOR>), grid, block, 0, c.stream, pa, rows.d, tw,
                        c.d_fpm, c.d_pc, c.log_n, s0, *epi);
   } else if (epi) {
-    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true>), grid, block, 0, c.stream, pa, rows.d, tw, c.d_fpm,
-                       c.d_pc, c.log_n, s0, *epi);
+    switch ((epi->top_out ? NTT_TOP : 0) | (epi->tensor ? NTT_TENSOR : 0)) {
+#define HETAL_EPI_CASE(XX)                                                                                       \
+  case XX:                                                                                                     \
+    hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, XX>), grid, block, 0, c.stream, pa, rows.d, tw,     \
+                       c.d_fpm, c.d_pc, c.log_n, s0, *epi);                                                    \
+    break;
+      HETAL_EPI_CASE(0)
+      HETAL_EPI_CASE(1)
+      HETAL_EPI_CASE(2)
+      HETAL_EPI_CASE(3)
+#undef HETAL_EPI_CASE
+    }
   } else {
     switch (L * 2 + (contiguous ? 1 : 0)) {
 #define HETAL_NTT_CASE(LL, CC)                                                                                 \
@@ -383,9 +426,14 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
     }
   }
   const double words = (double)c.n * rows.count * batch;
-  if (epi) {
-    // per word: the pass input and a read, out written; addx on every row, add0 / add1 on half of them
-    const double per_word = 24.0 + (epi->addx ? 8.0 : 0.0) + (epi->add0 ? 4.0 : 0.0) + (epi->add1 ? 4.0 : 0.0);
+  if (epi && INV) {
+    // the pair's two rows read, the product and the pass output written
+    c.end_launch(KC_NTT_INV_CONTIG, 32.0 * words);
+  } else if (epi) {
+    // per word: the pass input and a read, out written; addx on every row, add0 / add1 on half of them (the
+    // tensor product: the pair's rows, 3 of 4 on average)
+    const double per_word = 24.0 + (epi->addx ? 8.0 : 0.0) + (epi->add0 ? 4.0 : 0.0) + (epi->add1 ? 4.0 : 0.0) +
+                            (epi->tensor ? 24.0 : 0.0);
     c.end_launch(KC_NTT_FWD_EPILOGUE, per_word * words);
   } else {
     const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
@@ -408,6 +456,13 @@ void ntt_forward(Context& c, u64* base, size_t batch_stride, int batch, RowsRef 
 void ntt_inverse_first_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src) {
   if (rows.count == 0 || batch == 0) return;
   launch_pass<true>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, src);
+}
+
+void ntt_inverse_first_pass_tensor(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
+                                   const NttEpilogue& t) {
+  if (rows.count == 0 || batch == 0) return;
+  if (!t.tensor || !t.t_out) fail(HETAL_E_INVALID_ARG, "tensor pass without its pairs");
+  launch_pass<true>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, NttSrc{}, &t);
 }
 
 void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
