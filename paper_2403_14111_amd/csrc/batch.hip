@@ -39,21 +39,6 @@ __global__ void __launch_bounds__(TPB) tensor_batch_kernel(PtrArgs p, u64* __res
   d2[(size_t)item * l * n + i0] = mul_mod(a1, b1, m);
 }
 
-// out[item][p][i] = a[item][p][i] * pt_item[i].
-__global__ void __launch_bounds__(TPB) cmult_batch_kernel(const u64* __restrict__ a, size_t a_stride, PtrArgs p,
-                                                          u64* __restrict__ out, const ModInfo* __restrict__ mods,
-                                                          int log_n, int level) {
-  const int n = 1 << log_n;
-  const int l = level + 1;
-  const int k = blockIdx.x * TPB + threadIdx.x;
-  const int row = blockIdx.y;  // 0 .. 2l-1
-  const int i = row % l;
-  const int item = blockIdx.z;
-  const ModInfo m = mods[i];
-  out[(size_t)item * 2 * l * n + (size_t)row * n + k] =
-      mul_mod(a[item * a_stride + (size_t)row * n + k], p.a[item][(size_t)i * n + k], m);
-}
-
 // Segment g of a launch is items [start[g], start[g+1]) of the input (start[0] = 0 relative to the launch's
 // first item); its sum goes to item dst[g] of the output.
 constexpr int MAX_SEGMENTS = 64;
@@ -365,28 +350,19 @@ Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a,
   return o;
 }
 
-Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks) {
+Batch b_cmult_masks_rescale(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks) {
   if (masks.size() != 1 && (int)masks.size() != a.count) fail(HETAL_E_INVALID_ARG, "one mask or one per item");
-  const int l = a.level + 1;
-  Batch o(c, a.level, a.count);
-  for (int first = 0; first < a.count; first += MAX_BATCH) {
-    const int m = std::min(MAX_BATCH, a.count - first);
-    PtrArgs p;
-    for (int i = 0; i < MAX_BATCH; ++i) {
-      p.b[i] = nullptr;
-      if (i < m) {
-        const MaskSpec& s = masks.size() == 1 ? masks[0] : masks[first + i];
-        p.a[i] = mask_pt(c, mc, s.kind, s.k, s.cc, s.s0, s.s1, s.t, a.level);
-      } else {
-        p.a[i] = nullptr;
-      }
-    }
-    c.begin_launch();
-    hipLaunchKernelGGL(cmult_batch_kernel, grid3(c, 2 * l, m), dim3(TPB), 0, c.stream, a.d + (size_t)first * a.stride,
-                       a.stride, p, o.d + (size_t)first * c.ct_words(a.level), c.d_mod, c.log_n, a.level);
-    c.end_launch(KC_ELEMWISE, 8.0 * c.n * l * 5.0 * m);
+  if (a.level < 1) fail(HETAL_E_LEVEL, "no level left to rescale");
+  std::vector<const u64*> pts(a.count);
+  for (int i = 0; i < a.count; ++i) {
+    const MaskSpec& s = masks.size() == 1 ? masks[0] : masks[i];
+    pts[i] = mask_pt(c, mc, s.kind, s.k, s.cc, s.s0, s.s1, s.t, a.level);
   }
-  o.scale = a.scale * (double)c.primes[a.level];
+  Batch o(c, a.level - 1, a.count);
+  k_rescale(c, a.d, o.d, a.level, a.count, a.stride, c.ct_words(a.level - 1), nullptr, 0, nullptr, 0, nullptr,
+            pts.data());
+  const double masked = a.scale * (double)c.primes[a.level];  // the CMult's scale, then the rescale's
+  o.scale = masked / (double)c.primes[a.level];
   c.counters[3] += a.count;
   return o;
 }

@@ -332,6 +332,10 @@ struct NttEpilogue {
   int tensor = 0;
   const u64* ta[MAX_BATCH];
   const u64* tb[MAX_BATCH];
+  // When set (a plaintext product followed by a rescale): a is first multiplied by the plaintext ta[item]
+  // ([l][N], NTT form) word by word, and the rescale's first launch (ntt_inverse_first_pass_pt) multiplies its
+  // rows likewise before transforming them.
+  int pt_mul = 0;
   u64* t_out = nullptr;
   size_t t_out_stride = 0;
   u32 g[MAX_BATCH];           // per item: the Galois element (1: no permutation)
@@ -355,6 +359,9 @@ void ntt_inverse_first_pass(Context& c, u64* base, size_t batch_stride, int batc
 // products themselves (see NttEpilogue).
 void ntt_inverse_first_pass_tensor(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
                                    const NttEpilogue& t);
+// The same pass on src's rows times the plaintexts of t (t.pt_mul set), word by word.
+void ntt_inverse_first_pass_pt(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
+                               const NttEpilogue& t);
 void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,
                            const NttEpilogue& epi);
 
@@ -418,9 +425,11 @@ void k_tensor(Context& c, const u64* a, const u64* b, u64* d01, u64* d2, int lev
 // addx (or null): a ciphertext at level - 1 per item, addx_stride words apart, added to each result.
 // top_ready (or null): the two top rows of every item already through the inverse contiguous pass ([batch][2][N]
 // doubles, from a key switch's epilogue): the first launch is skipped.
+// pts (host, `batch` pointers to plaintexts at `level`, or null): rescale the ciphertexts times these plaintexts
+// instead (a CMult and its rescale in the rescale's three launches).
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
                const u64* kconst = nullptr, int in_poly_rows = 0, const u64* addx = nullptr, size_t addx_stride = 0,
-               const u64* top_ready = nullptr);
+               const u64* top_ready = nullptr, const u64* const* pts = nullptr);
 void k_reduce_signed(Context& c, const i64* coeffs, u64* out, RowsRef rows, int batch, size_t coeff_stride,
                      size_t out_stride);
 void k_encrypt(Context& c, const u64* a_ntt, const u64* e_ntt, const u64* m, const u64* s, u64* ct, int level);

@@ -685,12 +685,14 @@ void key_switch(Context& c, const KsJob& job) {
 
 // A rescale (Sec. 2.2) of `batch` ciphertexts at `level`: out = (in - [in_level]_centred) q_level^-1 over
 // q_0 .. q_{level-1} (with kconst: the same of in times the constant K, K in = [K_i in_i]_i; an input at a higher
-// level is taken at `level`; with addx, plus that addend), in three launches (two when a key switch's epilogue
-// has run the first) -- ModDown's pipeline with the single source prime q_level: the inverse
+// level is taken at `level`; with addx, plus that addend; with pts, of in times the item's plaintext), in three
+// launches (two when a key switch's epilogue has run the first) -- ModDown's pipeline with the single source prime q_level: the inverse
 // NTT's contiguous pass over the two top rows; one conversion launch (the inverse strided pass, the centred lift
 // to every q_i, the forward strided pass); the forward contiguous pass with the combine epilogue.
 void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t in_stride, size_t out_stride,
-               const u64* kconst, int in_poly_rows, const u64* addx, size_t addx_stride, const u64* top_ready) {
+               const u64* kconst, int in_poly_rows, const u64* addx, size_t addx_stride, const u64* top_ready,
+               const u64* const* pts) {
+  if (pts && (kconst || top_ready)) fail(HETAL_E_INVALID_ARG, "rescale: a plaintext product with another fusion");
   const size_t n = c.n;
   const int prow = in_poly_rows > 0 ? in_poly_rows : level + 1;
   // the top row's inverse transform ends with N^-1 (times the constant's residue mod q_level)
@@ -707,6 +709,11 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
     const int m = std::min(MAX_BATCH, batch - first);
     const u64* in_m = in + (size_t)first * in_stride;
     u64* out_m = out + (size_t)first * out_stride;
+    NttEpilogue ptm;  // the plaintexts of a fused CMult, if any
+    if (pts) {
+      ptm.pt_mul = 1;
+      for (int i = 0; i < MAX_BATCH; ++i) ptm.ta[i] = i < m ? pts[first + i] : nullptr;
+    }
     std::unique_ptr<Tmp> top;
     if (!top_ready) {
       top.reset(new Tmp(c.pool, (size_t)m * 2 * n));
@@ -715,7 +722,10 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
       src.batch_stride = in_stride;
       src.row_mul = prow;  // top row of poly p: p prow + level
       src.row_add = level;
-      ntt_inverse_first_pass(c, top->p, 2 * n, m, c.rows(ROWS_TOP, level), src);
+      if (pts)
+        ntt_inverse_first_pass_pt(c, top->p, 2 * n, m, c.rows(ROWS_TOP, level), src, ptm);
+      else
+        ntt_inverse_first_pass(c, top->p, 2 * n, m, c.rows(ROWS_TOP, level), src);
     }
     const size_t conv_words = 2 * (size_t)level * n;
     Tmp conv(c.pool, (size_t)m * conv_words);
@@ -760,6 +770,10 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
     if (addx) {
       epi.addx = addx + (size_t)first * addx_stride;
       epi.addx_stride = addx_stride;
+    }
+    if (pts) {
+      epi.pt_mul = 1;
+      for (int i = 0; i < MAX_BATCH; ++i) epi.ta[i] = ptm.ta[i];
     }
     for (int i = 0; i < MAX_BATCH; ++i) epi.g[i] = epi.ginv[i] = 1;
     ntt_forward_last_pass(c, conv, conv_words, m, out_rows, epi);

@@ -49,8 +49,7 @@ BView one(CtView x) { return BView{x.d, x.level, 1, x.scale, 0}; }
 Batch col_sum(Context& c, const KeySet& k, MaskCache& mc, Batch x, int s0, int s1) {
   const int lg = log2_exact(s1, "s1");
   for (int m = 0; m < lg; ++m) x = b_rotate_add(c, k, x.v(), 1 << m);
-  Batch masked = b_cmult_masks(c, mc, x.v(), {MaskSpec{MASK_FIRST_COL, 0, 0, s0, s1, 1.0}});
-  x = b_rescale(c, masked.v());
+  x = b_cmult_masks_rescale(c, mc, x.v(), {MaskSpec{MASK_FIRST_COL, 0, 0, s0, s1, 1.0}});
   for (int m = 0; m < lg; ++m) x = b_rotate_add(c, k, x.v(), -(1 << m));
   return x;
 }
@@ -68,8 +67,7 @@ Batch rot_left_finish(Context& c, const KeySet& k, MaskCache& mc, const Batch& a
                       int s1) {
   std::vector<MaskSpec> masks;
   for (int kk : ks) masks.push_back(MaskSpec{MASK_LEFT_COLS, kk, 0, s0, s1, 1.0});
-  Batch a2m = b_cmult_masks(c, mc, a1.v(), masks);
-  Batch a2 = b_rescale(c, a2m.v());
+  Batch a2 = b_cmult_masks_rescale(c, mc, a1.v(), masks);
   Batch a1d = b_mod_drop(c, a1.v(), a2.level);
   Batch rest = b_sub(c, a1d.v(), a2.v());
   BView a2v = a2.v();
@@ -83,8 +81,7 @@ Batch partial_rot_up(Context& c, const KeySet& k, MaskCache& mc, CtView b, const
   std::vector<MaskSpec> masks;
   for (int kk : ks) masks.push_back(MaskSpec{MASK_LEFT_COLS, kk, 0, s0, s1, 1.0});
   BView bc = BView{b.d, b.level, m, b.scale, 0};
-  Batch bpm = b_cmult_masks(c, mc, bc, masks);
-  Batch bp = b_rescale(c, bpm.v());
+  Batch bp = b_cmult_masks_rescale(c, mc, bc, masks);
   Batch bd = b_mod_drop(c, one(b), bp.level);
   Batch rest = b_sub(c, BView{bd.d, bd.level, m, bd.scale, 0}, bp.v());
   BView bpv = bp.v();
@@ -304,8 +301,7 @@ Batch abt_group(Context& c, const KeySet& k, MaskCache& mc, const std::vector<Ab
       for (int kk = 0; kk < half; ++kk) masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, kk, cc, s0, s1, reqs[r].t});
       runs_k.push_back(half);
     }
-  Batch xm = b_cmult_masks(c, mc, x.v(), masks);
-  x = b_rescale(c, xm.v());
+  x = b_cmult_masks_rescale(c, mc, x.v(), masks);
   Batch y = b_sum_segments(c, x.v(), runs_k);
   return b_conj_add(c, k, y.v());
 }
@@ -419,8 +415,7 @@ Batch atb_group(Context& c, const KeySet& k, MaskCache& mc, const std::vector<At
       for (int kk = 0; kk < half; ++kk) masks.push_back(MaskSpec{MASK_OFFDIAG_CPLX, -kk, cc, s0, s1, reqs[r].t});
       runs_k.push_back(half);
     }
-  Batch xm = b_cmult_masks(c, mc, x.v(), masks);
-  x = b_rescale(c, xm.v());
+  x = b_cmult_masks_rescale(c, mc, x.v(), masks);
   Batch y = b_sum_segments(c, x.v(), runs_k);
   return b_conj_add(c, k, y.v());
 }

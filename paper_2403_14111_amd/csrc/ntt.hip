@@ -73,6 +73,7 @@ struct PassArgs {
 // (The key switch's strided passes, which compute their input by a basis conversion, are in keyswitch.hip.)
 constexpr int NTT_TOP = 1;     // (with EPI) the top rows also run the inverse contiguous pass
 constexpr int NTT_TENSOR = 2;  // a Mult's tensor product computed where it is read (NttEpilogue::tensor)
+constexpr int NTT_PTMUL = 4;   // a plaintext product applied where the rows are read (NttEpilogue::pt_mul)
 
 template <int L, bool INV, bool CONTIG, bool EPI, int X = 0>
 __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, const int2* __restrict__ rows,
@@ -89,6 +90,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
   static_assert(!EPI || (CONTIG && !INV), "the epilogue belongs to the last forward pass");
   constexpr bool TOP = (X & NTT_TOP) != 0;
   constexpr bool TENSOR = (X & NTT_TENSOR) != 0;
+  constexpr bool PTMUL = (X & NTT_PTMUL) != 0;
   static_assert(!TENSOR || CONTIG, "the tensor product is read by the contiguous passes");
   // Words per sub-transform slice.  Within a slice one word of padding per 16 spreads the strided
   // reads; the slice length is chosen so that the 16-lane groups of a wave reading or writing
@@ -198,6 +200,7 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
         const u32 k = sp_off + sp_step * u;
         double av = epi.a_dbl ? mid_ld(ea[k]) : u2d(ea[k]);
         if (epi.a_mul) av = fmul(av, u2d(epi.a_k[i]), q, qi);  // in (-0.75 q, 1.75 q)
+        if (PTMUL) av = fmul(av, u2d(epi.ta[item][(size_t)i * n + k]), q, qi);
         double v = fmul(av - x[u], cst, q, qi);
         if (own_before) v = v + u2d(own[k]);
         x[u] = v;
@@ -301,6 +304,14 @@ __global__ void __launch_bounds__(NTT_THREADS) ntt_pass_kernel(PassArgs pa, cons
             x[u] = ffix(fred(fmul(u2d(a1[k]), u2d(b1[k]), q, qi), q, qi), q);
             d2[k] = d2u(x[u]);
           }
+        } else if (PTMUL) {
+          // times the item's plaintext, row of this prime
+          const u64* __restrict__ pt = epi.ta[item] + (size_t)rj.y * n;
+#pragma unroll
+          for (int u = 0; u < NTT_R; ++u) {
+            const u32 k = sp_off + sp_step * u;
+            x[u] = fred(fmul(u2d(ain[k]), u2d(pt[k]), q, qi), q, qi);  // [0, q]
+          }
         } else {
 #pragma unroll
           for (int u = 0; u < NTT_R; ++u) x[u] = u2d((ain + sp_step * u)[sp_off]);
@@ -387,15 +398,19 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   const bool contiguous = s0 + L == c.log_n;
   if (contiguous ? (L != 8) : (s0 != 0 || L + 8 != c.log_n)) fail(HETAL_E_PARAMS, "unsupported NTT pass shape");
   if (epi && !contiguous) fail(HETAL_E_PARAMS, "NTT epilogue outside the contiguous pass");
-  if (epi && INV && !epi->tensor) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
+  if (epi && INV && !epi->tensor && !epi->pt_mul) fail(HETAL_E_PARAMS, "NTT epilogue outside the last forward pass");
   if (epi && batch > MAX_BATCH) fail(HETAL_E_INVALID_ARG, "NTT epilogue batch");
   const NttEpilogue no_epi{};
   c.begin_launch();
-  if (epi && INV) {
+  if (epi && INV && epi->tensor) {
     hipLaunchKernelGGL((ntt_pass_kernel<8, true, true, false, NTT_TENSOR>), grid, block, 0, c.stream, pa, rows.d, tw,
                        c.d_fpm, c.d_pc, c.log_n, s0, *epi);
+  } else if (epi && INV) {
+    hipLaunchKernelGGL((ntt_pass_kernel<8, true, true, false, NTT_PTMUL>), grid, block, 0, c.stream, pa, rows.d, tw,
+                       c.d_fpm, c.d_pc, c.log_n, s0, *epi);
   } else if (epi) {
-    switch ((epi->top_out ? NTT_TOP : 0) | (epi->tensor ? NTT_TENSOR : 0)) {
+    if (epi->pt_mul && (epi->top_out || epi->tensor)) fail(HETAL_E_PARAMS, "unsupported epilogue combination");
+    switch ((epi->top_out ? NTT_TOP : 0) | (epi->tensor ? NTT_TENSOR : 0) | (epi->pt_mul ? NTT_PTMUL : 0)) {
 #define HETAL_EPI_CASE(XX)                                                                                       \
   case XX:                                                                                                     \
     hipLaunchKernelGGL((ntt_pass_kernel<8, false, true, true, XX>), grid, block, 0, c.stream, pa, rows.d, tw,     \
@@ -405,6 +420,7 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
       HETAL_EPI_CASE(1)
       HETAL_EPI_CASE(2)
       HETAL_EPI_CASE(3)
+      HETAL_EPI_CASE(4)
 #undef HETAL_EPI_CASE
     }
   } else {
@@ -427,13 +443,13 @@ void launch_pass(Context& c, int L, u64* base, size_t batch_stride, int batch, R
   }
   const double words = (double)c.n * rows.count * batch;
   if (epi && INV) {
-    // the pair's two rows read, the product and the pass output written
-    c.end_launch(KC_NTT_INV_CONTIG, 32.0 * words);
+    // the pair's two rows (or the row and the plaintext's) read; the pass output (and a tensor's product) written
+    c.end_launch(KC_NTT_INV_CONTIG, (epi->tensor ? 32.0 : 24.0) * words);
   } else if (epi) {
     // per word: the pass input and a read, out written; addx on every row, add0 / add1 on half of them (the
     // tensor product: the pair's rows, 3 of 4 on average)
     const double per_word = 24.0 + (epi->addx ? 8.0 : 0.0) + (epi->add0 ? 4.0 : 0.0) + (epi->add1 ? 4.0 : 0.0) +
-                            (epi->tensor ? 24.0 : 0.0);
+                            (epi->tensor ? 24.0 : 0.0) + (epi->pt_mul ? 8.0 : 0.0);
     c.end_launch(KC_NTT_FWD_EPILOGUE, per_word * words);
   } else {
     const int cls = INV ? (contiguous ? KC_NTT_INV_CONTIG : KC_NTT_INV_STRIDED)
@@ -463,6 +479,13 @@ void ntt_inverse_first_pass_tensor(Context& c, u64* base, size_t batch_stride, i
   if (rows.count == 0 || batch == 0) return;
   if (!t.tensor || !t.t_out) fail(HETAL_E_INVALID_ARG, "tensor pass without its pairs");
   launch_pass<true>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, NttSrc{}, &t);
+}
+
+void ntt_inverse_first_pass_pt(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows, NttSrc src,
+                               const NttEpilogue& t) {
+  if (rows.count == 0 || batch == 0) return;
+  if (!t.pt_mul) fail(HETAL_E_INVALID_ARG, "plaintext pass without its plaintexts");
+  launch_pass<true>(c, 8, base, batch_stride, batch, rows, c.log_n - 8, src, &t);
 }
 
 void ntt_forward_last_pass(Context& c, u64* base, size_t batch_stride, int batch, RowsRef rows,

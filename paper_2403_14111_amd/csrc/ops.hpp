@@ -175,8 +175,10 @@ Batch b_conj(Context& c, const KeySet& k, BView a);
 Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
 // b_hmult then b_rescale, with the rescale's first launch run by the key switch's epilogue: the same words.
 Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
-// CMult of item i by mask masks[i] (or masks[0] for all), each encoded at the batch level with scale q_level.
-Batch b_cmult_masks(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks);
+// CMult of item i by mask masks[i] (or masks[0] for all), each encoded at the batch level with scale q_level,
+// then the rescale: in the rescale's three launches, the products formed where the rows are read (the same words
+// as a CMult kernel followed by b_rescale).
+Batch b_cmult_masks_rescale(Context& c, MaskCache& mc, BView a, const std::vector<MaskSpec>& masks);
 // out[g] = sum over t < per of a[g * per + t], per = a.count / groups.
 Batch b_sum_groups(Context& c, BView a, int groups);
 // out[g] = sum of the g-th run of sizes[g] consecutive items (the runs cover the batch in order).

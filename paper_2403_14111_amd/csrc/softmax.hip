@@ -310,8 +310,7 @@ struct Steps {
 
   Val mask(Val x, MaskKind kind, int kk) {
     x = need(std::move(x), 1);
-    Batch m = b_cmult_masks(c, *mc, x.v, {MaskSpec{kind, kk, 0, s0, s1, 1.0}});
-    return Val(b_rescale(c, m.v()));
+    return Val(b_cmult_masks_rescale(c, *mc, x.v, {MaskSpec{kind, kk, 0, s0, s1, 1.0}}));
   }
 
   Val rot(const Val& x, int r) { return Val(b_rotate(c, k, x.v, {r})); }
