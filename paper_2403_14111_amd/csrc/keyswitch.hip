@@ -47,6 +47,15 @@ constexpr int KIND_MODDOWN = 1;
 constexpr int KIND_RESCALE = 2;  // one source, the top prime q_level of each polynomial; conversion factor 1
 constexpr int MAX_CONV = 4;  // terms of a fused conversion: alpha and K are at most this
 
+// A read of a table that no kernel writes while this one runs, through the constant address space: a uniform
+// address then takes the scalar memory path, whose waits (lgkmcnt) are independent of the vector memory
+// counter.  A vector load inside the conversion's loop over targets would make each target wait for the
+// previous target's stores, since that counter completes in order.
+template <class T>
+__device__ __forceinline__ T cload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
 // ------------------------------------------------------------------ basis conversion passes (launches 2 and 4)
 struct ConvArgs {
   const u64* src;        // per item: the rows the inverse strided pass reads (doubles)
@@ -118,7 +127,13 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
   }
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
-    if (i >= nsrc) continue;  // a short last digit: zero terms (its constants beyond the length are zero too)
+    if (i >= nsrc) {  // a short last digit: zero terms (its constants beyond the length are zero too)
+      // (set here, not only by the load's select, so that no source register enters the target loop with a
+      // load in flight: the loop would then wait for all vector memory on every target)
+#pragma unroll
+      for (int u = 0; u < NTT_R; ++u) y[i][u] = 0.0;
+      continue;
+    }
     const int row = a.src_row0[sg] + i;
     const int prime = KIND == KIND_MODUP ? row : KIND == KIND_MODDOWN ? a.num_q + i : a.src_prime;
     const NttScale sc = KIND == KIND_RESCALE ? a.scale_v : a.scale[KIND == KIND_MODUP ? row : sg * CNT + i];
@@ -175,7 +190,8 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
   // ---- each target: the conversion sum, then the forward strided pass
   u64* __restrict__ dstb = a.dst + (size_t)item * a.dst_stride;
   for (int tt = t_begin; tt < t_end; ++tt) {
-    const int2 rt = a.targets[a.first[sg] + tt];
+    const u64 rt2 = cload((const u64*)(a.targets + a.first[sg] + tt));  // (destination row, prime)
+    const int2 rt = make_int2((int)lo32(rt2), (int)hi32(rt2));
     const FpMod fm = fpm[rt.y];
     const double q = fm.q, qi = fm.qinv;
     const double* __restrict__ w = tw_fwd + (size_t)rt.y * n;
@@ -183,7 +199,8 @@ __global__ void __launch_bounds__(NTT_THREADS) modconv_kernel(ConvArgs a, const 
 #pragma unroll
     for (int i = 0; i < CNT; ++i)
       cc[i] = KIND == KIND_RESCALE ? 1.0
-                                   : u2d(KIND == KIND_MODUP ? a.modup[sg].dhat[i][rt.y] : a.moddown->phat[i][rt.y]);
+                                   : u2d(KIND == KIND_MODUP ? cload(&a.modup[sg].dhat[i][rt.y])
+                                                            : cload(&a.moddown->phat[i][rt.y]));
     double x[NTT_R];
     auto stages = [&](auto lazy) {
       constexpr bool LZ = decltype(lazy)::value;
