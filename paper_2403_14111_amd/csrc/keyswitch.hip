@@ -764,6 +764,9 @@ void k_rescale(Context& c, const u64* in, u64* out, int level, int batch, size_t
       a.src_prime = level;
       a.num_q = c.num_q;
       a.tpt = c.tune.tpt_moddown > 0 ? std::min(c.tune.tpt_moddown, level) : targets_per_task(c, level, 2, m);
+      // one source row: a task recomputes a single inverse pass per target, so where the heuristic settles for
+      // the smallest tasks (small launches) one target per task spreads the launch over more workgroups
+      if (c.tune.tpt_moddown <= 0 && a.tpt <= 2) a.tpt = 1;
       a.tasks_per_group = (level + a.tpt - 1) / a.tpt;
       a.colgroups = colgroups;
       a.groups = 2 * a.tasks_per_group * colgroups;
