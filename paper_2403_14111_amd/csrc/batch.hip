@@ -16,6 +16,8 @@ constexpr int TPB = 256;
 struct PtrArgs {
   const u64* a[MAX_BATCH];
   const u64* b[MAX_BATCH];
+  int ra[MAX_BATCH];  // rows per polynomial of each operand (its level + 1); an operand above the product's level
+  int rb[MAX_BATCH];  // is read as its mod-drop would be: the first level + 1 rows of each polynomial
 };
 
 // d01[item] = (a0 b0, a0 b1 + a1 b0), d2[item] = a1 b1.
@@ -30,7 +32,7 @@ __global__ void __launch_bounds__(TPB) tensor_batch_kernel(PtrArgs p, u64* __res
   const u64* __restrict__ a = p.a[item];
   const u64* __restrict__ b = p.b[item];
   const size_t i0 = (size_t)i * n + k, i1 = (size_t)(l + i) * n + k;
-  const u64 a0 = a[i0], a1 = a[i1], b0 = b[i0], b1 = b[i1];
+  const u64 a0 = a[i0], a1 = a[(size_t)(p.ra[item] + i) * n + k], b0 = b[i0], b1 = b[(size_t)(p.rb[item] + i) * n + k];
   U128 cross = mul_wide(a0, b1);
   acc_wide(cross, mul_wide(a1, b0));
   u64* __restrict__ o = d01 + (size_t)item * 2 * l * n;
@@ -123,6 +125,17 @@ static Batch b_addsub(Context& c, BView a, BView b, bool subtract) {
 
 Batch b_add(Context& c, BView a, BView b) { return b_addsub(c, a, b, false); }
 Batch b_sub(Context& c, BView a, BView b) { return b_addsub(c, a, b, true); }
+
+Batch b_addsub_at(Context& c, BView a, BView b, int level, bool subtract) {
+  if (a.count != b.count) fail(HETAL_E_LEVEL, "batch operands differ in count");
+  if (a.level < level || b.level < level || level < 0) fail(HETAL_E_LEVEL, "operand below the sum's level");
+  if (std::abs(a.scale - b.scale) > 1e-9 * std::max(std::abs(a.scale), std::abs(b.scale)))
+    fail(HETAL_E_SCALE, "batch operands with different scales");
+  Batch o(c, level, a.count);
+  k_addsub_rows(c, a.d, a.stride, a.level + 1, b.d, b.stride, b.level + 1, o.d, level, a.count, subtract);
+  o.scale = a.scale;
+  return o;
+}
 
 Batch b_mul_i(Context& c, BView a) {
   Batch pa;
@@ -273,8 +286,8 @@ Batch b_conj(Context& c, const KeySet& k, BView a) {
 constexpr int FUSED_TENSOR_ITEMS = 8;
 
 static void hmult_group(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b,
-                        int first, int m, u64* out, size_t out_stride, u64* top_out) {
-  const int level = a[first].level, l = level + 1;
+                        int first, int m, int level, u64* out, size_t out_stride, u64* top_out) {
+  const int l = level + 1;
   const size_t poly = c.poly_words(level), w = c.ct_words(level);
   KsJob job;
   job.level = level;
@@ -283,7 +296,9 @@ static void hmult_group(Context& c, const KeySet& k, const std::vector<CtView>& 
   job.out = out;
   job.out_stride = out_stride;
   job.top_out = top_out;
-  if (m >= FUSED_TENSOR_ITEMS) {
+  bool at_level = true;  // the fused form reads its operands at the product's level only
+  for (int i = first; i < first + m; ++i) at_level = at_level && a[i].level == level && b[i].level == level;
+  if (m >= FUSED_TENSOR_ITEMS && at_level) {
     job.tensor = true;
     for (int i = 0; i < m; ++i) {
       job.ta[i] = a[first + i].d;
@@ -297,6 +312,8 @@ static void hmult_group(Context& c, const KeySet& k, const std::vector<CtView>& 
   for (int i = 0; i < MAX_BATCH; ++i) {
     p.a[i] = i < m ? a[first + i].d : nullptr;
     p.b[i] = i < m ? b[first + i].d : nullptr;
+    p.ra[i] = i < m ? a[first + i].level + 1 : 0;
+    p.rb[i] = i < m ? b[first + i].level + 1 : 0;
   }
   c.begin_launch();
   hipLaunchKernelGGL(tensor_batch_kernel, grid3(c, l, m), dim3(TPB), 0, c.stream, p, d01.p, d2.p, c.d_mod, c.log_n,
@@ -311,38 +328,45 @@ static void hmult_group(Context& c, const KeySet& k, const std::vector<CtView>& 
   key_switch(c, job);
 }
 
-Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b) {
+// The product's level: `level`, with every operand at or above it (read as if mod-dropped), or with level < 0 the
+// common level of all operands.
+static int product_level(const std::vector<CtView>& a, const std::vector<CtView>& b, int level) {
   if (a.size() != b.size() || a.empty()) fail(HETAL_E_INVALID_ARG, "hmult batch operand counts differ");
+  const int lv = level < 0 ? a[0].level : level;
+  for (size_t i = 0; i < a.size(); ++i) {
+    if (level < 0 && (a[i].level != lv || b[i].level != lv)) fail(HETAL_E_LEVEL, "hmult operands at different levels");
+    if (a[i].level < lv || b[i].level < lv) fail(HETAL_E_LEVEL, "hmult operand below the product's level");
+  }
+  return lv;
+}
+
+Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b, int at) {
+  const int level = product_level(a, b, at), count = (int)a.size();
   if (!k.relin) fail(HETAL_E_NO_KEY, "relinearisation key missing");
-  const int level = a[0].level, count = (int)a.size();
-  for (int i = 0; i < count; ++i)
-    if (a[i].level != level || b[i].level != level) fail(HETAL_E_LEVEL, "hmult operands at different levels");
   Batch o(c, level, count);
   const size_t w = c.ct_words(level);
   const int group = std::max(1, std::min(MAX_BATCH, c.tune.ks_group));
   for (int first = 0; first < count; first += group) {
     const int m = std::min(group, count - first);
-    hmult_group(c, k, a, b, first, m, o.d + (size_t)first * w, w, nullptr);
+    hmult_group(c, k, a, b, first, m, level, o.d + (size_t)first * w, w, nullptr);
   }
   o.scale = a[0].scale * b[0].scale;
   c.counters[2] += count;
   return o;
 }
 
-Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b) {
-  if (a.size() != b.size() || a.empty()) fail(HETAL_E_INVALID_ARG, "hmult batch operand counts differ");
+Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b,
+                      int at) {
+  const int level = product_level(a, b, at), count = (int)a.size();
   if (!k.relin) fail(HETAL_E_NO_KEY, "relinearisation key missing");
-  const int level = a[0].level, count = (int)a.size();
   if (level < 1) fail(HETAL_E_LEVEL, "no level left to rescale");
-  for (int i = 0; i < count; ++i)
-    if (a[i].level != level || b[i].level != level) fail(HETAL_E_LEVEL, "hmult operands at different levels");
   Batch o(c, level - 1, count);
   const size_t w = c.ct_words(level), wo = c.ct_words(level - 1);
   const int group = std::max(1, std::min(MAX_BATCH, c.tune.ks_group));
   for (int first = 0; first < count; first += group) {
     const int m = std::min(group, count - first);
     Tmp prod(c.pool, (size_t)m * w), top(c.pool, (size_t)m * 2 * c.n);
-    hmult_group(c, k, a, b, first, m, prod, w, top);
+    hmult_group(c, k, a, b, first, m, level, prod, w, top);
     k_rescale(c, prod, o.d + (size_t)first * wo, level, m, w, wo, nullptr, 0, nullptr, 0, top);
   }
   o.scale = (a[0].scale * b[0].scale) / (double)c.primes[level];

@@ -414,6 +414,10 @@ u64* scratch_region(int device, size_t* words);
 // Elementwise kernels on [rows][N] arrays whose row i is modulo prime (i mod period).
 void k_add(Context& c, const u64* a, const u64* b, u64* out, int rows, int period);
 void k_sub(Context& c, const u64* a, const u64* b, u64* out, int rows, int period);
+// out[item] = a[item] ± b[item] at `level` (packed), reading each operand's first level + 1 rows of each of its
+// two polynomials (a_rows, b_rows: the operand's rows per polynomial; a_stride, b_stride: words between items).
+void k_addsub_rows(Context& c, const u64* a, size_t a_stride, int a_rows, const u64* b, size_t b_stride, int b_rows,
+                   u64* out, int level, int count, bool subtract);
 void k_mul_rows(Context& c, const u64* a, const u64* b, u64* out, int rows, int period, int b_period);
 void k_mul_i(Context& c, const u64* a, u64* out, int rows, int period);
 void k_galois(Context& c, const u64* a, u64* out, int rows, int period, u32 g);

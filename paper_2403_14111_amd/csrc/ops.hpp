@@ -156,6 +156,8 @@ struct MaskSpec {
 Batch b_pack(Context& c, const std::vector<CtView>& items);
 Batch b_add(Context& c, BView a, BView b);
 Batch b_sub(Context& c, BView a, BView b);
+// a ± b at `level`, the operands at or above it read as their mod-drops would be (no copy).
+Batch b_addsub_at(Context& c, BView a, BView b, int level, bool subtract);
 Batch b_mul_i(Context& c, BView a);
 Batch b_mod_drop(Context& c, BView a, int level);
 Batch b_rescale(Context& c, BView a);
@@ -171,10 +173,12 @@ Batch b_conj_add(Context& c, const KeySet& k, BView a);
 // One ciphertext rotated by each step, sharing one ModUp (hoisting).
 Batch b_rotate_hoisted(Context& c, const KeySet& k, CtView a, const std::vector<int>& steps);
 Batch b_conj(Context& c, const KeySet& k, BView a);
-// Mult (tensor + relinearisation) of the pairs (a[i], b[i]), all at one level.
-Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
+// Mult (tensor + relinearisation) of the pairs (a[i], b[i]), all at one level; or, with at >= 0, at level `at`
+// from operands at or above it, read as their mod-drops would be (no copy).
+Batch b_hmult(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b, int at = -1);
 // b_hmult then b_rescale, with the rescale's first launch run by the key switch's epilogue: the same words.
-Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b);
+Batch b_hmult_rescale(Context& c, const KeySet& k, const std::vector<CtView>& a, const std::vector<CtView>& b,
+                      int at = -1);
 // CMult of item i by mask masks[i] (or masks[0] for all), each encoded at the batch level with scale q_level,
 // then the rescale: in the rescale's three launches, the products formed where the rows are read (the same words
 // as a CMult kernel followed by b_rescale).

@@ -23,6 +23,22 @@ __global__ void __launch_bounds__(TPB) add_kernel(const u64* __restrict__ a, con
   o[idx] = sub ? sub_mod(a[idx], b[idx], q) : add_mod(a[idx], b[idx], q);
 }
 
+// Row r of item z of the output (polynomial r / l, limb r % l) from the operands' rows of the same polynomial and
+// limb, each operand with its own rows per polynomial and item stride.
+__global__ void __launch_bounds__(TPB) addsub_rows_kernel(const u64* __restrict__ a, size_t a_stride, int a_rows,
+                                                          const u64* __restrict__ b, size_t b_stride, int b_rows,
+                                                          u64* __restrict__ o, const ModInfo* __restrict__ mods,
+                                                          int log_n, int l, int sub) {
+  const int n = 1 << log_n;
+  const int k = blockIdx.x * TPB + threadIdx.x;
+  const int r = blockIdx.y, z = blockIdx.z;
+  const int p = r / l, i = r - p * l;
+  const u64 q = mods[i].q;
+  const u64 x = a[(size_t)z * a_stride + (size_t)(p * a_rows + i) * n + k];
+  const u64 y = b[(size_t)z * b_stride + (size_t)(p * b_rows + i) * n + k];
+  o[((size_t)z * 2 * l + r) * n + k] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
+}
+
 __global__ void __launch_bounds__(TPB) mul_rows_kernel(const u64* __restrict__ a, const u64* __restrict__ b,
                                                        u64* __restrict__ o, const ModInfo* __restrict__ mods,
                                                        int log_n, int period, int b_period) {
@@ -157,6 +173,16 @@ void k_sub(Context& c, const u64* a, const u64* b, u64* out, int rows, int perio
   c.begin_launch();
   hipLaunchKernelGGL(add_kernel, grid_for(c, rows, 1), dim3(TPB), 0, c.stream, a, b, out, c.d_mod, c.log_n, period, 1);
   c.end_launch(KC_ELEMWISE, 24.0 * c.n * rows);
+}
+
+void k_addsub_rows(Context& c, const u64* a, size_t a_stride, int a_rows, const u64* b, size_t b_stride, int b_rows,
+                   u64* out, int level, int count, bool subtract) {
+  const int l = level + 1;
+  if (a_rows < l || b_rows < l || count < 1) fail(HETAL_E_INVALID_ARG, "addsub operand shape");
+  c.begin_launch();
+  hipLaunchKernelGGL(addsub_rows_kernel, grid_for(c, 2 * l, count), dim3(TPB), 0, c.stream, a, a_stride, a_rows, b,
+                     b_stride, b_rows, out, c.d_mod, c.log_n, l, subtract ? 1 : 0);
+  c.end_launch(KC_ELEMWISE, 24.0 * c.n * 2 * l * count);
 }
 
 void k_mul_rows(Context& c, const u64* a, const u64* b, u64* out, int rows, int period, int b_period) {

@@ -284,8 +284,6 @@ struct Steps {
     return Val(std::move(out));
   }
 
-  Val drop(Val x, int lv) { return x.level() == lv ? std::move(x) : Val(b_mod_drop(c, x.v, lv)); }
-
   Val rescale(const Val& x) { return Val(b_rescale(c, x.v)); }
 
   // x * v with v at scale q_level, rescaled (the scale is kept; one level).
@@ -318,17 +316,14 @@ struct Steps {
   Val mult(Val a, Val b, bool same) {
     a = need(std::move(a), 1);
     if (!same) b = need(std::move(b), 1);
-    const BView bv0 = same ? a.v : b.v;
-    const int lv = std::min(a.level(), bv0.level);
-    a = drop(std::move(a), lv);
-    if (!same) b = drop(std::move(b), lv);
     const BView av = a.v, bv = same ? a.v : b.v;
+    const int lv = std::min(av.level, bv.level);  // an operand above it is read as its mod-drop (no copy)
     std::vector<CtView> va, vb;
     for (int i = 0; i < av.count; ++i) {
       va.push_back(av.item(i));
       vb.push_back(bv.item(i));
     }
-    return Val(b_hmult_rescale(c, k, va, vb));
+    return Val(b_hmult_rescale(c, k, va, vb, lv));
   }
 
   // Independent products as one lockstep Mult + rescale: every item goes through the operations it would get
@@ -342,19 +337,14 @@ struct Steps {
       if (lv >= 0 && l != lv) return false;
       lv = l;
     }
-    std::vector<Val> held;
-    held.reserve(2 * ops.size());
     std::vector<CtView> va, vb;
     for (const auto& op : ops) {
-      held.push_back(drop(Val(op.first), lv));
-      held.push_back(drop(Val(op.second), lv));
-      const BView a = held[held.size() - 2].v, b = held.back().v;
-      for (int i = 0; i < a.count; ++i) {
-        va.push_back(a.item(i));
-        vb.push_back(b.item(i));
+      for (int i = 0; i < op.first.count; ++i) {
+        va.push_back(op.first.item(i));
+        vb.push_back(op.second.item(i));
       }
     }
-    auto r = std::make_shared<Batch>(b_hmult_rescale(c, k, va, vb));
+    auto r = std::make_shared<Batch>(b_hmult_rescale(c, k, va, vb, lv));
     const size_t w = c.ct_words(lv - 1);
     size_t off = 0;
     out.clear();
@@ -376,10 +366,7 @@ struct Steps {
       const double sigma = sa * q / sb;
       b = Val(b_mul_const_rescale(c, b.v, b.level(), 1.0, sigma));
     }
-    const int lv = std::min(a.level(), b.level());
-    a = drop(std::move(a), lv);
-    b = drop(std::move(b), lv);
-    return Val(subtract ? b_sub(c, a.v, b.v) : b_add(c, a.v, b.v));
+    return Val(b_addsub_at(c, a.v, b.v, std::min(a.level(), b.level()), subtract));
   }
 
   Val poly(Val x, const std::vector<double>& coeffs) {
