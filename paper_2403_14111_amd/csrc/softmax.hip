@@ -263,22 +263,22 @@ struct Steps {
     if (!rf.fn || d > top) fail(HETAL_E_LEVEL, "depth budget exhausted (no refresh, and the library does not bootstrap)");
     Batch out(c, top, x.v.count);
     const size_t wtop = c.ct_words(top), w = c.ct_words(x.level());
-    Tmp buf(c.pool, wtop);
     for (int i = 0; i < x.v.count; ++i) {
-      HCHECK(hipMemcpyAsync(buf.p, x.v.item(i).d, w * 8, hipMemcpyDeviceToDevice, c.stream));
+      // the item goes into its slot of the output, where the key holder re-encrypts it in place
+      u64* slot = out.d + (size_t)i * wtop;
+      HCHECK(hipMemcpyAsync(slot, x.v.item(i).d, w * 8, hipMemcpyDeviceToDevice, c.stream));
       HCHECK(hipStreamSynchronize(c.stream));
       hetal_ct h;
-      h.data = buf.p;
+      h.data = slot;
       h.capacity = wtop;
       h.level = x.level();
       h.scale = x.scale();
       const int rc = rf.fn(rf.user, &h);
       if (rc != HETAL_OK) fail(rc, "refresh callback failed");
-      if (h.data != buf.p || h.level != top || !(h.scale > 0.0) || !std::isfinite(h.scale))
+      if (h.data != slot || h.level != top || !(h.scale > 0.0) || !std::isfinite(h.scale))
         fail(HETAL_E_INVALID_ARG, "refresh must re-encrypt in place at the top level with a positive scale");
       if (i > 0 && h.scale != out.scale) fail(HETAL_E_SCALE, "refresh gave the items of one batch different scales");
       out.scale = h.scale;
-      HCHECK(hipMemcpyAsync(out.d + (size_t)i * wtop, buf.p, wtop * 8, hipMemcpyDeviceToDevice, c.stream));
       rf.count += 1;
     }
     return Val(std::move(out));
